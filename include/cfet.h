@@ -1,0 +1,210 @@
+/*
+ * cfet.h -- C ABI of the MI355X commutator-free exponential time-propagator
+ * library (libcfet.so).
+ *
+ * The library propagates  i d/dt psi = H(t) psi  with
+ *     H(t) = H0 + sum_k f_k(t) H_k                (paper Sec. 1, eq. DGL; A(t) = -i H(t))
+ * by commutator-free exponential time-propagators (CFETs): one time step of
+ * size dt is
+ *     psi <- exp(Omega_1) exp(Omega_2) ... exp(Omega_s) psi        (Sec. 4, eq. Ucf)
+ *     Omega_i = -i dt (a_i H0 + sum_k b_{i,k} H_k),
+ *     a_i = sum_m g_{i,m},  b_{i,k} = sum_m g_{i,m} f_k(t + x_m dt)  (Sec. 7, eq. OmGLeg)
+ * with the Gauss-Legendre points x_m of Table tab:GaussLeg and the weights
+ * g_{i,m} built from the coefficient tables of Secs. 4-5.  exp(Omega_s) acts
+ * on psi first.  Each exponential is computed by the Lanczos (Krylov)
+ * technique of Sec. 8.1 with m basis vectors; all of it runs in HIP kernels
+ * on one GPU.
+ *
+ * Conventions for every entry point
+ *   - Return value: CFET_OK (0) or a positive CFET_E* code.  Nothing aborts
+ *     and no C++ exception crosses this boundary.  cfet_last_error() gives a
+ *     message for the last failure on a context (or, for ctx == NULL, the last
+ *     failure of a context-less call on this thread).
+ *   - Complex numbers are interleaved (re, im) float64 pairs, i.e. the layout
+ *     of C99 double complex / torch.complex128.
+ *   - Device pointers are HIP device allocations on the context's device.
+ *     "Host or device" pointers are classified with hipPointerGetAttributes.
+ *   - Work enqueued on a caller stream is stream-ordered: the call returns
+ *     after enqueueing; faults found on the device (non-finite values,
+ *     eigen-solver non-convergence) are latched and reported by the next call
+ *     on the context or by cfet_stats().
+ *   - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef CFET_H
+#define CFET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFET_API __attribute__((visibility("default")))
+
+#define CFET_VERSION 1
+#define CFET_MAX_KRYLOV 64   /* largest Krylov dimension m */
+#define CFET_MAX_TERMS 7     /* largest number of driven terms H_k */
+
+enum {
+  CFET_OK = 0,
+  CFET_EINVAL = 1,        /* bad argument, shape or CSR structure */
+  CFET_ENOMEM = 2,        /* device or host allocation failed */
+  CFET_EDEVICE = 3,       /* HIP runtime error */
+  CFET_ENONFINITE = 4,    /* NaN/Inf in input data or produced on the device */
+  CFET_EUNSUPPORTED = 5,  /* valid request this build does not implement */
+  CFET_ENOCONV = 6        /* small eigen-solver did not converge */
+};
+
+/* Coefficient tables (Tables 4thCFET, 6thCFET, 8thCoeff, 4thCFETOpt,
+ * 6thCFETOpt; CF2:1 is the exponential midpoint rule, Sec. 4 eq. UCF2). */
+typedef enum {
+  CFET_CF2_1 = 0,
+  CFET_CF4_2 = 1,
+  CFET_CF4_3 = 2,
+  CFET_CF4_3OPT = 3,
+  CFET_CF6_4 = 4,
+  CFET_CF6_5 = 5,
+  CFET_CF6_5B = 6,
+  CFET_CF6_6 = 7,
+  CFET_CF6_5IMP = 8,
+  CFET_CF6_5OPT = 9,
+  CFET_CF6_6OPT = 10,
+  CFET_CF8_11 = 11,
+  CFET_NUM_SCHEMES = 12
+} cfet_scheme;
+
+/* Sparse Hermitian matrix in CSR.  row_ptr: int64[n+1] with row_ptr[0] = 0,
+ * non-decreasing, row_ptr[n] = nnz.  col: int32[nnz] in [0, n).  val:
+ * 2*nnz float64 (interleaved complex).  Columns need not be sorted; a
+ * column may not repeat within a row.  Host or device pointers; read only
+ * during cfet_create. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const double *val;
+} cfet_csr;
+
+/* Drive functions f_k(t), evaluated on the host in float64:
+ *   COS       A cos(omega t + phi)
+ *   SIN2_COS  A sin^2(pi t / Tp) cos(omega t + phi) for 0 <= t <= Tp, else 0
+ *   PWC       u[j] for t_edges[j] <= t < t_edges[j+1], else 0 (npieces pieces,
+ *             t_edges strictly increasing; host pointers, copied at create)
+ *   SECH_COS  A cos(omega t + phi) / cosh((t - tc)/tau)  (pulse of Sec. 11.1,
+ *             eq. BPulse)                                                    */
+typedef enum {
+  CFET_DRIVE_COS = 0,
+  CFET_DRIVE_SIN2_COS = 1,
+  CFET_DRIVE_PWC = 2,
+  CFET_DRIVE_SECH_COS = 3
+} cfet_drive_kind;
+
+typedef struct {
+  int32_t kind;
+  double A, omega, phi, Tp, tc, tau;
+  int32_t npieces;
+  const double *t_edges; /* npieces + 1 entries (PWC only) */
+  const double *u;       /* npieces entries (PWC only) */
+} cfet_drive;
+
+/* Flags for cfet_create. */
+#define CFET_VALIDATE_HERMITIAN 0x1u /* check H = H^dagger for every matrix */
+
+typedef struct cfet_ctx cfet_ctx;
+
+/* Statistics of a context, accumulated over all cfet_propagate calls. */
+typedef struct {
+  int64_t n;                 /* Hilbert-space dimension */
+  int64_t nnz_stored;        /* stored non-zeros of the merged operator */
+  int64_t exponentials;      /* exponentials applied */
+  int64_t matvecs;           /* H applications (sum of effective m) */
+  int32_t min_m_eff;         /* smallest effective Krylov dimension seen */
+  int32_t breakdowns;        /* exponentials that stopped early (beta ~ 0) */
+  int32_t path;              /* last propagation path: 0 none, 1 multi-kernel,
+                                2 single-workgroup, 3 cooperative */
+  int32_t status;            /* latched device status (CFET_OK or code) */
+  double last_norm;          /* ||psi|| after the last exponential */
+  int64_t timed_launches;    /* SpMV launches timed with events (cfet_profile) */
+  double timed_ms;           /* their summed event-measured duration */
+} cfet_stats_t;
+
+/* Build a context for H(t) = H0 + sum_k f_k(t) Hk[k], k < nterms
+ * (1 <= nterms <= CFET_MAX_TERMS).  All matrices must be n x n.  The matrices
+ * are validated (shape, CSR structure, finiteness, optionally Hermiticity)
+ * and copied into library-owned device memory on the current HIP device,
+ * merged into one CSR whose entries carry their term index.  *out receives
+ * the context (NULL on failure).  The caller owns the context and releases it
+ * with cfet_destroy. */
+CFET_API int cfet_create(const cfet_csr *H0, int32_t nterms, const cfet_csr *Hk,
+                         const cfet_drive *fk, uint32_t flags, cfet_ctx **out);
+
+/* Propagate psi in place over nsteps CFET steps of size dt starting at t0
+ * (step n starts at t0 + n dt, computed fresh for each n).  psi_dev:
+ * complex128[n] device buffer owned by the caller.  scheme: cfet_scheme.
+ * krylov_m: Lanczos basis size, 1..CFET_MAX_KRYLOV (clipped to n).  dt may be
+ * negative; nsteps == 0 is a no-op.  hip_stream: hipStream_t (NULL = default
+ * stream).  Lanczos stops early at basis size j < m when
+ * beta_j <= 1e-12 max_{k<=j}(|alpha_k| + beta_k); psi is never renormalised.
+ * Enqueues only; returns CFET_EINVAL/ENOMEM/EDEVICE for host-visible
+ * failures. */
+CFET_API int cfet_propagate(cfet_ctx *c, void *psi_dev, double t0, double dt, int64_t nsteps,
+                            int32_t scheme, int32_t krylov_m, void *hip_stream);
+
+/* Gradient of F = |<target|psi(T)>|^2 with respect to piecewise-constant drive
+ * amplitudes.  Not implemented in this build: returns CFET_EUNSUPPORTED. */
+CFET_API int cfet_gradient(cfet_ctx *c, const void *psi0_dev, const void *target_dev, double t0,
+                           double dt, int64_t nsteps, int32_t scheme, int32_t krylov_m,
+                           const double *u, int32_t K, double *F_out, double *dFdu_out,
+                           void *hip_stream);
+
+/* y = (a H0 + sum_k b[k] Hk[k]) x on the device (the weighted apply that the
+ * Lanczos recursion uses; Sec. 8: the sparsity pattern of the sum is the
+ * union of the patterns).  x_dev, y_dev: complex128[n] device buffers, must
+ * not overlap.  b: host array of nterms doubles.  Stream-ordered. */
+CFET_API int cfet_apply(cfet_ctx *c, const void *x_dev, void *y_dev, double a, const double *b,
+                        void *hip_stream);
+
+/* Synchronise the context's last stream and report statistics and the
+ * latched device status (which this call clears). */
+CFET_API int cfet_stats(cfet_ctx *c, cfet_stats_t *s);
+
+/* Release all device and host memory of the context (synchronises). */
+CFET_API int cfet_destroy(cfet_ctx *c);
+
+CFET_API const char *cfet_last_error(const cfet_ctx *c);
+
+/* Kernel timing for measurement: with enable != 0, cfet_propagate records a
+ * HIP event pair on the caller's stream around every launch of the Lanczos
+ * SpMV kernel (up to max_launches pairs per call; later launches run
+ * untimed), and cfet_stats reports the count and summed duration.  The
+ * events add a little launch overhead, so throughput is measured with timing
+ * off.  enable == 0 releases the events. */
+CFET_API int cfet_profile(cfet_ctx *c, int32_t enable, int32_t max_launches);
+
+/* Host-side view of the library's own scheme data: s (exponentials), M
+ * (Gauss-Legendre points), the nodes x[M] and the weights g[s*M] (row-major,
+ * g[i*M + m]).  Any output pointer may be NULL.  Sec. 7, eq. OmGLeg. */
+CFET_API int cfet_scheme_info(int32_t scheme, int32_t *s, int32_t *M, double *x, double *g);
+
+/* Per-step weights exactly as cfet_propagate uses them: a[i] (i < s) and
+ * b[(n*s + i)*nterms + k] for steps n < nsteps.  Host arrays. */
+CFET_API int cfet_step_weights(const cfet_ctx *c, double t0, double dt, int64_t nsteps,
+                               int32_t scheme, double *a, double *b);
+
+/* c = exp(-i dt T) e_1 for the real symmetric tridiagonal T with diagonal
+ * alpha[k] and off-diagonal beta[k-1] (Sec. 8.1: the exponential of the small
+ * projected matrix), computed by the device kernel that the propagator uses.
+ * alpha_dev, beta_dev: float64 device arrays; c_dev: complex128[k] device
+ * array; 1 <= k <= CFET_MAX_KRYLOV.  Stream-ordered; a convergence failure is
+ * reported through *status_dev (int32 device scalar: 0 or CFET_ENOCONV). */
+CFET_API int cfet_tridiag_expm(const double *alpha_dev, const double *beta_dev, int32_t k,
+                               double dt, void *c_dev, int32_t *status_dev, void *hip_stream);
+
+CFET_API int cfet_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFET_H */

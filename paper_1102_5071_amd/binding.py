@@ -1,0 +1,258 @@
+"""ctypes binding of libcfet.so (the C ABI in include/cfet.h).
+
+Argument marshalling only: every step of the propagation runs in the
+library's HIP kernels.  PyTorch supplies device memory (complex128 tensors on
+the GPU) and the current HIP stream.  If the shared library is missing the
+binding raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_uint32, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcfet.so")
+
+SCHEMES = {"CF2:1": 0, "CF4:2": 1, "CF4:3": 2, "CF4:3Opt": 3, "CF6:4": 4, "CF6:5": 5,
+           "CF6:5b": 6, "CF6:6": 7, "CF6:5Imp": 8, "CF6:5Opt": 9, "CF6:6Opt": 10,
+           "CF8:11": 11}
+DRIVE_KINDS = {"cos": 0, "sin2cos": 1, "pwc": 2, "sechcos": 3}
+ERRORS = {0: "CFET_OK", 1: "CFET_EINVAL", 2: "CFET_ENOMEM", 3: "CFET_EDEVICE",
+          4: "CFET_ENONFINITE", 5: "CFET_EUNSUPPORTED", 6: "CFET_ENOCONV"}
+VALIDATE_HERMITIAN = 0x1
+MAX_KRYLOV = 64
+
+
+class CfetError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("nnz", c_int64), ("row_ptr", c_void_p), ("col", c_void_p),
+                ("val", c_void_p)]
+
+
+class _Drive(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("A", c_double), ("omega", c_double), ("phi", c_double),
+                ("Tp", c_double), ("tc", c_double), ("tau", c_double), ("npieces", c_int32),
+                ("t_edges", c_void_p), ("u", c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("nnz_stored", c_int64), ("exponentials", c_int64),
+                ("matvecs", c_int64), ("min_m_eff", c_int32), ("breakdowns", c_int32),
+                ("path", c_int32), ("status", c_int32), ("last_norm", c_double),
+                ("timed_launches", c_int64), ("timed_ms", c_double)]
+
+
+_LIB = None
+
+
+def load():
+    """Load libcfet.so (once).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1102_5071_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.cfet_version.restype = c_int32
+    lib.cfet_last_error.restype = ctypes.c_char_p
+    lib.cfet_last_error.argtypes = [c_void_p]
+    lib.cfet_create.argtypes = [POINTER(_CSR), c_int32, POINTER(_CSR), POINTER(_Drive), c_uint32,
+                                POINTER(c_void_p)]
+    lib.cfet_propagate.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int64, c_int32,
+                                   c_int32, c_void_p]
+    lib.cfet_gradient.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_double, c_int64,
+                                  c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
+                                  c_void_p]
+    lib.cfet_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]
+    lib.cfet_stats.argtypes = [c_void_p, POINTER(_Stats)]
+    lib.cfet_destroy.argtypes = [c_void_p]
+    lib.cfet_scheme_info.argtypes = [c_int32, POINTER(c_int32), POINTER(c_int32), c_void_p,
+                                     c_void_p]
+    lib.cfet_step_weights.argtypes = [c_void_p, c_double, c_double, c_int64, c_int32, c_void_p,
+                                      c_void_p]
+    lib.cfet_profile.argtypes = [c_void_p, c_int32, c_int32]
+    lib.cfet_tridiag_expm.argtypes = [c_void_p, c_void_p, c_int32, c_double, c_void_p, c_void_p,
+                                      c_void_p]
+    for name in ("cfet_create", "cfet_propagate", "cfet_gradient", "cfet_apply", "cfet_stats",
+                 "cfet_destroy", "cfet_scheme_info", "cfet_step_weights", "cfet_tridiag_expm",
+                 "cfet_profile"):
+        getattr(lib, name).restype = c_int32
+    _LIB = lib
+    return lib
+
+
+def _check(code: int, ctx=None):
+    if code != 0:
+        lib = load()
+        msg = lib.cfet_last_error(ctx).decode(errors="replace")
+        raise CfetError(code, msg)
+
+
+def scheme_id(scheme) -> int:
+    return SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+
+
+def scheme_info(scheme):
+    """(x, g) as the library computes them (host-side call, no device work)."""
+    lib = load()
+    s = c_int32()
+    M = c_int32()
+    _check(lib.cfet_scheme_info(scheme_id(scheme), ctypes.byref(s), ctypes.byref(M), None, None))
+    x = np.zeros(M.value)
+    g = np.zeros(s.value * M.value)
+    _check(lib.cfet_scheme_info(scheme_id(scheme), ctypes.byref(s), ctypes.byref(M),
+                                x.ctypes.data, g.ctypes.data))
+    return x, g.reshape(s.value, M.value)
+
+
+def _ptr(a):
+    """Data pointer of a numpy array or a torch tensor (host or device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _csr_struct(m, keep):
+    rp = m.row_ptr
+    col = m.col
+    val = m.val
+    if isinstance(rp, np.ndarray):
+        rp = np.ascontiguousarray(rp, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.complex128)
+    keep.extend([rp, col, val])
+    return _CSR(int(m.n), int(rp[-1]) if isinstance(rp, np.ndarray) else int(m.nnz),
+                _ptr(rp), _ptr(col), _ptr(val))
+
+
+def _drive_struct(d, keep):
+    kind = DRIVE_KINDS[d["kind"]]
+    edges = u = None
+    npieces = 0
+    if d["kind"] == "pwc":
+        edges = np.ascontiguousarray(d["t_edges"], dtype=np.float64)
+        u = np.ascontiguousarray(d["u"], dtype=np.float64)
+        npieces = len(u)
+        keep.extend([edges, u])
+    return _Drive(kind, float(d.get("A", 0.0)), float(d.get("omega", 0.0)),
+                  float(d.get("phi", 0.0)), float(d.get("Tp", 0.0)), float(d.get("tc", 0.0)),
+                  float(d.get("tau", 1.0)), npieces, _ptr(edges), _ptr(u))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+class Propagator:
+    """Owns a cfet context for H(t) = H0 + sum_k f_k(t) Hk[k]."""
+
+    def __init__(self, H0, Hk, drives, validate_hermitian: bool = False):
+        lib = load()
+        keep = []
+        self.nterms = len(Hk)
+        if len(drives) != self.nterms:
+            raise ValueError("one drive per driven term")
+        h0 = _csr_struct(H0, keep)
+        hk = (_CSR * self.nterms)(*[_csr_struct(h, keep) for h in Hk])
+        dv = (_Drive * self.nterms)(*[_drive_struct(d, keep) for d in drives])
+        ctx = c_void_p()
+        flags = VALIDATE_HERMITIAN if validate_hermitian else 0
+        code = lib.cfet_create(ctypes.byref(h0), self.nterms, hk, dv, flags, ctypes.byref(ctx))
+        if code != 0:
+            raise CfetError(code, lib.cfet_last_error(None).decode(errors="replace"))
+        self._ctx = ctx
+        self.n = int(H0.n)
+
+    # -- helpers ---------------------------------------------------------
+    def _check_vec(self, v):
+        import torch
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.complex128
+                and v.is_contiguous() and v.numel() == self.n):
+            raise ValueError("expected a contiguous complex128 CUDA tensor of length n")
+
+    def propagate(self, psi, t0: float, dt: float, nsteps: int, scheme, m: int, stream=None):
+        """psi (complex128 CUDA tensor) is updated in place."""
+        self._check_vec(psi)
+        _check(load().cfet_propagate(self._ctx, c_void_p(psi.data_ptr()), float(t0), float(dt),
+                                     int(nsteps), scheme_id(scheme), int(m),
+                                     _stream_handle(stream)), self._ctx)
+        return psi
+
+    def apply(self, x, a: float, b, y=None, stream=None):
+        import torch
+        self._check_vec(x)
+        if y is None:
+            y = torch.empty_like(x)
+        self._check_vec(y)
+        bb = np.ascontiguousarray(np.atleast_1d(np.asarray(b, dtype=np.float64)))
+        if bb.size != self.nterms:
+            raise ValueError("need one weight per driven term")
+        _check(load().cfet_apply(self._ctx, c_void_p(x.data_ptr()), c_void_p(y.data_ptr()),
+                                 float(a), bb.ctypes.data, _stream_handle(stream)), self._ctx)
+        return y
+
+    def step_weights(self, t0: float, dt: float, nsteps: int, scheme):
+        s = scheme_info(scheme)[1].shape[0]
+        a = np.zeros(s)
+        b = np.zeros(max(nsteps, 1) * s * self.nterms)
+        _check(load().cfet_step_weights(self._ctx, float(t0), float(dt), int(nsteps),
+                                        scheme_id(scheme), a.ctypes.data, b.ctypes.data),
+               self._ctx)
+        return a, b[:nsteps * s * self.nterms].reshape(nsteps, s, self.nterms)
+
+    def stats(self) -> dict:
+        st = _Stats()
+        _check(load().cfet_stats(self._ctx, ctypes.byref(st)), self._ctx)
+        return {f[0]: getattr(st, f[0]) for f in _Stats._fields_}
+
+    def profile(self, enable: bool, max_launches: int = 65536):
+        _check(load().cfet_profile(self._ctx, 1 if enable else 0, int(max_launches)), self._ctx)
+
+    def gradient(self, *args, **kw):
+        _check(load().cfet_gradient(self._ctx, None, None, 0.0, 0.0, 0, 0, 1, None, 0, None, None,
+                                    None), self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().cfet_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def tridiag_expm(alpha, beta, dt: float, stream=None):
+    """c = exp(-i dt T) e_1 by the library's device kernel.  alpha, beta:
+    float64 CUDA tensors (len k, k-1).  Returns (c, status)."""
+    import torch
+    k = alpha.numel()
+    c = torch.empty(k, dtype=torch.complex128, device=alpha.device)
+    status = torch.zeros(1, dtype=torch.int32, device=alpha.device)
+    bptr = c_void_p(beta.data_ptr()) if beta is not None and beta.numel() > 0 else None
+    _check(load().cfet_tridiag_expm(c_void_p(alpha.data_ptr()), bptr, int(k), float(dt),
+                                    c_void_p(c.data_ptr()), c_void_p(status.data_ptr()),
+                                    _stream_handle(stream)))
+    return c, int(status.item())

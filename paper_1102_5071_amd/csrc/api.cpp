@@ -1,0 +1,664 @@
+// Host side of libcfet: argument validation, CSR merge and upload, workspace
+// management and the CFET step loop that enqueues the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "cfet_internal.h"
+
+using cfet::DevCSR;
+using cfet::DevStats;
+using cfet::DriveSpec;
+using cfet::LzScalars;
+using cfet::SchemeTable;
+
+struct cfet_ctx {
+  int device = 0;
+  int64_t n = 0;
+  int nterms = 0;
+  DevCSR A;
+  cfet::LaunchPlan plan{};
+  std::vector<DriveSpec> drives;
+  // Krylov workspace (grown on demand)
+  int m_alloc = 0;
+  double2* basis = nullptr;         // (m_alloc - 1) * n vectors
+  std::vector<double2*> h_W;        // host copy of the pointers (W[0] patched per call)
+  double* partA = nullptr;
+  double* partB = nullptr;
+  LzScalars* S = nullptr;           // Lanczos scalars of the running exponential
+  DevStats* stats = nullptr;
+  DevStats* stats_host = nullptr;   // pinned mirror, refreshed at the end of each call
+  hipStream_t last_stream = nullptr;
+  cfet::EventPool events;
+  bool profiling = false;
+  int64_t timed_launches = 0;
+  double timed_ms = 0.0;
+  bool have_work = false;
+  int last_path = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(cfet_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(cfet_ctx* c, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  const int code = (e == hipErrorOutOfMemory) ? CFET_ENOMEM : CFET_EDEVICE;
+  return fail(c, code, msg);
+}
+
+// True if p is device (or managed) memory; false for plain host memory.
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  const hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+template <class T>
+bool fetch_to_host(const T* p, size_t count, std::vector<T>& out, const T** view) {
+  if (count == 0) {
+    *view = p;
+    return true;
+  }
+  if (is_device_ptr(p)) {
+    try {
+      out.resize(count);
+    } catch (const std::bad_alloc&) {
+      return false;
+    }
+    if (hipMemcpy(out.data(), p, count * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
+      return false;
+    *view = out.data();
+  } else {
+    *view = p;
+  }
+  return true;
+}
+
+struct HostCSR {
+  int64_t n, nnz;
+  const int64_t* rp;
+  const int32_t* col;
+  const double* val;
+  std::vector<int64_t> rp_buf;
+  std::vector<int32_t> col_buf;
+  std::vector<double> val_buf;
+};
+
+int load_csr(cfet_ctx* c, const cfet_csr* m, const char* name, HostCSR* h) {
+  if (!m) return fail(c, CFET_EINVAL, std::string(name) + ": null matrix");
+  if (m->n <= 0 || m->nnz < 0) return fail(c, CFET_EINVAL, std::string(name) + ": bad n/nnz");
+  if (!m->row_ptr) return fail(c, CFET_EINVAL, std::string(name) + ": null row_ptr");
+  if (m->nnz > 0 && (!m->col || !m->val))
+    return fail(c, CFET_EINVAL, std::string(name) + ": null col/val");
+  h->n = m->n;
+  h->nnz = m->nnz;
+  if (!fetch_to_host(m->row_ptr, size_t(m->n + 1), h->rp_buf, &h->rp) ||
+      !fetch_to_host(m->col, size_t(m->nnz), h->col_buf, &h->col) ||
+      !fetch_to_host(m->val, size_t(2 * m->nnz), h->val_buf, &h->val))
+    return fail(c, CFET_ENOMEM, std::string(name) + ": cannot stage matrix on the host");
+  return CFET_OK;
+}
+
+// Structure and value checks, split over threads by rows.
+int validate_csr(cfet_ctx* c, const HostCSR& h, const char* name) {
+  if (h.rp[0] != 0 || h.rp[h.n] != h.nnz)
+    return fail(c, CFET_EINVAL, std::string(name) + ": row_ptr[0] != 0 or row_ptr[n] != nnz");
+  const int64_t n = h.n;
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 65536) nth = 1;
+  std::vector<int> bad(nth, 0);
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nth; ++t) {
+    pool.emplace_back([&, t]() {
+      const int64_t r0 = n * t / nth, r1 = n * (t + 1) / nth;
+      std::vector<int64_t> seen;  // duplicate detection by marking columns with the row id
+      for (int64_t r = r0; r < r1 && !bad[t]; ++r) {
+        const int64_t b = h.rp[r], e = h.rp[r + 1];
+        if (e < b || e > h.nnz) {
+          bad[t] = 1;
+          break;
+        }
+        for (int64_t k = b; k < e; ++k) {
+          const int32_t col = h.col[k];
+          if (col < 0 || col >= n) {
+            bad[t] = 2;
+            break;
+          }
+          if (!std::isfinite(h.val[2 * k]) || !std::isfinite(h.val[2 * k + 1])) {
+            bad[t] = 3;
+            break;
+          }
+          for (int64_t k2 = b; k2 < k && (e - b) <= 64; ++k2)
+            if (h.col[k2] == col) {
+              bad[t] = 4;
+              break;
+            }
+        }
+        if (!bad[t] && (e - b) > 64) {  // long rows: sort a copy
+          seen.assign(h.col + b, h.col + e);
+          std::sort(seen.begin(), seen.end());
+          if (std::adjacent_find(seen.begin(), seen.end()) != seen.end()) bad[t] = 4;
+        }
+      }
+    });
+  }
+  for (auto& th : pool) th.join();
+  for (unsigned t = 0; t < nth; ++t) {
+    switch (bad[t]) {
+      case 1: return fail(c, CFET_EINVAL, std::string(name) + ": row_ptr not non-decreasing");
+      case 2: return fail(c, CFET_EINVAL, std::string(name) + ": column index out of range");
+      case 3: return fail(c, CFET_ENONFINITE, std::string(name) + ": non-finite value");
+      case 4: return fail(c, CFET_EINVAL, std::string(name) + ": repeated column in a row");
+      default: break;
+    }
+  }
+  return CFET_OK;
+}
+
+int check_hermitian(cfet_ctx* c, const HostCSR& h, const char* name) {
+  for (int64_t r = 0; r < h.n; ++r) {
+    for (int64_t k = h.rp[r]; k < h.rp[r + 1]; ++k) {
+      const int64_t col = h.col[k];
+      bool found = false;
+      for (int64_t k2 = h.rp[col]; k2 < h.rp[col + 1]; ++k2) {
+        if (h.col[k2] == r) {
+          const double dr = h.val[2 * k] - h.val[2 * k2];
+          const double di = h.val[2 * k + 1] + h.val[2 * k2 + 1];
+          const double sc = std::fabs(h.val[2 * k]) + std::fabs(h.val[2 * k + 1]) + 1e-300;
+          if (std::fabs(dr) > 1e-12 * sc || std::fabs(di) > 1e-12 * sc)
+            return fail(c, CFET_EINVAL, std::string(name) + ": not Hermitian");
+          found = true;
+          break;
+        }
+      }
+      const bool zero = h.val[2 * k] == 0.0 && h.val[2 * k + 1] == 0.0;
+      if (!found && !zero) return fail(c, CFET_EINVAL, std::string(name) + ": not Hermitian");
+    }
+  }
+  return CFET_OK;
+}
+
+int copy_drive(cfet_ctx* c, const cfet_drive& d, DriveSpec* out) {
+  out->kind = d.kind;
+  out->A = d.A;
+  out->omega = d.omega;
+  out->phi = d.phi;
+  out->Tp = d.Tp;
+  out->tc = d.tc;
+  out->tau = d.tau;
+  switch (d.kind) {
+    case CFET_DRIVE_COS:
+      if (!std::isfinite(d.A) || !std::isfinite(d.omega) || !std::isfinite(d.phi))
+        return fail(c, CFET_EINVAL, "drive: non-finite parameter");
+      break;
+    case CFET_DRIVE_SIN2_COS:
+      if (!(d.Tp > 0.0) || !std::isfinite(d.Tp) || !std::isfinite(d.A) ||
+          !std::isfinite(d.omega) || !std::isfinite(d.phi))
+        return fail(c, CFET_EINVAL, "drive: SIN2_COS needs finite parameters and Tp > 0");
+      break;
+    case CFET_DRIVE_PWC: {
+      if (d.npieces < 1 || !d.t_edges || !d.u)
+        return fail(c, CFET_EINVAL, "drive: PWC needs npieces >= 1 and edges/u arrays");
+      out->edges.assign(d.t_edges, d.t_edges + d.npieces + 1);
+      out->u.assign(d.u, d.u + d.npieces);
+      for (int j = 0; j < d.npieces; ++j)
+        if (!(out->edges[j] < out->edges[j + 1]) || !std::isfinite(out->u[j]))
+          return fail(c, CFET_EINVAL, "drive: PWC edges must increase and u be finite");
+      if (!std::isfinite(out->edges[0]) || !std::isfinite(out->edges[d.npieces]))
+        return fail(c, CFET_EINVAL, "drive: PWC edges must be finite");
+      break;
+    }
+    case CFET_DRIVE_SECH_COS:
+      if (!(d.tau != 0.0) || !std::isfinite(d.tau) || !std::isfinite(d.A) ||
+          !std::isfinite(d.omega) || !std::isfinite(d.phi) || !std::isfinite(d.tc))
+        return fail(c, CFET_EINVAL, "drive: SECH_COS needs finite parameters and tau != 0");
+      break;
+    default:
+      return fail(c, CFET_EINVAL, "drive: unknown kind");
+  }
+  return CFET_OK;
+}
+
+void free_events(cfet_ctx* c) {
+  for (int i = 0; i < c->events.cap; ++i) {
+    if (c->events.begin[i]) (void)hipEventDestroy(c->events.begin[i]);
+    if (c->events.end[i]) (void)hipEventDestroy(c->events.end[i]);
+  }
+  delete[] c->events.begin;
+  delete[] c->events.end;
+  c->events = cfet::EventPool();
+}
+
+// Sum the durations of the recorded event pairs (their stream must be done).
+void harvest_events(cfet_ctx* c) {
+  for (int i = 0; i < c->events.used; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->events.begin[i], c->events.end[i]) == hipSuccess) {
+      c->timed_ms += ms;
+      c->timed_launches += 1;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  c->events.used = 0;
+}
+
+void free_ctx(cfet_ctx* c) {
+  if (!c) return;
+  free_events(c);
+  if (c->A.rowptr) (void)hipFree(c->A.rowptr);
+  if (c->A.colt) (void)hipFree(c->A.colt);
+  if (c->A.val) (void)hipFree(c->A.val);
+  if (c->basis) (void)hipFree(c->basis);
+  if (c->partA) (void)hipFree(c->partA);
+  if (c->partB) (void)hipFree(c->partB);
+  if (c->S) (void)hipFree(c->S);
+  if (c->stats) (void)hipFree(c->stats);
+  if (c->stats_host) (void)hipHostFree(c->stats_host);
+  delete c;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int ensure_workspace(cfet_ctx* c, int m) {
+  if (m <= c->m_alloc) return CFET_OK;
+  hipError_t e;
+  if (c->basis) {
+    e = hipFree(c->basis);
+    c->basis = nullptr;
+    c->m_alloc = 0;
+  }
+  const size_t bytes = size_t(m - 1) * size_t(c->n) * sizeof(double2);
+  if (bytes > 0) {
+    e = hipMalloc(&c->basis, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      c->basis = nullptr;
+      return fail(c, CFET_ENOMEM, "cannot allocate the Krylov basis (" +
+                                      std::to_string(bytes >> 20) + " MiB)");
+    }
+  }
+  c->h_W.assign(cfet::kMaxM, nullptr);
+  for (int j = 1; j < m; ++j) c->h_W[j] = c->basis + size_t(j - 1) * size_t(c->n);
+  c->m_alloc = m;
+  return CFET_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfet_version(void) { return CFET_VERSION; }
+
+const char* cfet_last_error(const cfet_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_err.c_str();
+}
+
+int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cfet_drive* fk,
+                uint32_t flags, cfet_ctx** out) {
+  if (!out) return fail(nullptr, CFET_EINVAL, "out is null");
+  *out = nullptr;
+  if (nterms < 1 || nterms > CFET_MAX_TERMS)
+    return fail(nullptr, CFET_EINVAL, "nterms must be in 1..7");
+  if (!H0 || !Hk || !fk) return fail(nullptr, CFET_EINVAL, "null H0, Hk or fk");
+  cfet_ctx* c = new (std::nothrow) cfet_ctx();
+  if (!c) return fail(nullptr, CFET_ENOMEM, "cannot allocate context");
+  int rc;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return hip_fail(nullptr, e, "hipGetDevice");
+  }
+  std::vector<HostCSR> mats(nterms + 1);
+  rc = load_csr(c, H0, "H0", &mats[0]);
+  for (int k = 0; rc == CFET_OK && k < nterms; ++k) rc = load_csr(c, &Hk[k], "Hk", &mats[k + 1]);
+  if (rc != CFET_OK) {
+    g_err = c->err;
+    free_ctx(c);
+    return rc;
+  }
+  const int64_t n = mats[0].n;
+  for (int k = 1; k <= nterms; ++k)
+    if (mats[k].n != n) {
+      rc = fail(c, CFET_EINVAL, "all matrices must have the same n");
+      free_ctx(c);
+      return rc;
+    }
+  if (n >= cfet::kMaxDim) {
+    rc = fail(c, CFET_EUNSUPPORTED, "dimension must be below 2^29");
+    free_ctx(c);
+    return rc;
+  }
+  for (int k = 0; k <= nterms && rc == CFET_OK; ++k) {
+    rc = validate_csr(c, mats[k], k == 0 ? "H0" : "Hk");
+    if (rc == CFET_OK && (flags & CFET_VALIDATE_HERMITIAN))
+      rc = check_hermitian(c, mats[k], k == 0 ? "H0" : "Hk");
+  }
+  c->drives.resize(nterms);
+  for (int k = 0; k < nterms && rc == CFET_OK; ++k) rc = copy_drive(c, fk[k], &c->drives[k]);
+  if (rc != CFET_OK) {
+    g_err = c->err;
+    free_ctx(c);
+    return rc;
+  }
+  c->n = n;
+  c->nterms = nterms;
+
+  // merged CSR on the host: row r holds the entries of H0, then of H1, ...
+  int64_t nnz = 0;
+  for (int k = 0; k <= nterms; ++k) nnz += mats[k].nnz;
+  std::vector<int64_t> rp;
+  std::vector<uint32_t> colt;
+  std::vector<double> val;
+  try {
+    rp.resize(n + 1);
+    colt.resize(nnz);
+    val.resize(2 * nnz);
+  } catch (const std::bad_alloc&) {
+    rc = fail(c, CFET_ENOMEM, "cannot stage the merged matrix on the host");
+    free_ctx(c);
+    return rc;
+  }
+  rp[0] = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t len = 0;
+    for (int k = 0; k <= nterms; ++k) len += mats[k].rp[r + 1] - mats[k].rp[r];
+    rp[r + 1] = rp[r] + len;
+  }
+  {
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 65536) nth = 1;
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; ++t) {
+      pool.emplace_back([&, t]() {
+        const int64_t r0 = n * t / nth, r1 = n * (t + 1) / nth;
+        for (int64_t r = r0; r < r1; ++r) {
+          int64_t pos = rp[r];
+          for (int k = 0; k <= nterms; ++k) {
+            const HostCSR& h = mats[k];
+            for (int64_t q = h.rp[r]; q < h.rp[r + 1]; ++q, ++pos) {
+              colt[pos] = uint32_t(h.col[q]) | (uint32_t(k) << cfet::kTermShift);
+              val[2 * pos] = h.val[2 * q];
+              val[2 * pos + 1] = h.val[2 * q + 1];
+            }
+          }
+        }
+      });
+    }
+    for (auto& th : pool) th.join();
+  }
+  c->A.n = n;
+  c->A.nnz = nnz;
+  e = hipMalloc(&c->A.rowptr, (n + 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&c->A.colt, std::max<int64_t>(nnz, 1) * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&c->A.val, std::max<int64_t>(nnz, 1) * sizeof(double2));
+  if (e == hipSuccess) e = hipMemcpy(c->A.rowptr, rp.data(), (n + 1) * sizeof(int64_t),
+                                     hipMemcpyHostToDevice);
+  if (e == hipSuccess && nnz)
+    e = hipMemcpy(c->A.colt, colt.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && nnz)
+    e = hipMemcpy(c->A.val, val.data(), nnz * sizeof(double2), hipMemcpyHostToDevice);
+  c->plan = cfet::make_plan(n, nnz);
+  const int np = std::max(c->plan.nb_spmv, c->plan.nb_vec);
+  if (e == hipSuccess) e = hipMalloc(&c->partA, np * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&c->partB, np * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&c->S, sizeof(LzScalars));
+  if (e == hipSuccess) e = hipMalloc(&c->stats, sizeof(DevStats));
+  if (e == hipSuccess) e = hipHostMalloc(&c->stats_host, sizeof(DevStats));
+  if (e == hipSuccess) e = cfet::launch_stats_init(c->stats, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    rc = hip_fail(c, e, "cfet_create: device setup");
+    (void)hipGetLastError();
+    g_err = c->err;
+    free_ctx(c);
+    return rc;
+  }
+  std::memset(c->stats_host, 0, sizeof(DevStats));
+  c->h_W.assign(cfet::kMaxM, nullptr);
+  *out = c;
+  return CFET_OK;
+}
+
+int cfet_destroy(cfet_ctx* c) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  DeviceGuard g(c->device);
+  if (c->have_work) (void)hipStreamSynchronize(c->last_stream);
+  free_ctx(c);
+  return CFET_OK;
+}
+
+int cfet_scheme_info(int32_t scheme, int32_t* s, int32_t* M, double* x, double* g) {
+  SchemeTable t;
+  if (!cfet::scheme_build(scheme, &t)) return fail(nullptr, CFET_EINVAL, "unknown scheme");
+  if (s) *s = t.s;
+  if (M) *M = t.M;
+  if (x)
+    for (int m = 0; m < t.M; ++m) x[m] = t.x[m];
+  if (g)
+    for (int i = 0; i < t.s; ++i)
+      for (int m = 0; m < t.M; ++m) g[i * t.M + m] = t.g[i][m];
+  return CFET_OK;
+}
+
+int cfet_step_weights(const cfet_ctx* c, double t0, double dt, int64_t nsteps, int32_t scheme,
+                      double* a, double* b) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  SchemeTable t;
+  if (!cfet::scheme_build(scheme, &t)) return fail(nullptr, CFET_EINVAL, "unknown scheme");
+  if (nsteps < 0 || !a || (nsteps > 0 && !b)) return fail(nullptr, CFET_EINVAL, "bad arguments");
+  std::vector<double> bb(t.s * c->nterms);
+  for (int64_t n = 0; n < nsteps; ++n) {
+    cfet::step_weights(t, c->drives, t0 + double(n) * dt, dt, a, bb.data());
+    std::memcpy(b + n * t.s * c->nterms, bb.data(), bb.size() * sizeof(double));
+  }
+  if (nsteps == 0) {
+    for (int i = 0; i < t.s; ++i) {
+      double sa = 0.0;
+      for (int m = 0; m < t.M; ++m) sa += t.g[i][m];
+      a[i] = sa;
+    }
+  }
+  return CFET_OK;
+}
+
+int cfet_apply(cfet_ctx* c, const void* x_dev, void* y_dev, double a, const double* b,
+               void* hip_stream) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  if (!x_dev || !y_dev || !b) return fail(c, CFET_EINVAL, "null x, y or b");
+  if (x_dev == y_dev) return fail(c, CFET_EINVAL, "x and y must not overlap");
+  if (!is_device_ptr(x_dev) || !is_device_ptr(y_dev))
+    return fail(c, CFET_EINVAL, "x and y must be device memory");
+  DeviceGuard g(c->device);
+  cfet::TermWeights tw;
+  std::memset(&tw, 0, sizeof(tw));
+  tw.w[0] = a;
+  for (int k = 0; k < c->nterms; ++k) tw.w[k + 1] = b[k];
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const hipError_t e = cfet::launch_apply(c->A, c->nterms, c->plan, tw,
+                                          static_cast<const double2*>(x_dev),
+                                          static_cast<double2*>(y_dev), st);
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_apply launch");
+  c->last_stream = st;
+  c->have_work = true;
+  return CFET_OK;
+}
+
+int cfet_propagate(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
+                   int32_t scheme, int32_t krylov_m, void* hip_stream) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  if (!psi_dev) return fail(c, CFET_EINVAL, "null psi");
+  if (nsteps < 0) return fail(c, CFET_EINVAL, "nsteps < 0");
+  if (krylov_m < 1 || krylov_m > CFET_MAX_KRYLOV)
+    return fail(c, CFET_EINVAL, "krylov_m must be in 1..64");
+  if (!std::isfinite(t0) || !std::isfinite(dt)) return fail(c, CFET_EINVAL, "non-finite t0/dt");
+  SchemeTable sc;
+  if (!cfet::scheme_build(scheme, &sc)) return fail(c, CFET_EINVAL, "unknown scheme");
+  if (!is_device_ptr(psi_dev)) return fail(c, CFET_EINVAL, "psi must be device memory");
+  DeviceGuard g(c->device);
+  // report a fault latched by earlier work that has already finished
+  if (c->have_work && hipStreamQuery(c->last_stream) == hipSuccess &&
+      c->stats_host->status != CFET_OK) {
+    const int st = c->stats_host->status;
+    c->stats_host->status = CFET_OK;
+    return fail(c, st, "device fault latched by an earlier call (see cfet_stats)");
+  }
+  if (nsteps == 0) return CFET_OK;
+  const int m = int(std::min<int64_t>(krylov_m, c->n));
+  int rc = ensure_workspace(c, m);
+  if (rc != CFET_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  c->h_W[0] = static_cast<double2*>(psi_dev);
+  hipError_t e;
+  cfet::ExpWork wk;
+  wk.W_host = c->h_W.data();
+  wk.partA = c->partA;
+  wk.partB = c->partB;
+  wk.S = c->S;
+  wk.stats = c->stats;
+  if (c->profiling) {
+    if (c->events.used > 0) {
+      (void)hipStreamSynchronize(c->last_stream);
+      harvest_events(c);
+    }
+    wk.events = &c->events;
+  } else {
+    wk.events = nullptr;
+  }
+  e = cfet::launch_norm_start(c->h_W[0], c->n, c->plan, c->partA, st);
+  if (e != hipSuccess) return hip_fail(c, e, "norm kernel");
+  std::vector<double> a(sc.s), b(sc.s * c->nterms);
+  cfet::TermWeights tw;
+  std::memset(&tw, 0, sizeof(tw));
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const double tn = t0 + double(n) * dt;
+    cfet::step_weights(sc, c->drives, tn, dt, a.data(), b.data());
+    for (int i = sc.s - 1; i >= 0; --i) {
+      tw.w[0] = a[i];
+      for (int k = 0; k < c->nterms; ++k) tw.w[k + 1] = b[i * c->nterms + k];
+      e = cfet::launch_exponential(c->A, c->nterms, c->plan, tw, dt, m, wk, st);
+      if (e != hipSuccess) return hip_fail(c, e, "exponential kernels");
+    }
+  }
+  e = cfet::launch_final_norm(c->partA, c->plan.nb_vec, c->stats, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->stats_host, c->stats, sizeof(DevStats), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(c, e, "final kernels");
+  c->last_stream = st;
+  c->have_work = true;
+  c->last_path = 1;
+  return CFET_OK;
+}
+
+int cfet_profile(cfet_ctx* c, int32_t enable, int32_t max_launches) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  DeviceGuard g(c->device);
+  if (c->have_work) (void)hipStreamSynchronize(c->last_stream);
+  harvest_events(c);
+  free_events(c);
+  c->profiling = false;
+  c->timed_launches = 0;
+  c->timed_ms = 0.0;
+  if (!enable) return CFET_OK;
+  if (max_launches < 1 || max_launches > (1 << 20))
+    return fail(c, CFET_EINVAL, "max_launches must be in 1..2^20");
+  c->events.begin = new (std::nothrow) hipEvent_t[max_launches]();
+  c->events.end = new (std::nothrow) hipEvent_t[max_launches]();
+  if (!c->events.begin || !c->events.end) {
+    free_events(c);
+    return fail(c, CFET_ENOMEM, "cannot allocate the event pool");
+  }
+  c->events.cap = max_launches;
+  for (int i = 0; i < max_launches; ++i) {
+    hipError_t e = hipEventCreate(&c->events.begin[i]);
+    if (e == hipSuccess) e = hipEventCreate(&c->events.end[i]);
+    if (e != hipSuccess) {
+      free_events(c);
+      return hip_fail(c, e, "hipEventCreate");
+    }
+  }
+  c->profiling = true;
+  return CFET_OK;
+}
+
+int cfet_gradient(cfet_ctx* c, const void*, const void*, double, double, int64_t, int32_t,
+                  int32_t, const double*, int32_t, double*, double*, void*) {
+  return fail(c, CFET_EUNSUPPORTED, "cfet_gradient is not implemented in this build");
+}
+
+int cfet_stats(cfet_ctx* c, cfet_stats_t* s) {
+  if (!c || !s) return fail(c, CFET_EINVAL, "null argument");
+  DeviceGuard g(c->device);
+  hipError_t e = hipSuccess;
+  if (c->have_work) e = hipStreamSynchronize(c->last_stream);
+  if (e != hipSuccess) return hip_fail(c, e, "synchronise");
+  DevStats d;
+  e = hipMemcpy(&d, c->stats, sizeof(d), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "read statistics");
+  std::memset(s, 0, sizeof(*s));
+  s->n = c->n;
+  s->nnz_stored = c->A.nnz;
+  s->exponentials = int64_t(d.exponentials);
+  s->matvecs = int64_t(d.matvecs);
+  s->min_m_eff = d.exponentials ? d.min_m_eff : 0;
+  s->breakdowns = d.breakdowns;
+  s->path = c->last_path;
+  s->status = d.status;
+  s->last_norm = std::sqrt(d.last_norm2);
+  harvest_events(c);
+  s->timed_launches = c->timed_launches;
+  s->timed_ms = c->timed_ms;
+  if (d.status != CFET_OK) {
+    const int32_t ok = CFET_OK;
+    e = hipMemcpy(reinterpret_cast<char*>(c->stats) + offsetof(DevStats, status), &ok,
+                  sizeof(ok), hipMemcpyHostToDevice);
+    c->stats_host->status = CFET_OK;
+    if (e != hipSuccess) return hip_fail(c, e, "clear status");
+  }
+  return CFET_OK;
+}
+
+int cfet_tridiag_expm(const double* alpha_dev, const double* beta_dev, int32_t k, double dt,
+                      void* c_dev, int32_t* status_dev, void* hip_stream) {
+  if (k < 1 || k > CFET_MAX_KRYLOV) return fail(nullptr, CFET_EINVAL, "k must be in 1..64");
+  if (!alpha_dev || !c_dev || (k > 1 && !beta_dev))
+    return fail(nullptr, CFET_EINVAL, "null argument");
+  if (!std::isfinite(dt)) return fail(nullptr, CFET_EINVAL, "non-finite dt");
+  const hipError_t e =
+      cfet::launch_tridiag_expm(alpha_dev, beta_dev, k, dt, static_cast<double2*>(c_dev),
+                                status_dev, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "tridiagonal exponential launch");
+  return CFET_OK;
+}
+
+}  // extern "C"

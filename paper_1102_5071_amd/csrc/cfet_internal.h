@@ -1,0 +1,116 @@
+// Internal declarations shared by the host driver and the device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cfet.h"
+
+namespace cfet {
+
+constexpr int kMaxStages = 11;  // CF8:11 has the most exponentials
+constexpr int kMaxTerms = CFET_MAX_TERMS;
+constexpr int kMaxM = CFET_MAX_KRYLOV;
+constexpr int kTermShift = 29;  // merged CSR: column | (term << 29)
+constexpr uint32_t kColMask = (1u << kTermShift) - 1u;
+constexpr int64_t kMaxDim = (int64_t(1) << kTermShift);
+constexpr double kBreakdownRel = 1e-12;
+
+struct SchemeTable {
+  int s, M, order;
+  double x[4], w[4];
+  double g[kMaxStages][4];
+};
+
+struct DriveSpec {
+  int kind;
+  double A, omega, phi, Tp, tc, tau;
+  std::vector<double> edges, u;
+};
+
+bool scheme_build(int id, SchemeTable* out);
+double drive_eval(const DriveSpec& d, double t);
+void step_weights(const SchemeTable& sc, const std::vector<DriveSpec>& drives, double t_n,
+                  double dt, double* a, double* b);
+
+// Per-exponential Lanczos scalars, written by block 0 of one kernel and read
+// by all blocks of later kernels only (kernel boundaries order the accesses;
+// no launch reads a field that the same launch writes).
+struct LzScalars {
+  double alpha[kMaxM];
+  double beta[kMaxM];        // beta[j] = ||w_{j+1}||  (off-diagonal of T)
+  double inv_nrm[kMaxM];     // stored basis vector j is w_j, v_j = w_j * inv_nrm[j]
+  double beta0;
+  double coef[2 * kMaxM];    // recombination: psi = sum_j coef_j w_j
+  int32_t brk[kMaxM];        // brk[j] = 1: the recursion stopped at or before step j
+  int32_t m_eff;             // effective Krylov dimension (final after the small exponential)
+  int32_t pad;
+};
+
+// Device-side statistics and latched status.
+struct DevStats {
+  unsigned long long exponentials;
+  unsigned long long matvecs;
+  int32_t min_m_eff;
+  int32_t breakdowns;
+  int32_t status;
+  int32_t pad;
+  double last_norm2;
+};
+
+// Term weights of one exponential: w[0] multiplies H0, w[1+k] multiplies H_k.
+struct TermWeights {
+  double w[kMaxTerms + 1];
+};
+
+// Device copy of the merged operator.
+struct DevCSR {
+  int64_t n = 0, nnz = 0;
+  int64_t* rowptr = nullptr;   // int64[n+1]
+  uint32_t* colt = nullptr;    // column | term << kTermShift
+  double2* val = nullptr;      // complex128[nnz]
+};
+
+// Launch helpers (device.hip).
+struct LaunchPlan {
+  int G;        // lanes per row in the SpMV
+  int nb_spmv;  // blocks of the SpMV kernels
+  int nb_vec;   // blocks of the elementwise kernels
+};
+
+LaunchPlan make_plan(int64_t n, int64_t nnz);
+
+hipError_t launch_apply(const DevCSR& A, int nterms, const LaunchPlan& plan, const TermWeights& tw,
+                        const double2* x, double2* y, hipStream_t st);
+
+// Multi-kernel exponential: psi <- exp(-i dt H_w) psi using m Lanczos vectors.
+struct EventPool {
+  hipEvent_t* begin = nullptr;
+  hipEvent_t* end = nullptr;
+  int cap = 0;
+  int used = 0;
+};
+
+struct ExpWork {
+  double2* const* W_host;  // basis pointers: W[0] = psi, W[j] = workspace (W[j] = W[1] + (j-1) n)
+  EventPool* events;     // optional SpMV timing (null: off)
+  double* partA;         // partial sums (norms)
+  double* partB;         // partial sums (alpha)
+  LzScalars* S;          // scalar block of the exponential
+  DevStats* stats;
+};
+
+hipError_t launch_norm_start(const double2* psi, int64_t n, const LaunchPlan& plan, double* part,
+                             hipStream_t st);
+hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& plan,
+                              const TermWeights& tw, double dt, int m, const ExpWork& wk,
+                              hipStream_t st);
+hipError_t launch_final_norm(const double* part, int np, DevStats* st_dev, hipStream_t st);
+hipError_t launch_tridiag_expm(const double* alpha, const double* beta, int k, double dt,
+                               double2* c, int32_t* status, hipStream_t st);
+hipError_t launch_stats_init(DevStats* st_dev, hipStream_t st);
+
+}  // namespace cfet

@@ -1,0 +1,288 @@
+// exp(-i dt T) e_1 for a real symmetric tridiagonal T of order k <= 64,
+// computed by one 64-lane wavefront (the small exponential of paper Sec. 8.1).
+//
+// Method: implicit symmetric QR iteration with Wilkinson shift (bulge chasing
+// with Givens rotations), deflating from the bottom, accumulating the
+// rotations into Z so that T = Z diag(lambda) Z^T.  Then
+//     c = Z exp(-i dt lambda) Z^T e_1,  c_r = sum_l Z[r][l] e^{-i dt lambda_l} Z[0][l].
+// Lane r holds T's diagonal entry a_r and sub-diagonal entry b_r (b_r couples
+// rows r and r+1) in registers and row r of Z in LDS (column-major,
+// Z[col*64 + row], so every lane touches only its own bank).  Uniform scalars
+// of the sweep are read with v_readlane; deflation flags for all positions
+// are formed in parallel and combined with a ballot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cfet {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Diagonalise T in place: on return lane l's a holds eigenvalue l and column l
+// of Z (LDS) its eigenvector.  Returns 0 or CFET_ENOCONV.
+__device__ inline int tridiag_eig_wave(double& a, double& b, int k, double* Z) {
+  const int lane = threadIdx.x & 63;
+  for (int col = 0; col < k; ++col) Z[col * 64 + lane] = (lane == col) ? 1.0 : 0.0;
+  if (lane >= k - 1) b = 0.0;
+  if (lane >= k) a = 0.0;
+  const double eps = 2.220446049250313e-16;
+  const double tnorm = wave_max(fabs(a) + fabs(b));
+  const double floor_abs = 1e-2 * eps * tnorm;
+  int q = k - 1;
+  int iters = 0;
+  const int maxit = 40 * k;
+  while (q > 0) {
+    const double anext = __shfl_down(a, 1, 64);
+    const bool neg = (lane < k - 1) && (fabs(b) <= eps * (fabs(a) + fabs(anext)) + floor_abs);
+    const unsigned long long mask = __ballot(neg);
+    if (neg) b = 0.0;
+    while (q > 0 && ((mask >> (q - 1)) & 1ull)) --q;
+    if (q == 0) break;
+    const unsigned long long below = (q >= 2) ? (mask & ((1ull << (q - 1)) - 1ull)) : 0ull;
+    const int p = below ? (64 - __clzll(below)) : 0;
+    if (++iters > maxit) return CFET_ENOCONV;
+    // Wilkinson shift from the trailing 2x2 block of [p..q]
+    const double aq = lane_read(a, q), aq1 = lane_read(a, q - 1), bq = lane_read(b, q - 1);
+    const double d = 0.5 * (aq1 - aq);
+    const double h = sqrt(d * d + bq * bq);
+    const double mu = aq - bq * bq / (d + (d >= 0.0 ? h : -h));
+    // chase the bulge from p to q
+    double ak = lane_read(a, p), bk = lane_read(b, p);
+    double bprev = 0.0, bulge = 0.0;
+    double zk = Z[p * 64 + lane];
+    for (int kk = p; kk < q; ++kk) {
+      const double ak1 = lane_read(a, kk + 1);
+      const double bk1 = (kk + 1 < q) ? lane_read(b, kk + 1) : 0.0;
+      const double xr = (kk == p) ? ak - mu : bprev;
+      const double zr = (kk == p) ? bk : bulge;
+      const double r = sqrt(xr * xr + zr * zr);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) {
+        const double ir = 1.0 / r;
+        c = xr * ir;
+        s = zr * ir;
+      }
+      if (kk > p && lane == kk - 1) b = r;
+      const double cc = c * c, ss = s * s, cs = c * s;
+      const double nak = cc * ak + 2.0 * cs * bk + ss * ak1;
+      const double nak1 = ss * ak - 2.0 * cs * bk + cc * ak1;
+      const double nbk = cs * (ak1 - ak) + (cc - ss) * bk;
+      bulge = s * bk1;
+      const double nbk1 = c * bk1;
+      if (lane == kk) a = nak;
+      ak = nak1;
+      bk = nbk1;
+      bprev = nbk;
+      const double zk1 = Z[(kk + 1) * 64 + lane];
+      Z[kk * 64 + lane] = c * zk + s * zk1;
+      zk = c * zk1 - s * zk;
+    }
+    if (lane == q) a = ak;
+    if (lane == q - 1) b = bprev;
+    Z[q * 64 + lane] = zk;
+  }
+  return 0;
+}
+
+// c (lane r holds c_r) = exp(-i dt T) e_1 by diagonalisation.  a, b as above
+// (taken by value).  Z: 64*64 doubles of LDS, phi: 64 complex of LDS.
+// Returns 0 or CFET_ENOCONV.
+__device__ inline int tridiag_exp_e1_qr(double a, double b, int k, double dt, double* Z,
+                                        double2* phi, double2& c) {
+  const int lane = threadIdx.x & 63;
+  const int status = tridiag_eig_wave(a, b, k, Z);
+  double sn, cs;
+  sincos(dt * a, &sn, &cs);
+  const double z0 = Z[lane * 64];  // row 0 of eigenvector 'lane'
+  if (lane < k) phi[lane] = make_double2(cs * z0, -sn * z0);
+  wave_sync();
+  double cr = 0.0, ci = 0.0;
+  for (int l = 0; l < k; ++l) {
+    const double z = Z[l * 64 + lane];
+    const double2 p = phi[l];
+    cr += z * p.x;
+    ci += z * p.y;
+  }
+  c = (lane < k) ? make_double2(cr, ci) : make_double2(0.0, 0.0);
+  wave_sync();
+  return status;
+}
+
+}  // namespace cfet
+
+namespace cfet {
+
+// Values of the neighbouring lanes (wavefront-wide DPP shifts; 0 past the ends).
+__device__ __forceinline__ double from_lane_below(double v) {  // lane r receives lane r-1
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_lane_above(double v) {  // lane r receives lane r+1
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Number of eigenvalues of T below x (Sylvester inertia of the LDL^T
+// factorisation of T - x I); x may differ per lane.
+__device__ inline int sturm_count(double a, double b, int k, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  double bprev = 0.0;
+  for (int r = 0; r < k; ++r) {
+    const double ar = lane_read(a, r);
+    d = (ar - x) - ((r > 0) ? bprev * bprev / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    cnt += (d < 0.0) ? 1 : 0;
+    bprev = lane_read(b, r);
+  }
+  return cnt;
+}
+
+constexpr int kChebMaxTerms = 8192;      // LDS doubles reserved for the Bessel values
+constexpr double kChebMaxTheta = 7000.0; // beyond this the QR path is cheaper
+
+// c = exp(-i dt T) e_1 by the Chebyshev expansion of exp(-i theta x) on the
+// spectral interval of T (Jacobi-Anger: exp(-i theta x) = J_0(theta)
+// + 2 sum_k (-i)^k J_k(theta) T_k(x)).  With X = (T - sigma)/h the vectors
+// T_k(X) e_1 are real and follow t_{k+1} = 2 X t_k - t_{k-1}; the Bessel values
+// J_k(theta) come from Miller's backward recurrence normalised by
+// J_0 + 2 sum J_2k = 1.  lds: kChebMaxTerms doubles.  Returns 0, or 1 if theta
+// is too large for this path (the caller then diagonalises).
+__device__ inline int tridiag_exp_e1_cheb(double a, double b, int k, double dt, double* lds,
+                                          double2& c) {
+  const int lane = threadIdx.x & 63;
+  if (lane >= k - 1) b = 0.0;
+  if (lane >= k) a = 0.0;
+  const double bl = from_lane_below(b);      // b_{r-1}
+  // Gershgorin interval
+  double lo = (lane < k) ? a - fabs(bl) - fabs(b) : 1e300;
+  double hi = (lane < k) ? a + fabs(bl) + fabs(b) : -1e300;
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  double theta = fabs(dt) * 0.5 * (hi - lo);
+  if (theta > 32.0 && k > 1) {
+    // Two rounds of 64-point multisection on the Sturm count tighten both
+    // ends: round 0 spans the Gershgorin interval, round 1 spends 32 points
+    // on each end within one round-0 spacing.  Every update keeps a valid
+    // bound (count == k: all eigenvalues below x; count == 0: none below x).
+    const double w0 = (hi - lo) / 64.0;
+    for (int round = 0; round < 2; ++round) {
+      const double x = (round == 0) ? lo + w0 * (double)(lane + 1)
+                       : (lane < 32) ? lo + w0 * (double)(lane + 1) / 32.0
+                                     : hi - w0 * (double)(64 - lane) / 32.0;
+      const int cnt = sturm_count(a, b, k, x);
+      const double nhi = wave_min((cnt == k) ? x : 1e300);
+      const double nlo = wave_max((cnt == 0) ? x : -1e300);
+      if (nhi < 1e299) hi = fmin(hi, nhi);
+      if (nlo > -1e299) lo = fmax(lo, nlo);
+    }
+    // rounding in the counts can misplace a bound by a few ulps
+    const double pad = 1e-10 * (fabs(hi) + fabs(lo)) + 1e-300;
+    hi += pad;
+    lo -= pad;
+  }
+  const double sigma = 0.5 * (hi + lo);
+  const double h = 0.5 * (hi - lo);
+  theta = fabs(dt) * h;
+  if (theta > kChebMaxTheta) return 1;
+  // phase of exp(-i dt sigma)
+  double sn, cs;
+  sincos(dt * sigma, &sn, &cs);
+  if (!(theta > 1e-300)) {  // T = sigma I
+    c = (lane == 0) ? make_double2(cs, -sn) : make_double2(0.0, 0.0);
+    return 0;
+  }
+  const int N = (int)ceil(theta + 12.0 * cbrt(theta) + 20.0);
+  const int Nm = N + 30;
+  // Miller: f_{Nm+1} = 0, f_{Nm} = tiny, f_{j-1} = (2j/theta) f_j - f_{j+1}
+  double f1 = 0.0, f0 = 1e-30, S = 0.0;
+  const double it2 = 2.0 / theta;
+  for (int j = Nm; j >= 1; --j) {
+    if (j <= N) {
+      if (lane == 0) lds[j] = f0;
+      if ((j & 1) == 0) S += 2.0 * f0;
+    }
+    const double fm = (double)j * it2 * f0 - f1;
+    f1 = f0;
+    f0 = fm;
+    if (fabs(f0) > 1e200) {  // rescale everything computed so far
+      f0 *= 1e-200;
+      f1 *= 1e-200;
+      S *= 1e-200;
+      if (lane == 0)
+        for (int q = j; q <= N; ++q) lds[q] *= 1e-200;
+    }
+  }
+  if (lane == 0) lds[0] = f0;
+  S += f0;
+  wave_sync();
+  // forward Chebyshev recurrence on the real vectors t_k = T_k(X) e_1
+  const double inv_h = 1.0 / h;
+  const double ax = (lane < k) ? (a - sigma) * inv_h : 0.0;
+  const double blo = bl * inv_h, bhi = b * inv_h;
+  const double sgn = (dt >= 0.0) ? -1.0 : 1.0;   // phase (sgn i)^k
+  double tp = (lane == 0) ? 1.0 : 0.0;           // t_0
+  double cr = lds[0] * tp, ci = 0.0;
+  double t = ax * tp + blo * from_lane_below(tp) + bhi * from_lane_above(tp);  // t_1
+  ci += 2.0 * sgn * lds[1] * t;
+  for (int j = 2; j <= N; ++j) {
+    const double xt = ax * t + blo * from_lane_below(t) + bhi * from_lane_above(t);
+    const double tn = 2.0 * xt - tp;
+    tp = t;
+    t = tn;
+    const double w = 2.0 * lds[j];
+    switch (j & 3) {
+      case 0: cr += w * t; break;
+      case 1: ci += sgn * w * t; break;
+      case 2: cr -= w * t; break;
+      default: ci -= sgn * w * t; break;
+    }
+  }
+  const double invS = 1.0 / S;
+  cr *= invS;
+  ci *= invS;
+  // multiply by exp(-i dt sigma) = cs - i sn
+  c = (lane < k) ? make_double2(cs * cr + sn * ci, cs * ci - sn * cr) : make_double2(0.0, 0.0);
+  wave_sync();
+  return 0;
+}
+
+// Dispatcher: Chebyshev when cheap, diagonalisation otherwise.  lds must hold
+// kChebMaxTerms doubles (it also hosts Z and phi of the QR path).
+__device__ inline int tridiag_exp_e1(double a, double b, int k, double dt, double* lds,
+                                     double2& c) {
+  if (k == 1) {
+    double sn, cs;
+    sincos(dt * a, &sn, &cs);
+    c = ((threadIdx.x & 63) == 0) ? make_double2(cs, -sn) : make_double2(0.0, 0.0);
+    return 0;
+  }
+  if (tridiag_exp_e1_cheb(a, b, k, dt, lds, c) == 0) return 0;
+  return tridiag_exp_e1_qr(a, b, k, dt, lds, reinterpret_cast<double2*>(lds + 64 * 64), c);
+}
+
+}  // namespace cfet

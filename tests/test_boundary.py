@@ -1,0 +1,81 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, host-side scheme data agrees with the oracle, and argument errors
+that are decided before any device work return the documented codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import schemes as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cfet.h")
+
+B = pytest.importorskip("paper_1102_5071_amd.binding")
+
+
+def _lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libcfet.so is not built (run python -m paper_1102_5071_amd.build)")
+    return B.load()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"CFET_API\s+[\w\s\*]+?\b(cfet_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for must in ("cfet_create", "cfet_propagate", "cfet_gradient", "cfet_stats", "cfet_destroy",
+                 "cfet_apply", "cfet_last_error", "cfet_tridiag_expm"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert lib.cfet_version() == 1
+
+
+def test_scheme_enum_matches_header():
+    text = open(HEADER).read()
+    enum = dict((k, int(v)) for k, v in re.findall(r"(CFET_CF\w+)\s*=\s*(\d+)", text))
+    names = {"CF2:1": "CFET_CF2_1", "CF4:2": "CFET_CF4_2", "CF4:3": "CFET_CF4_3",
+             "CF4:3Opt": "CFET_CF4_3OPT", "CF6:4": "CFET_CF6_4", "CF6:5": "CFET_CF6_5",
+             "CF6:5b": "CFET_CF6_5B", "CF6:6": "CFET_CF6_6", "CF6:5Imp": "CFET_CF6_5IMP",
+             "CF6:5Opt": "CFET_CF6_5OPT", "CF6:6Opt": "CFET_CF6_6OPT", "CF8:11": "CFET_CF8_11"}
+    for k, v in names.items():
+        assert B.SCHEMES[k] == enum[v]
+
+
+@pytest.mark.parametrize("name", list(S.SCHEMES))
+def test_library_scheme_weights_match_oracle(name):
+    _lib()
+    x, g = B.scheme_info(name)
+    xo, go = S.gl_weights(S.scheme(name))
+    assert np.allclose(x, xo, atol=1e-16, rtol=0)
+    assert g.shape == go.shape
+    # independent evaluations (explicit polynomials vs recurrence): a few ulps
+    assert np.allclose(g, go, atol=1e-15, rtol=0)
+
+
+def test_host_side_argument_errors():
+    lib = _lib()
+    assert lib.cfet_scheme_info(99, None, None, None, None) == 1
+    assert lib.cfet_scheme_info(-1, None, None, None, None) == 1
+    assert lib.cfet_create(None, 1, None, None, 0, None) == 1
+    out = ctypes.c_void_p()
+    assert lib.cfet_create(None, 1, None, None, 0, ctypes.byref(out)) == 1
+    assert lib.cfet_create(None, 0, None, None, 0, ctypes.byref(out)) == 1
+    assert lib.cfet_create(None, 8, None, None, 0, ctypes.byref(out)) == 1
+    assert out.value is None
+    assert lib.cfet_tridiag_expm(None, None, 0, 0.1, None, None, None) == 1
+    assert lib.cfet_tridiag_expm(None, None, 65, 0.1, None, None, None) == 1
+    assert lib.cfet_propagate(None, None, 0.0, 0.1, 1, 1, 4, None) == 1
+    assert lib.cfet_stats(None, None) == 1
+    assert lib.cfet_destroy(None) == 1
+    assert b"null" in lib.cfet_last_error(None)
