@@ -40,6 +40,14 @@ def spmv_algorithmic_bytes(dim, nnz_total, ncsr):
     return 20 * nnz_total + 8 * (dim + 1) * ncsr + 32 * dim
 
 
+def exponential_algorithmic_bytes(dim, nnz_total, ncsr, m):
+    """One Lanczos exponential: m SpMVs, m-1 three-term updates with norm
+    (read y, v_j, v_{j-1}, write w: 64 B per row) and the recombination
+    (read m basis vectors, write psi: (m+1)*16 B per row)."""
+    return (m * spmv_algorithmic_bytes(dim, nnz_total, ncsr) + (m - 1) * 64 * dim
+            + (m + 1) * 16 * dim)
+
+
 def make_workload(name, L):
     from paper_1102_5071_amd import inputs as I
     if name == "hydrogen":
@@ -86,6 +94,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=-1,
                     help="oracle sample length (steps); 0 disables")
     ap.add_argument("--no-error", action="store_true", help="skip the state-error run")
+    ap.add_argument("--path", default=None, choices=["multi", "single", "coop"],
+                    help="force an execution path (default: chosen by dimension)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -105,7 +115,7 @@ def main():
     K, W = args.steps, args.warmup
     log(f"workload {label}, dt={p.dt}, steps={K}, warmup={W}")
     t = time.perf_counter()
-    P = B.Propagator(p.H0, p.Hk, p.drives)
+    P = B.Propagator(p.H0, p.Hk, p.drives, path=args.path)
     log(f"context created in {time.perf_counter() - t:.1f}s")
     nnz_total = p.H0.nnz + sum(h.nnz for h in p.Hk)
     ncsr = 1 + len(p.Hk)
@@ -133,7 +143,11 @@ def main():
         f"matvecs {matvecs} (expected {K * s * min(p.m, p.dim)}), min m_eff {st1['min_m_eff']}")
     psi_end = psi.clone()
 
-    # kernel timing pass (events around every SpMV launch on the propagation stream)
+    path = B.PATH_NAMES[st1["path"]]
+    m_eff = min(p.m, p.dim)
+    # kernel timing pass: HIP events on the propagation stream around every
+    # launch of the dominant kernel (the SpMV on the multi-kernel path, the
+    # whole-call kernel on the persistent paths)
     psi.copy_(psi_start)
     P.profile(True, max_launches=min(K * s * p.m, 1 << 18))
     P.propagate(psi, t_start, p.dt, K, p.scheme, p.m)
@@ -141,9 +155,14 @@ def main():
     stp = P.stats()
     P.profile(False)
     avg_ms = stp["timed_ms"] / max(1, stp["timed_launches"])
-    bytes_per_launch = spmv_algorithmic_bytes(p.dim, nnz_total, ncsr)
+    if path == "multi":
+        kernel = "k_lz_spmv"
+        bytes_per_launch = spmv_algorithmic_bytes(p.dim, nnz_total, ncsr)
+    else:
+        kernel = "k_propagate"
+        bytes_per_launch = K * s * exponential_algorithmic_bytes(p.dim, nnz_total, ncsr, m_eff)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    log(f"SpMV: {stp['timed_launches']} launches, avg {avg_ms * 1e3:.2f} us, "
+    log(f"path {path}: {kernel} {stp['timed_launches']} launches, avg {avg_ms * 1e3:.2f} us, "
         f"{bytes_per_launch / 1e6:.2f} MB algorithmic -> {achieved:.0f} GB/s")
 
     # state error over the timed window: reference at dt/4 with m = 40
@@ -184,10 +203,10 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": label, "dim": p.dim, "nnz": nnz_total, "scheme": p.scheme,
-                   "krylov_m": p.m, "dt": p.dt, "t0": t_start,
+                   "krylov_m": p.m, "dt": p.dt, "t0": t_start, "path": path,
                    "state_error": state_error,
                    "matvecs_per_step": matvecs / K},
-        "roofline": {"bound": "hbm", "kernel": "k_lz_spmv", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": bytes_per_launch,

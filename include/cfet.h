@@ -110,6 +110,19 @@ typedef struct {
 
 /* Flags for cfet_create. */
 #define CFET_VALIDATE_HERMITIAN 0x1u /* check H = H^dagger for every matrix */
+/* Execution path of cfet_propagate (default: chosen from the dimension).
+ * All paths compute the same propagation; they differ in launch structure:
+ * one kernel per Lanczos phase, one persistent single-workgroup launch per
+ * call, or one persistent cooperative (grid-barrier) launch per call. */
+#define CFET_FORCE_MULTIKERNEL 0x10u
+#define CFET_FORCE_SINGLE 0x20u       /* if the rows fit one workgroup's registers */
+#define CFET_FORCE_COOPERATIVE 0x40u  /* if the rows fit the co-resident blocks */
+/* A forced persistent path that does not fit falls back to the multi-kernel
+ * path; cfet_stats reports the path taken. */
+/* Store the operator in sliced-ELL form (64-row slices, column-major, driven
+ * terms first in each row) for the multi-kernel path; the default for large
+ * dimensions, where only the multi-kernel path runs. */
+#define CFET_LAYOUT_SELL 0x100u
 
 typedef struct cfet_ctx cfet_ctx;
 
@@ -175,9 +188,11 @@ CFET_API int cfet_destroy(cfet_ctx *c);
 CFET_API const char *cfet_last_error(const cfet_ctx *c);
 
 /* Kernel timing for measurement: with enable != 0, cfet_propagate records a
- * HIP event pair on the caller's stream around every launch of the Lanczos
- * SpMV kernel (up to max_launches pairs per call; later launches run
- * untimed), and cfet_stats reports the count and summed duration.  The
+ * HIP event pair on the caller's stream around every launch of its dominant
+ * kernel -- the Lanczos SpMV on the multi-kernel path, the whole persistent
+ * kernel on the single-workgroup and cooperative paths -- (up to max_launches
+ * pairs; later launches run untimed), and cfet_stats reports the count and
+ * summed duration.  The
  * events add a little launch overhead, so throughput is measured with timing
  * off.  enable == 0 releases the events. */
 CFET_API int cfet_profile(cfet_ctx *c, int32_t enable, int32_t max_launches);

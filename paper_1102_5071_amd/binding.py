@@ -23,6 +23,9 @@ DRIVE_KINDS = {"cos": 0, "sin2cos": 1, "pwc": 2, "sechcos": 3}
 ERRORS = {0: "CFET_OK", 1: "CFET_EINVAL", 2: "CFET_ENOMEM", 3: "CFET_EDEVICE",
           4: "CFET_ENONFINITE", 5: "CFET_EUNSUPPORTED", 6: "CFET_ENOCONV"}
 VALIDATE_HERMITIAN = 0x1
+PATH_FLAGS = {None: 0, "auto": 0, "multi": 0x10, "single": 0x20, "coop": 0x40,
+              "sell": 0x10 | 0x100}
+PATH_NAMES = {0: "none", 1: "multi", 2: "single", 3: "coop"}
 MAX_KRYLOV = 64
 
 
@@ -160,7 +163,7 @@ def _stream_handle(stream):
 class Propagator:
     """Owns a cfet context for H(t) = H0 + sum_k f_k(t) Hk[k]."""
 
-    def __init__(self, H0, Hk, drives, validate_hermitian: bool = False):
+    def __init__(self, H0, Hk, drives, validate_hermitian: bool = False, path=None):
         lib = load()
         keep = []
         self.nterms = len(Hk)
@@ -170,7 +173,7 @@ class Propagator:
         hk = (_CSR * self.nterms)(*[_csr_struct(h, keep) for h in Hk])
         dv = (_Drive * self.nterms)(*[_drive_struct(d, keep) for d in drives])
         ctx = c_void_p()
-        flags = VALIDATE_HERMITIAN if validate_hermitian else 0
+        flags = (VALIDATE_HERMITIAN if validate_hermitian else 0) | PATH_FLAGS[path]
         code = lib.cfet_create(ctypes.byref(h0), self.nterms, hk, dv, flags, ctypes.byref(ctx))
         if code != 0:
             raise CfetError(code, lib.cfet_last_error(None).decode(errors="replace"))

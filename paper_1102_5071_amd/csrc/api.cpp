@@ -24,6 +24,8 @@ struct cfet_ctx {
   int64_t n = 0;
   int nterms = 0;
   DevCSR A;
+  cfet::DevSELL sell;
+  bool use_sell = false;
   cfet::LaunchPlan plan{};
   std::vector<DriveSpec> drives;
   // Krylov workspace (grown on demand)
@@ -42,12 +44,35 @@ struct cfet_ctx {
   double timed_ms = 0.0;
   bool have_work = false;
   int last_path = 0;
+  uint32_t flags = 0;
+  // persistent paths
+  double* d_wts = nullptr;          // per-call weight table on the device
+  size_t wts_cap = 0;               // doubles
+  double* h_wts = nullptr;          // pinned staging buffer
+  size_t h_wts_cap = 0;
+  hipEvent_t wts_copied = nullptr;  // the staging buffer may be rewritten once this fired
+  bool wts_pending = false;
+  double* d_part = nullptr;         // 4 * blocks partial sums (2 parities x 2 sums)
+  double2* zbuf = nullptr;          // 2 * n: H u_k of the last two Lanczos steps
+  int part_cap = 0;
+  unsigned long long* d_bar = nullptr;
+  int* d_fault = nullptr;
+  long long spin_limit = 0;
+  int num_cus = 0;
+  int max_row = 0;                  // longest row of the merged operator
+  int preset_single = -1;           // register preset of the one-workgroup kernel (-1: none)
+  int preset_coop = -1;             // register preset of the cooperative kernel (-1: none)
+  int coop_blocks = 0;              // grid of the cooperative kernel
   std::string err;
 };
 
 namespace {
 
 thread_local std::string g_err;
+
+// automatic path choice by dimension
+constexpr int64_t kAutoSingleMaxN = 4096;
+constexpr int64_t kAutoCoopMaxN = int64_t(1) << 22;
 
 int fail(cfet_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -269,12 +294,24 @@ void free_ctx(cfet_ctx* c) {
   if (c->A.rowptr) (void)hipFree(c->A.rowptr);
   if (c->A.colt) (void)hipFree(c->A.colt);
   if (c->A.val) (void)hipFree(c->A.val);
+  if (c->sell.slice_ptr) (void)hipFree(c->sell.slice_ptr);
+  if (c->sell.slice_width) (void)hipFree(c->sell.slice_width);
+  if (c->sell.rowlen) (void)hipFree(c->sell.rowlen);
+  if (c->sell.colt) (void)hipFree(c->sell.colt);
+  if (c->sell.val) (void)hipFree(c->sell.val);
   if (c->basis) (void)hipFree(c->basis);
   if (c->partA) (void)hipFree(c->partA);
   if (c->partB) (void)hipFree(c->partB);
   if (c->S) (void)hipFree(c->S);
   if (c->stats) (void)hipFree(c->stats);
   if (c->stats_host) (void)hipHostFree(c->stats_host);
+  if (c->d_wts) (void)hipFree(c->d_wts);
+  if (c->h_wts) (void)hipHostFree(c->h_wts);
+  if (c->wts_copied) (void)hipEventDestroy(c->wts_copied);
+  if (c->d_part) (void)hipFree(c->d_part);
+  if (c->zbuf) (void)hipFree(c->zbuf);
+  if (c->d_bar) (void)hipFree(c->d_bar);
+  if (c->d_fault) (void)hipFree(c->d_fault);
   delete c;
 }
 
@@ -310,6 +347,130 @@ int ensure_workspace(cfet_ctx* c, int m) {
   c->h_W.assign(cfet::kMaxM, nullptr);
   for (int j = 1; j < m; ++j) c->h_W[j] = c->basis + size_t(j - 1) * size_t(c->n);
   c->m_alloc = m;
+  return CFET_OK;
+}
+
+// 1: one kernel per phase, 2: one workgroup, 3: cooperative grid
+bool single_fits(const cfet_ctx* c) { return c->preset_single >= 0; }
+
+bool coop_fits(const cfet_ctx* c) { return c->preset_coop >= 0 && c->coop_blocks > 0; }
+
+int choose_path(const cfet_ctx* c) {
+  if (c->flags & CFET_FORCE_MULTIKERNEL) return 1;
+  if ((c->flags & CFET_FORCE_SINGLE) && single_fits(c)) return 2;
+  if ((c->flags & CFET_FORCE_COOPERATIVE) && coop_fits(c)) return 3;
+  if (c->flags & (CFET_FORCE_SINGLE | CFET_FORCE_COOPERATIVE)) return 1;
+  if (c->n <= kAutoSingleMaxN && single_fits(c)) return 2;
+  if (c->n <= kAutoCoopMaxN && coop_fits(c)) return 3;
+  return 1;
+}
+
+int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
+                         const SchemeTable& sc, int m, int path, hipStream_t st) {
+  const int nt1 = c->nterms + 1;
+  if (c->profiling && c->events.used > 0) {
+    (void)hipStreamSynchronize(c->last_stream);
+    harvest_events(c);
+  }
+  const size_t need = size_t(nsteps) * sc.s * nt1;
+  hipError_t e;
+  // the pinned staging buffer is reused: wait for its previous upload
+  if (c->wts_pending) {
+    e = hipEventSynchronize(c->wts_copied);
+    if (e != hipSuccess) return hip_fail(c, e, "wait for the weight upload");
+    c->wts_pending = false;
+  }
+  if (need > c->h_wts_cap) {
+    if (c->h_wts) (void)hipHostFree(c->h_wts);
+    c->h_wts = nullptr;
+    c->h_wts_cap = 0;
+    e = hipHostMalloc(&c->h_wts, need * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, CFET_ENOMEM, "cannot allocate the pinned weight table");
+    }
+    c->h_wts_cap = need;
+  }
+  if (need > c->wts_cap) {
+    if (c->d_wts) (void)hipFree(c->d_wts);
+    c->d_wts = nullptr;
+    c->wts_cap = 0;
+    e = hipMalloc(&c->d_wts, need * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, CFET_ENOMEM, "cannot allocate the device weight table");
+    }
+    c->wts_cap = need;
+  }
+  std::vector<double> a(sc.s), b(sc.s * c->nterms);
+  for (int64_t n = 0; n < nsteps; ++n) {
+    cfet::step_weights(sc, c->drives, t0 + double(n) * dt, dt, a.data(), b.data());
+    double* row = c->h_wts + size_t(n) * sc.s * nt1;
+    for (int i = 0; i < sc.s; ++i) {
+      row[i * nt1] = a[i];
+      for (int k = 0; k < c->nterms; ++k) row[i * nt1 + 1 + k] = b[i * c->nterms + k];
+    }
+  }
+  e = hipMemcpyAsync(c->d_wts, c->h_wts, need * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(c->wts_copied, st);
+  if (e != hipSuccess) return hip_fail(c, e, "upload the weight table");
+  c->wts_pending = true;
+  int nblocks = 1;
+  if (path == 3) {
+    nblocks = c->coop_blocks;
+    if (4 * nblocks > c->part_cap) {
+      if (c->d_part) (void)hipFree(c->d_part);
+      c->d_part = nullptr;
+      c->part_cap = 0;
+      e = hipMalloc(&c->d_part, 4 * nblocks * sizeof(double));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, CFET_ENOMEM, "cannot allocate partial sums");
+      }
+      c->part_cap = 4 * nblocks;
+    }
+  }
+  if (!c->zbuf) {
+    e = hipMalloc(&c->zbuf, 2 * size_t(c->n) * sizeof(double2));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      c->zbuf = nullptr;
+      return fail(c, CFET_ENOMEM, "cannot allocate the persistent z buffers");
+    }
+  }
+  cfet::PersistArgs pa;
+  pa.rowptr = c->A.rowptr;
+  pa.colt = c->A.colt;
+  pa.val = c->A.val;
+  pa.n = c->n;
+  pa.nterms = c->nterms;
+  pa.wts = c->d_wts;
+  pa.s = sc.s;
+  pa.nsteps = nsteps;
+  pa.m = m;
+  pa.dt = dt;
+  pa.psi = static_cast<double2*>(psi_dev);
+  pa.basis = c->basis;
+  pa.zbuf = c->zbuf;
+  pa.part = c->d_part;
+  pa.bar = c->d_bar;
+  pa.fault = c->d_fault;
+  pa.stats = c->stats;
+  pa.spin_limit = c->spin_limit;
+  const bool timed = c->profiling && c->events.used < c->events.cap;
+  if (timed) (void)hipEventRecord(c->events.begin[c->events.used], st);
+  e = cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop, path == 2,
+                             nblocks, st);
+  if (timed && e == hipSuccess) {
+    (void)hipEventRecord(c->events.end[c->events.used], st);
+    c->events.used += 1;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->stats_host, c->stats, sizeof(DevStats), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(c, e, "persistent propagation launch");
+  c->last_stream = st;
+  c->have_work = true;
+  c->last_path = path;
   return CFET_OK;
 }
 
@@ -373,31 +534,48 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
   }
   c->n = n;
   c->nterms = nterms;
+  c->flags = flags;
 
-  // merged CSR on the host: row r holds the entries of H0, then of H1, ...
+  // Device layouts.  CSR (row r: entries of H0, then H1, ...) serves the
+  // persistent paths and small problems; SELL (row r: H1.., then H0) serves the
+  // multi-kernel path for large dimensions, where CSR is not kept.
   int64_t nnz = 0;
   for (int k = 0; k <= nterms; ++k) nnz += mats[k].nnz;
-  std::vector<int64_t> rp;
-  std::vector<uint32_t> colt;
-  std::vector<double> val;
+  std::vector<int32_t> rowlen;
   try {
-    rp.resize(n + 1);
-    colt.resize(nnz);
-    val.resize(2 * nnz);
+    rowlen.resize(n);
   } catch (const std::bad_alloc&) {
-    rc = fail(c, CFET_ENOMEM, "cannot stage the merged matrix on the host");
+    rc = fail(c, CFET_ENOMEM, "cannot stage row lengths on the host");
     free_ctx(c);
     return rc;
   }
-  rp[0] = 0;
   for (int64_t r = 0; r < n; ++r) {
     int64_t len = 0;
     for (int k = 0; k <= nterms; ++k) len += mats[k].rp[r + 1] - mats[k].rp[r];
-    rp[r + 1] = rp[r] + len;
+    rowlen[r] = int32_t(std::min<int64_t>(len, INT32_MAX));
+    c->max_row = std::max<int>(c->max_row, rowlen[r]);
   }
-  {
-    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n < 65536) nth = 1;
+  const bool use_sell = (flags & CFET_LAYOUT_SELL) || n > kAutoCoopMaxN;
+  const bool need_csr = !use_sell || n <= kAutoCoopMaxN;
+  c->A.n = n;
+  c->A.nnz = nnz;
+  const unsigned nth_all = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (need_csr) {
+    std::vector<int64_t> rp;
+    std::vector<uint32_t> colt;
+    std::vector<double> val;
+    try {
+      rp.resize(n + 1);
+      colt.resize(nnz);
+      val.resize(2 * nnz);
+    } catch (const std::bad_alloc&) {
+      rc = fail(c, CFET_ENOMEM, "cannot stage the merged matrix on the host");
+      free_ctx(c);
+      return rc;
+    }
+    rp[0] = 0;
+    for (int64_t r = 0; r < n; ++r) rp[r + 1] = rp[r] + rowlen[r];
+    const unsigned nth = (n < 65536) ? 1u : nth_all;
     std::vector<std::thread> pool;
     for (unsigned t = 0; t < nth; ++t) {
       pool.emplace_back([&, t]() {
@@ -416,25 +594,113 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       });
     }
     for (auto& th : pool) th.join();
+    e = hipMalloc(&c->A.rowptr, (n + 1) * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&c->A.colt, std::max<int64_t>(nnz, 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&c->A.val, std::max<int64_t>(nnz, 1) * sizeof(double2));
+    if (e == hipSuccess)
+      e = hipMemcpy(c->A.rowptr, rp.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz)
+      e = hipMemcpy(c->A.colt, colt.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz)
+      e = hipMemcpy(c->A.val, val.data(), nnz * sizeof(double2), hipMemcpyHostToDevice);
   }
-  c->A.n = n;
-  c->A.nnz = nnz;
-  e = hipMalloc(&c->A.rowptr, (n + 1) * sizeof(int64_t));
-  if (e == hipSuccess) e = hipMalloc(&c->A.colt, std::max<int64_t>(nnz, 1) * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(&c->A.val, std::max<int64_t>(nnz, 1) * sizeof(double2));
-  if (e == hipSuccess) e = hipMemcpy(c->A.rowptr, rp.data(), (n + 1) * sizeof(int64_t),
-                                     hipMemcpyHostToDevice);
-  if (e == hipSuccess && nnz)
-    e = hipMemcpy(c->A.colt, colt.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess && nnz)
-    e = hipMemcpy(c->A.val, val.data(), nnz * sizeof(double2), hipMemcpyHostToDevice);
+  if (e == hipSuccess && use_sell) {
+    const int64_t nsl = (n + 63) / 64;
+    std::vector<int64_t> sptr(nsl + 1);
+    std::vector<int32_t> swid(nsl);
+    sptr[0] = 0;
+    for (int64_t sl = 0; sl < nsl; ++sl) {
+      int w = 0;
+      for (int64_t r = sl * 64; r < std::min<int64_t>(n, sl * 64 + 64); ++r) w = std::max(w, rowlen[r]);
+      swid[sl] = w;
+      sptr[sl + 1] = sptr[sl] + 64 * int64_t(w);
+    }
+    const int64_t slots = sptr[nsl];
+    std::vector<uint32_t> scol;
+    std::vector<double> sval;
+    try {
+      scol.assign(slots, 0u);
+      sval.assign(2 * slots, 0.0);
+    } catch (const std::bad_alloc&) {
+      rc = fail(c, CFET_ENOMEM, "cannot stage the SELL matrix on the host");
+      free_ctx(c);
+      return rc;
+    }
+    const unsigned nth = (n < 65536) ? 1u : nth_all;
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; ++t) {
+      pool.emplace_back([&, t]() {
+        const int64_t s0 = nsl * t / nth, s1 = nsl * (t + 1) / nth;
+        for (int64_t sl = s0; sl < s1; ++sl) {
+          for (int64_t r = sl * 64; r < std::min<int64_t>(n, sl * 64 + 64); ++r) {
+            const int64_t lane = r - sl * 64;
+            int64_t k = 0;
+            for (int tt = 1; tt <= nterms + 1; ++tt) {
+              const int term = (tt == nterms + 1) ? 0 : tt;  // driven terms first, then H0
+              const HostCSR& h = mats[term];
+              for (int64_t q = h.rp[r]; q < h.rp[r + 1]; ++q, ++k) {
+                const int64_t pos = sptr[sl] + 64 * k + lane;
+                scol[pos] = uint32_t(h.col[q]) | (uint32_t(term) << cfet::kTermShift);
+                sval[2 * pos] = h.val[2 * q];
+                sval[2 * pos + 1] = h.val[2 * q + 1];
+              }
+            }
+          }
+        }
+      });
+    }
+    for (auto& th : pool) th.join();
+    c->sell.n = n;
+    c->sell.slots = slots;
+    e = hipMalloc(&c->sell.slice_ptr, (nsl + 1) * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&c->sell.slice_width, nsl * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&c->sell.rowlen, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&c->sell.colt, std::max<int64_t>(slots, 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&c->sell.val, std::max<int64_t>(slots, 1) * sizeof(double2));
+    if (e == hipSuccess)
+      e = hipMemcpy(c->sell.slice_ptr, sptr.data(), (nsl + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->sell.slice_width, swid.data(), nsl * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->sell.rowlen, rowlen.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && slots)
+      e = hipMemcpy(c->sell.colt, scol.data(), slots * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && slots)
+      e = hipMemcpy(c->sell.val, sval.data(), slots * sizeof(double2), hipMemcpyHostToDevice);
+    c->use_sell = true;
+  }
   c->plan = cfet::make_plan(n, nnz);
+  if (c->use_sell) c->plan.nb_spmv = cfet::sell_grid(n);
   const int np = std::max(c->plan.nb_spmv, c->plan.nb_vec);
   if (e == hipSuccess) e = hipMalloc(&c->partA, np * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->partB, np * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->S, sizeof(LzScalars));
   if (e == hipSuccess) e = hipMalloc(&c->stats, sizeof(DevStats));
   if (e == hipSuccess) e = hipHostMalloc(&c->stats_host, sizeof(DevStats));
+  if (e == hipSuccess) e = hipMalloc(&c->d_bar, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&c->d_fault, sizeof(int));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->wts_copied, hipEventDisableTiming);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e == hipSuccess) {
+    int khz = 0;
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device);
+    if (khz <= 0) khz = 100000;
+    c->spin_limit = (long long)khz * 1000LL * 10LL;  // 10 s
+  }
+  c->preset_single = need_csr ? cfet::persistent_choose_preset(c->max_row, n) : -1;
+  if (e == hipSuccess && c->num_cus > 0 && need_csr) {
+    // cooperative grid: one block per CU, but at least ~128 rows per block
+    const int64_t nbw = std::max<int64_t>(1, std::min<int64_t>(c->num_cus, (n + 127) / 128));
+    const int64_t rows = (n + nbw - 1) / nbw;
+    c->preset_coop = cfet::persistent_choose_preset(c->max_row, rows);
+    if (c->preset_coop >= 0) {
+      int maxb = 0;
+      e = cfet::persistent_max_blocks(c->preset_coop, nterms, &maxb);
+      c->coop_blocks = (maxb >= nbw) ? int(nbw) : 0;
+      if (c->coop_blocks == 0) c->preset_coop = -1;
+    }
+  }
   if (e == hipSuccess) e = cfet::launch_stats_init(c->stats, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -505,9 +771,13 @@ int cfet_apply(cfet_ctx* c, const void* x_dev, void* y_dev, double a, const doub
   tw.w[0] = a;
   for (int k = 0; k < c->nterms; ++k) tw.w[k + 1] = b[k];
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const hipError_t e = cfet::launch_apply(c->A, c->nterms, c->plan, tw,
-                                          static_cast<const double2*>(x_dev),
-                                          static_cast<double2*>(y_dev), st);
+  const hipError_t e =
+      c->use_sell ? cfet::launch_sell_apply(c->sell, c->nterms, tw,
+                                            static_cast<const double2*>(x_dev),
+                                            static_cast<double2*>(y_dev), st)
+                  : cfet::launch_apply(c->A, c->nterms, c->plan, tw,
+                                       static_cast<const double2*>(x_dev),
+                                       static_cast<double2*>(y_dev), st);
   if (e != hipSuccess) return hip_fail(c, e, "cfet_apply launch");
   c->last_stream = st;
   c->have_work = true;
@@ -538,6 +808,8 @@ int cfet_propagate(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nst
   int rc = ensure_workspace(c, m);
   if (rc != CFET_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int path = choose_path(c);
+  if (path != 1) return propagate_persistent(c, psi_dev, t0, dt, nsteps, sc, m, path, st);
   c->h_W[0] = static_cast<double2*>(psi_dev);
   hipError_t e;
   cfet::ExpWork wk;
@@ -546,6 +818,7 @@ int cfet_propagate(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nst
   wk.partB = c->partB;
   wk.S = c->S;
   wk.stats = c->stats;
+  wk.sell = c->use_sell ? &c->sell : nullptr;
   if (c->profiling) {
     if (c->events.used > 0) {
       (void)hipStreamSynchronize(c->last_stream);

@@ -74,6 +74,25 @@ struct DevCSR {
   double2* val = nullptr;      // complex128[nnz]
 };
 
+// Device copy of the operator in sliced-ELL form (sell.hip): slices of 64
+// consecutive rows stored column-major and padded to the slice's longest row.
+struct DevSELL {
+  int64_t n = 0;
+  int64_t* slice_ptr = nullptr;  // first slot of each slice
+  int32_t* slice_width = nullptr;
+  int32_t* rowlen = nullptr;     // entries of each row
+  uint32_t* colt = nullptr;      // column | term << kTermShift (padding: 0)
+  double2* val = nullptr;        // padding: 0
+  int64_t slots = 0;
+};
+
+int sell_grid(int64_t n);
+hipError_t launch_sell_apply(const DevSELL& S, int nterms, const TermWeights& tw, const double2* x,
+                             double2* y, hipStream_t st);
+hipError_t launch_sell_lz_spmv(const DevSELL& S, int nterms, const TermWeights& tw,
+                               const double2* x, double2* y, const double* pin, int npin,
+                               double* pout, LzScalars* L, int j, hipStream_t st);
+
 // Launch helpers (device.hip).
 struct LaunchPlan {
   int G;        // lanes per row in the SpMV
@@ -96,6 +115,7 @@ struct EventPool {
 
 struct ExpWork {
   double2* const* W_host;  // basis pointers: W[0] = psi, W[j] = workspace (W[j] = W[1] + (j-1) n)
+  const DevSELL* sell;   // SELL layout for the SpMV (null: CSR)
   EventPool* events;     // optional SpMV timing (null: off)
   double* partA;         // partial sums (norms)
   double* partB;         // partial sums (alpha)
@@ -109,6 +129,36 @@ hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& pla
                               const TermWeights& tw, double dt, int m, const ExpWork& wk,
                               hipStream_t st);
 hipError_t launch_final_norm(const double* part, int np, DevStats* st_dev, hipStream_t st);
+// Persistent propagation (persistent.hip): one launch for a whole call.
+constexpr int kPersistBlock = 512;  // threads per block of the persistent kernels
+
+struct PersistArgs {
+  const int64_t* rowptr;
+  const uint32_t* colt;
+  const double2* val;
+  int64_t n;
+  int nterms;
+  const double* wts;        // [(step*s + i)*(1+nterms) + t]: t = 0 -> a_i, t > 0 -> b_{i,t-1}
+  int s;
+  int64_t nsteps;
+  int m;
+  double dt;
+  double2* psi;
+  double2* basis;           // basis vector j >= 1 at basis + (j-1)*n
+  double2* zbuf;            // 2 * n: H u_k of the last two Lanczos steps
+  double* part;             // 2 parities x 2 sums x gridDim partial sums
+  unsigned long long* bar;  // barrier arrival counter (reset before the launch)
+  int* fault;               // set when a barrier wait times out
+  DevStats* stats;
+  long long spin_limit;     // barrier wait limit in wall-clock ticks
+};
+
+hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,
+                             hipStream_t st);
+hipError_t persistent_max_blocks(int preset, int nterms, int* out);
+int persistent_rows_per_block(int preset);
+int persistent_choose_preset(int max_row, int64_t min_rows_per_block);
+
 hipError_t launch_tridiag_expm(const double* alpha, const double* beta, int k, double dt,
                                double2* c, int32_t* status, hipStream_t st);
 hipError_t launch_stats_init(DevStats* st_dev, hipStream_t st);

@@ -424,7 +424,9 @@ hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& pla
     double2* y = (j + 1 < m) ? wk.W_host[j + 1] : nullptr;
     EventPool* ev = (wk.events && wk.events->used < wk.events->cap) ? wk.events : nullptr;
     if (ev) (void)hipEventRecord(ev->begin[ev->used], st);
-    if (nterms == 1)
+    if (wk.sell)
+      e = launch_sell_lz_spmv(*wk.sell, nterms, tw, x, y, wk.partA, plan.nb_vec, wk.partB, S, j, st);
+    else if (nterms == 1)
       e = dispatch_spmv<1>(plan.G, A, plan.nb_spmv, tw, x, y, wk.partA, plan.nb_vec, wk.partB, S,
                            j, st);
     else

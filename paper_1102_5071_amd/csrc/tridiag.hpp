@@ -272,9 +272,11 @@ __device__ inline int tridiag_exp_e1_cheb(double a, double b, int k, double dt, 
 }
 
 // Dispatcher: Chebyshev when cheap, diagonalisation otherwise.  lds must hold
-// kChebMaxTerms doubles (it also hosts Z and phi of the QR path).
-__device__ inline int tridiag_exp_e1(double a, double b, int k, double dt, double* lds,
-                                     double2& c) {
+// kChebMaxTerms doubles (it also hosts Z and phi of the QR path).  Kept out of
+// line: it runs once per exponential, and inlining it would raise the register
+// count of the whole persistent kernel.
+__device__ __noinline__ int tridiag_exp_e1(double a, double b, int k, double dt, double* lds,
+                                           double2& c) {
   if (k == 1) {
     double sn, cs;
     sincos(dt * a, &sn, &cs);

@@ -20,6 +20,7 @@ torch = pytest.importorskip("torch")
 B = pytest.importorskip("paper_1102_5071_amd.binding")
 
 PROP_TOL = 1e-10
+PATHS = ["multi", "single", "coop", "sell"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -45,12 +46,19 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def run_gpu(prob_H0, Hk, drives, psi0, t0, dt, nsteps, scheme, m):
-    with B.Propagator(prob_H0, Hk, drives) as P:
+def run_gpu(prob_H0, Hk, drives, psi0, t0, dt, nsteps, scheme, m, path=None):
+    with B.Propagator(prob_H0, Hk, drives, path=path) as P:
         psi = dev(psi0)
         P.propagate(psi, t0, dt, nsteps, scheme, m)
         out = host(psi)
         st = P.stats()
+    if path is not None:
+        # a persistent path whose rows do not fit falls back to the multi-kernel one
+        # ("sell" is the multi-kernel path on the sliced-ELL layout)
+        assert B.PATH_NAMES[st["path"]] in (path, "multi")
+        if path in ("single", "coop") and prob_H0.n <= 1024:
+            assert B.PATH_NAMES[st["path"]] == path
+    assert st["status"] == 0, st
     return out, st
 
 
@@ -83,8 +91,9 @@ def _apply_ref(H0, Hk, a, b, x):
     return y
 
 
+@pytest.mark.parametrize("layout", ["multi", "sell"])
 @pytest.mark.parametrize("case", ["ising10", "hydrogen_small", "ragged", "two_term", "heis12"])
-def test_apply_matches_reference(case):
+def test_apply_matches_reference(case, layout):
     rng = np.random.default_rng(5)
     if case == "ising10":
         p = I.config_ising()
@@ -105,7 +114,7 @@ def test_apply_matches_reference(case):
     x = I.random_state(H0.n, rng)
     a = -0.37
     b = [0.81, -1.3][:len(Hk)]
-    with B.Propagator(H0, Hk, drives) as P:
+    with B.Propagator(H0, Hk, drives, path=layout) as P:
         y = host(P.apply(dev(x), a, b))
     ref = _apply_ref(H0, Hk, a, b, x)
     assert rel(y, ref) < 1e-14
@@ -151,8 +160,9 @@ def test_tridiag_exponential(name, a, b, dt):
 # --------------------------------------------------------------------------
 # full propagation
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("scheme", list(S.SCHEMES))
-def test_propagate_random_all_schemes(scheme):
+def test_propagate_random_all_schemes(scheme, path):
     rng = np.random.default_rng(21)
     n = 64
     H0 = I.random_hermitian(n, rng, density=0.15)
@@ -162,7 +172,7 @@ def test_propagate_random_all_schemes(scheme):
               {"kind": "sechcos", "A": 0.5, "omega": 0.8, "phi": 0.0, "tc": 0.3, "tau": 0.7}]
     psi0 = I.random_state(n, rng)
     args = (H0, [H1, H2], drives, psi0, 0.1, 0.05, 12, scheme, 10)
-    out, st = run_gpu(*args)
+    out, st = run_gpu(*args, path=path)
     ref = O.propagate(*args[:8], m=10)
     assert rel(out, ref) < PROP_TOL
     assert st["status"] == 0
@@ -180,9 +190,10 @@ def test_step_weights_match_oracle():
                 assert np.allclose(b[n], rb, rtol=0, atol=1e-15)
 
 
-def test_ising_full_run():
+@pytest.mark.parametrize("path", PATHS)
+def test_ising_full_run(path):
     p = I.config_ising()          # L = 10, CF4:2, dt 0.01, 1000 steps, m 16
-    out, st = run_gpu(p.H0, p.Hk, p.drives, p.psi0, 0.0, p.dt, p.nsteps, p.scheme, p.m)
+    out, st = run_gpu(p.H0, p.Hk, p.drives, p.psi0, 0.0, p.dt, p.nsteps, p.scheme, p.m, path)
     ref = O.propagate(p.H0, p.Hk, p.drives, p.psi0, 0.0, p.dt, p.nsteps, p.scheme, m=p.m)
     assert rel(out, ref) < PROP_TOL
     assert st["exponentials"] == 2 * p.nsteps
@@ -190,7 +201,8 @@ def test_ising_full_run():
     assert abs(np.linalg.norm(out) - 1.0) < 1e-12
 
 
-def test_hydrogen_full_size_short_run():
+@pytest.mark.parametrize("path", PATHS)
+def test_hydrogen_full_size_short_run(path):
     # dim 128000, CF8:11, m 30: the benchmark's launch configuration.  The
     # table's dt = 0.05 puts dt*||H|| near 1e4, where the m = 30 Krylov step is
     # not converged and the result moves by 1e-4 under 1e-16 input noise (on
@@ -200,16 +212,17 @@ def test_hydrogen_full_size_short_run():
     nsteps = 6
     t0 = 40.0                     # inside the pulse
     dt = 0.001
-    out, st = run_gpu(p.H0, p.Hk, p.drives, p.psi0, t0, dt, nsteps, p.scheme, p.m)
+    out, st = run_gpu(p.H0, p.Hk, p.drives, p.psi0, t0, dt, nsteps, p.scheme, p.m, path)
     ref = O.propagate(p.H0, p.Hk, p.drives, p.psi0, t0, dt, nsteps, p.scheme, m=p.m)
     assert rel(out, ref) < PROP_TOL
     assert st["matvecs"] == nsteps * 11 * p.m
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("L,nsteps", [(10, 40), (14, 4)])
-def test_heisenberg_runs(L, nsteps):
+def test_heisenberg_runs(L, nsteps, path):
     p = I.config_heisenberg(L=L)
-    out, st = run_gpu(p.H0, p.Hk, p.drives, p.psi0, 0.0, p.dt, nsteps, p.scheme, p.m)
+    out, st = run_gpu(p.H0, p.Hk, p.drives, p.psi0, 0.0, p.dt, nsteps, p.scheme, p.m, path)
     ref = O.propagate(p.H0, p.Hk, p.drives, p.psi0, 0.0, p.dt, nsteps, p.scheme, m=p.m)
     assert rel(out, ref) < PROP_TOL
 
@@ -217,54 +230,60 @@ def test_heisenberg_runs(L, nsteps):
 # --------------------------------------------------------------------------
 # edge cases
 # --------------------------------------------------------------------------
-def test_two_level_breakdown_and_closed_form():
+@pytest.mark.parametrize("path", PATHS)
+def test_two_level_breakdown_and_closed_form(path):
     Delta, V, w = 0.5, 0.5, 1.0
     H0, Hk, drives = I.two_level(Delta, V, w)
     psi0 = np.array([1.0, 0.0], dtype=complex)
     T = 2 * math.pi
-    out, st = run_gpu(H0, Hk, drives, psi0, 0.0, T / 200, 200, "CF6:5Opt", 16)
+    out, st = run_gpu(H0, Hk, drives, psi0, 0.0, T / 200, 200, "CF6:5Opt", 16, path)
     ref = O.propagate(H0, Hk, drives, psi0, 0.0, T / 200, 200, "CF6:5Opt", m=16)
     assert rel(out, ref) < PROP_TOL
     assert st["min_m_eff"] == 2
 
 
-def test_zero_state_stays_zero():
+@pytest.mark.parametrize("path", PATHS)
+def test_zero_state_stays_zero(path):
     p = I.config_ising(L=6)
-    out, st = run_gpu(p.H0, p.Hk, p.drives, np.zeros(64, complex), 0.0, 0.01, 3, "CF4:2", 8)
+    out, st = run_gpu(p.H0, p.Hk, p.drives, np.zeros(64, complex), 0.0, 0.01, 3, "CF4:2", 8,
+                      path)
     assert np.all(out == 0)
 
 
-def test_eigenvector_start():
+@pytest.mark.parametrize("path", PATHS)
+def test_eigenvector_start(path):
     H0 = I.diagonal(np.linspace(-1, 1, 32))
     H1 = I.diagonal(np.zeros(32))
     drives = [{"kind": "cos", "A": 1.0, "omega": 1.0}]
     psi0 = np.zeros(32, complex)
     psi0[5] = 0.6 - 0.8j
-    out, st = run_gpu(H0, [H1], drives, psi0, 0.0, 0.1, 5, "CF4:3Opt", 12)
+    out, st = run_gpu(H0, [H1], drives, psi0, 0.0, 0.1, 5, "CF4:3Opt", 12, path)
     lam = np.linspace(-1, 1, 32)[5]
     assert abs(out[5] - psi0[5] * np.exp(-0.5j * lam)) < 1e-14
     assert st["min_m_eff"] == 1
 
 
-def test_m_larger_than_dim_and_m_one():
+@pytest.mark.parametrize("path", PATHS)
+def test_m_larger_than_dim_and_m_one(path):
     rng = np.random.default_rng(3)
     H0 = I.random_hermitian(12, rng)
     H1 = I.random_hermitian(12, rng)
     drives = [{"kind": "cos", "A": 1.0, "omega": 2.0}]
     psi0 = I.random_state(12, rng)
     for m in (1, 40):
-        out, st = run_gpu(H0, [H1], drives, psi0, 0.0, 0.02, 5, "CF4:2", m)
+        out, st = run_gpu(H0, [H1], drives, psi0, 0.0, 0.02, 5, "CF4:2", m, path)
         ref = O.propagate(H0, [H1], drives, psi0, 0.0, 0.02, 5, "CF4:2", m=m)
         assert rel(out, ref) < PROP_TOL
 
 
-def test_negative_dt_and_nsteps_zero():
+@pytest.mark.parametrize("path", PATHS)
+def test_negative_dt_and_nsteps_zero(path):
     rng = np.random.default_rng(4)
     H0 = I.random_hermitian(16, rng)
     H1 = I.random_hermitian(16, rng)
     drives = [{"kind": "cos", "A": 1.0, "omega": 2.0}]
     psi0 = I.random_state(16, rng)
-    with B.Propagator(H0, [H1], drives) as P:
+    with B.Propagator(H0, [H1], drives, path=path) as P:
         psi = dev(psi0)
         P.propagate(psi, 0.0, 0.1, 0, "CF6:5Opt", 16)
         assert np.array_equal(host(psi), psi0)
@@ -273,14 +292,15 @@ def test_negative_dt_and_nsteps_zero():
         assert rel(host(psi), psi0) < 1e-11
 
 
-def test_piecewise_constant_drive():
+@pytest.mark.parametrize("path", PATHS)
+def test_piecewise_constant_drive(path):
     rng = np.random.default_rng(9)
     H0 = I.random_hermitian(40, rng, density=0.2)
     H1 = I.random_hermitian(40, rng, density=0.2)
     edges = np.linspace(0.0, 1.0, 11)
     drives = [{"kind": "pwc", "t_edges": edges, "u": rng.uniform(-1, 1, 10)}]
     psi0 = I.random_state(40, rng)
-    out, _ = run_gpu(H0, [H1], drives, psi0, 0.0, 0.01, 100, "CF6:5Opt", 14)
+    out, _ = run_gpu(H0, [H1], drives, psi0, 0.0, 0.01, 100, "CF6:5Opt", 14, path)
     ref = O.propagate(H0, [H1], drives, psi0, 0.0, 0.01, 100, "CF6:5Opt", m=14)
     assert rel(out, ref) < PROP_TOL
 
