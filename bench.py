@@ -164,6 +164,10 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     log(f"path {path}: {kernel} {stp['timed_launches']} launches, avg {avg_ms * 1e3:.2f} us, "
         f"{bytes_per_launch / 1e6:.2f} MB algorithmic -> {achieved:.0f} GB/s")
+    seg = [a - b for a, b in zip(stp["segment_us"], st1["segment_us"])]
+    if path != "multi":
+        log("persistent segments (block 0, us per step): spmv %.1f, reduce/barrier %.1f, "
+            "small exp %.1f, recombination %.1f" % tuple(x / K for x in seg))
 
     # state error over the timed window: reference at dt/4 with m = 40
     state_error = None

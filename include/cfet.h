@@ -138,8 +138,11 @@ typedef struct {
                                 2 single-workgroup, 3 cooperative */
   int32_t status;            /* latched device status (CFET_OK or code) */
   double last_norm;          /* ||psi|| after the last exponential */
-  int64_t timed_launches;    /* SpMV launches timed with events (cfet_profile) */
+  int64_t timed_launches;    /* launches timed with events (cfet_profile) */
   double timed_ms;           /* their summed event-measured duration */
+  double segment_us[4];      /* persistent paths with cfet_profile on: time of block 0 in
+                                SpMV phases, reductions/barriers, small exponentials,
+                                recombinations (microseconds, cumulative) */
 } cfet_stats_t;
 
 /* Build a context for H(t) = H0 + sum_k f_k(t) Hk[k], k < nterms

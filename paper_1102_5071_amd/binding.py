@@ -50,7 +50,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("n", c_int64), ("nnz_stored", c_int64), ("exponentials", c_int64),
                 ("matvecs", c_int64), ("min_m_eff", c_int32), ("breakdowns", c_int32),
                 ("path", c_int32), ("status", c_int32), ("last_norm", c_double),
-                ("timed_launches", c_int64), ("timed_ms", c_double)]
+                ("timed_launches", c_int64), ("timed_ms", c_double),
+                ("segment_us", c_double * 4)]
 
 
 _LIB = None
@@ -220,7 +221,9 @@ class Propagator:
     def stats(self) -> dict:
         st = _Stats()
         _check(load().cfet_stats(self._ctx, ctypes.byref(st)), self._ctx)
-        return {f[0]: getattr(st, f[0]) for f in _Stats._fields_}
+        out = {f[0]: getattr(st, f[0]) for f in _Stats._fields_}
+        out["segment_us"] = list(out["segment_us"])
+        return out
 
     def profile(self, enable: bool, max_launches: int = 65536):
         _check(load().cfet_profile(self._ctx, 1 if enable else 0, int(max_launches)), self._ctx)

@@ -457,6 +457,7 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
   pa.fault = c->d_fault;
   pa.stats = c->stats;
   pa.spin_limit = c->spin_limit;
+  pa.timing = c->profiling ? 1 : 0;
   const bool timed = c->profiling && c->events.used < c->events.cap;
   if (timed) (void)hipEventRecord(c->events.begin[c->events.used], st);
   e = cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop, path == 2,
@@ -677,7 +678,8 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
   if (e == hipSuccess) e = hipMalloc(&c->S, sizeof(LzScalars));
   if (e == hipSuccess) e = hipMalloc(&c->stats, sizeof(DevStats));
   if (e == hipSuccess) e = hipHostMalloc(&c->stats_host, sizeof(DevStats));
-  if (e == hipSuccess) e = hipMalloc(&c->d_bar, sizeof(unsigned long long));
+  if (e == hipSuccess)
+    e = hipMalloc(&c->d_bar, cfet::persistent_barrier_words() * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(&c->d_fault, sizeof(int));
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->wts_copied, hipEventDisableTiming);
   if (e == hipSuccess)
@@ -688,12 +690,12 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     if (khz <= 0) khz = 100000;
     c->spin_limit = (long long)khz * 1000LL * 10LL;  // 10 s
   }
-  c->preset_single = need_csr ? cfet::persistent_choose_preset(c->max_row, n) : -1;
+  c->preset_single = need_csr ? cfet::persistent_choose_preset(c->max_row, n, true) : -1;
   if (e == hipSuccess && c->num_cus > 0 && need_csr) {
     // cooperative grid: one block per CU, but at least ~128 rows per block
     const int64_t nbw = std::max<int64_t>(1, std::min<int64_t>(c->num_cus, (n + 127) / 128));
     const int64_t rows = (n + nbw - 1) / nbw;
-    c->preset_coop = cfet::persistent_choose_preset(c->max_row, rows);
+    c->preset_coop = cfet::persistent_choose_preset(c->max_row, rows, false);
     if (c->preset_coop >= 0) {
       int maxb = 0;
       e = cfet::persistent_max_blocks(c->preset_coop, nterms, &maxb);
@@ -911,6 +913,13 @@ int cfet_stats(cfet_ctx* c, cfet_stats_t* s) {
   harvest_events(c);
   s->timed_launches = c->timed_launches;
   s->timed_ms = c->timed_ms;
+  {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess ||
+        khz <= 0)
+      khz = 100000;
+    for (int i = 0; i < 4; ++i) s->segment_us[i] = double(d.seg[i]) * 1000.0 / double(khz);
+  }
   if (d.status != CFET_OK) {
     const int32_t ok = CFET_OK;
     e = hipMemcpy(reinterpret_cast<char*>(c->stats) + offsetof(DevStats, status), &ok,

@@ -59,6 +59,8 @@ struct DevStats {
   int32_t status;
   int32_t pad;
   double last_norm2;
+  long long seg[4];  // persistent kernels with timing on: wall-clock ticks of block 0 in
+                     // SpMV phases, reductions/barriers, small exponentials, recombinations
 };
 
 // Term weights of one exponential: w[0] multiplies H0, w[1+k] multiplies H_k.
@@ -147,17 +149,19 @@ struct PersistArgs {
   double2* basis;           // basis vector j >= 1 at basis + (j-1)*n
   double2* zbuf;            // 2 * n: H u_k of the last two Lanczos steps
   double* part;             // 2 parities x 2 sums x gridDim partial sums
-  unsigned long long* bar;  // barrier arrival counter (reset before the launch)
+  unsigned long long* bar;  // barrier counters (persistent_barrier_words(), reset per launch)
   int* fault;               // set when a barrier wait times out
   DevStats* stats;
   long long spin_limit;     // barrier wait limit in wall-clock ticks
+  int timing;               // accumulate per-segment wall-clock time (block 0)
 };
 
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,
                              hipStream_t st);
 hipError_t persistent_max_blocks(int preset, int nterms, int* out);
-int persistent_rows_per_block(int preset);
-int persistent_choose_preset(int max_row, int64_t min_rows_per_block);
+int persistent_rows_per_block(int preset, bool single);
+int persistent_barrier_words();
+int persistent_choose_preset(int max_row, int64_t min_rows_per_block, bool single);
 
 hipError_t launch_tridiag_expm(const double* alpha, const double* beta, int k, double dt,
                                double2* c, int32_t* status, hipStream_t st);

@@ -333,6 +333,7 @@ __global__ void k_stats_init(DevStats* st) {
   st->breakdowns = 0;
   st->status = CFET_OK;
   st->last_norm2 = 0.0;
+  for (int i = 0; i < 4; ++i) st->seg[i] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_final_norm(const double* __restrict__ part, int np,

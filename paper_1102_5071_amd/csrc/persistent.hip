@@ -46,13 +46,34 @@ namespace {
 struct Preset {
   int G, P, Q;
 };
-constexpr Preset kPresets[] = {{1, 2, 12}, {1, 1, 8}, {2, 2, 8}, {4, 1, 8}};
-constexpr int kNumPresets = sizeof(kPresets) / sizeof(kPresets[0]);
+// cooperative kernel (gathers prefetched into registers)
+constexpr Preset kCoopPresets[] = {{1, 1, 5}, {1, 1, 8}, {2, 1, 8}, {4, 1, 8}};
+// single-workgroup kernel (working vectors in LDS, n <= kSingleMaxRows)
+constexpr Preset kSinglePresets[] = {{1, 2, 12}, {2, 2, 8}, {4, 2, 8}};
+constexpr int kNumCoopPresets = sizeof(kCoopPresets) / sizeof(kCoopPresets[0]);
+constexpr int kNumSinglePresets = sizeof(kSinglePresets) / sizeof(kSinglePresets[0]);
+constexpr int kSingleMaxRows = 1024;
 
+// One DPP step of the wavefront sum: v + (v moved by the DPP pattern), rows
+// outside row_mask add 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return v + __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes in a fixed order with DPP moves (pair swap, quad
+// swap, half-row and row mirrors, then row broadcasts 15 and 31); the total
+// lands in lane 63 and is broadcast from there.
 __device__ __forceinline__ double p_wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return lane_read(v, 63);
 }
 
 // Block sum; every thread receives the value thread 0 formed.
@@ -108,6 +129,12 @@ __device__ __forceinline__ void dstore(double* p, double v) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Barrier state: word 0 = top arrival counter, words kBarGroupStride*(1+g) =
+// arrival counter of group g (blocks b with b % groups == g), one 128-byte
+// line each, so arrivals of different groups do not serialise on one address.
+constexpr int kBarGroups = 16;
+constexpr int kBarGroupStride = 16;  // 64-bit words per 128-byte line
+
 __device__ bool grid_barrier(unsigned long long* bar, int* fault, unsigned long long& epoch,
                              long long limit, int* s_ok) {
   // all memory operations of this wave (device-scope stores included) are done
@@ -116,25 +143,30 @@ __device__ bool grid_barrier(unsigned long long* bar, int* fault, unsigned long 
   if (threadIdx.x == 0) {
     int ok = 1;
     epoch += 1ull;
-    const unsigned long long target = epoch * (unsigned long long)gridDim.x;
-    unsigned long long v =
-        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1ull;
-    if (v < target) {
-      const long long t0 = wall_clock64();
-      for (;;) {
-        v = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (v >= target) break;
-        if (__hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          ok = 0;
-          break;
-        }
-        if (wall_clock64() - t0 > limit) {
-          __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+    const int nb = gridDim.x;
+    const int ng = nb < kBarGroups ? nb : kBarGroups;
+    const int g = blockIdx.x % ng;
+    const unsigned long long members = (unsigned long long)((nb - 1 - g) / ng + 1);
+    const unsigned long long gv =
+        __hip_atomic_fetch_add(bar + kBarGroupStride * (1 + g), 1ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT) + 1ull;
+    if (gv == epoch * members)  // last of its group: arrive at the top level
+      __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long target = epoch * (unsigned long long)ng;
+    const long long t0 = wall_clock64();
+    for (;;) {
+      const unsigned long long v = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v >= target) break;
+      if (__hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 0;
+        break;
       }
+      if (wall_clock64() - t0 > limit) {
+        __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
     }
     *s_ok = ok;
   }
@@ -216,10 +248,30 @@ __device__ __forceinline__ bool all_reduce2(double& a, double& b, const PersistA
   return true;
 }
 
+// Segment timer (block 0, thread 0, only when A.timing is set).
+struct SegTimer {
+  long long last;
+  bool on;
+  __device__ void start(bool enable) {
+    on = enable && blockIdx.x == 0 && threadIdx.x == 0;
+    if (on) last = wall_clock64();
+  }
+  __device__ void lap(DevStats* st, int seg) {
+    if (!on) return;
+    const long long t = wall_clock64();
+    st->seg[seg] += t - last;
+    last = t;
+  }
+};
+
 template <int G, int PMAX, int QMAX, int NT, bool SINGLE>
 __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
   constexpr int BLOCK = kPersistBlock;
   __shared__ Shared sh;
+  // single workgroup: u_k ring (k mod 3) and z_k ring (k mod 2) in LDS
+  constexpr int LN = SINGLE ? kSingleMaxRows : 1;
+  __shared__ double2 lu[3][LN];
+  __shared__ double2 lz[2][LN];
   const int nb = gridDim.x;
   const int64_t n = A.n;
   const int64_t per = (n + nb - 1) / nb;
@@ -235,7 +287,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
   double2* __restrict__ psi = A.psi;
   // u_0 = psi, u_k (k >= 1) in the basis storage; z_k alternates between two buffers
   auto U = [&](int k) -> double2* {
-    return (k == 0) ? psi : A.basis + (size_t)(k - 1) * (size_t)n;
+    return (k <= 0) ? psi : A.basis + (size_t)(k - 1) * (size_t)n;
   };
   auto Zb = [&](int k) -> double2* { return A.zbuf + (size_t)(k & 1) * (size_t)n; };
 
@@ -258,7 +310,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
     for (int q = 0; q < QMAX; ++q) {
       const int64_t e = beg + lane + (int64_t)q * G;
       if (e < end) {
-        ccol[p][q] = A.colt[e];
+        ccol[p][q] = A.colt[e] ;
         cval[p][q] = A.val[e];
       } else {
         ccol[p][q] = 0u;
@@ -273,12 +325,35 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
 
   // own-row state (lane 0 of each group): u_{k-1}, u_{k-2}, z_{k-1}
   double2 u1[PMAX], u2[PMAX], zp[PMAX];
+  // raw values gathered for the register-held entries of the current phase
+  double2 g1[PMAX][QMAX], g2[PMAX][QMAX], gz[PMAX][QMAX];
 #pragma unroll
   for (int p = 0; p < PMAX; ++p) {
     u1[p] = u2[p] = zp[p] = make_double2(0.0, 0.0);
     if (lane == 0 && rowp[p] >= 0) u1[p] = vload<SINGLE>(psi + rowp[p]);  // becomes u_0
   }
+  // issue the gathers of phase k: u_{k-1}, z_{k-1}, u_{k-2} (phase 0: psi only)
+  auto gather = [&](int k) {
+    if (SINGLE) return;
+    const double2* __restrict__ a1 = U(k - 1);
+    const double2* __restrict__ az = Zb(k - 1);
+    const double2* __restrict__ a2 = U(k - 2);
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        if (rowp[p] >= 0 && q < cnt[p]) {
+          const int64_t c = ccol[p][q] & kColMask;
+          g1[p][q] = vload<SINGLE>(a1 + c);
+          if (k >= 1) gz[p][q] = vload<SINGLE>(az + c);
+          if (k >= 2) g2[p][q] = vload<SINGLE>(a2 + c);
+        }
+      }
+    }
+  };
 
+  SegTimer tm;
+  tm.start(A.timing != 0);
   for (int64_t step = 0; ok && step < A.nsteps; ++step) {
     for (int i = A.s - 1; ok && i >= 0; --i) {
       if (threadIdx.x < nt1)
@@ -289,45 +364,100 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
       int meff = m;
       bool zero = false;
       double nu0 = 0.0;
-      // recurrence coefficients of the phase (uniform)
       double c1 = 0.0, c2 = 0.0, c3 = 0.0;
-      for (int k = 0; k < m; ++k) {
-        const double2* __restrict__ zprev = Zb(k + 1);   // z_{k-1}
-        const double2* __restrict__ um1 = (k >= 1) ? U(k - 1) : psi;
-        const double2* __restrict__ um2 = (k >= 2) ? U(k - 2) : psi;
+      double S1 = 0.0, S2 = 0.0;  // block sums of <u, z> and ||u||^2 of the last phase
+      if (SINGLE) {
+#pragma unroll
+        for (int p = 0; p < PMAX; ++p)
+          if (lane == 0 && rowp[p] >= 0) lu[0][rowp[p]] = u1[p];
+        __syncthreads();
+      }
+      gather(0);
+      for (int k = 0; k <= m; ++k) {
+        if (k >= 1) {
+          tm.lap(A.stats, 1);
+          // ---- reduction of phase k-1; the gathers of phase k fly meanwhile
+          if (!SINGLE) {
+            const double* P = A.part + (size_t)((pc - 1) & 1) * 2 * gridDim.x;
+            double sa = 0.0, sb = 0.0;
+            for (int t = threadIdx.x; t < (int)gridDim.x; t += blockDim.x) {
+              sa += dload(P + 2 * t);
+              sb += dload(P + 2 * t + 1);
+            }
+            S1 = sa;
+            S2 = sb;
+          }
+          if (k < m) gather(k);
+          if (!SINGLE) p_block_sum2(S1, S2, sh.red);
+          const double nu = sqrt(S2);
+          if (k == 1) {
+            nu0 = nu;
+            if (nu == 0.0) {  // psi == 0 stays 0
+              zero = true;
+              break;
+            }
+          } else {
+            // beta_{k-2} = nu_{k-1}: early-stop rule of the recurrence
+            double sc = 0.0;
+            for (int t = 0; t < k - 2; ++t) sc = fmax(sc, fabs(sh.alpha[t]) + sh.beta[t]);
+            sc = fmax(sc, fabs(sh.alpha[k - 2]) + nu);
+            __syncthreads();
+            if (threadIdx.x == 0) sh.beta[k - 2] = nu;
+            __syncthreads();
+            if (nu <= kBreakdownRel * sc) {
+              meff = k - 1;
+              break;
+            }
+          }
+          const double inv = 1.0 / nu;
+          const double alpha = S1 * inv * inv;
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            sh.alpha[k - 1] = alpha;
+            sh.inv[k - 1] = inv;
+          }
+          __syncthreads();
+          if (k == m) break;
+          // u_k = (z_{k-1} - alpha_{k-1} u_{k-1})/nu_{k-1} - (nu_{k-1}/nu_{k-2}) u_{k-2}
+          c1 = inv;
+          c2 = alpha * inv;
+          c3 = (k >= 2) ? nu * sh.inv[k - 2] : 0.0;
+        }
+        // ---- phase k: u_k on own rows, z_k = H_w u_k, partial sums
         double2* __restrict__ uk = U(k);
         double2* __restrict__ zk = Zb(k);
-        // ---- own rows: u_k (k >= 1; u_0 = psi is already stored)
+        const double2* __restrict__ um1 = U(k - 1);
+        const double2* __restrict__ zm1 = Zb(k - 1);
+        const double2* __restrict__ um2 = U(k - 2);
         double s_uz = 0.0, s_uu = 0.0;
-        double2 ucur[PMAX];
 #pragma unroll
         for (int p = 0; p < PMAX; ++p) {
-          ucur[p] = u1[p];
+          double2 ucur = u1[p];
           if (k >= 1 && lane == 0 && rowp[p] >= 0) {
-            ucur[p] = form_u(zp[p], u1[p], u2[p], c1, c2, (k >= 2) ? c3 : 0.0);
-            vstore<SINGLE>(uk + rowp[p], ucur[p]);
+            ucur = form_u(zp[p], u1[p], u2[p], c1, c2, c3);
+            vstore<SINGLE>(uk + rowp[p], ucur);
+            if (SINGLE) lu[k % 3][rowp[p]] = ucur;
           }
-        }
-        // ---- z_k = H_w u_k, u_k gathered (formed on the fly for k >= 1)
-#pragma unroll
-        for (int p = 0; p < PMAX; ++p) {
           double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
           if (rowp[p] >= 0) {
 #pragma unroll
-            for (int q = 0; q < QMAX + 1; ++q) {
-              // q < QMAX: register-held entries; q == QMAX: tail loop from memory
-              const int64_t tb = (q == QMAX) ? tail_beg[p] : 0;
-              const int64_t te = (q == QMAX) ? tail_end[p] : ((q < cnt[p]) ? 1 : 0);
-              for (int64_t e = tb; e < te; e += G) {
-                const uint32_t ct = (q == QMAX) ? A.colt[e] : ccol[p][q < QMAX ? q : 0];
-                const double2 v = (q == QMAX) ? A.val[e] : cval[p][q < QMAX ? q : 0];
-                const int64_t c = ct & kColMask;
-                double2 xv = vload<SINGLE>(um1 + c);
-                if (k >= 1) {
-                  const double2 zc = vload<SINGLE>(zprev + c);
-                  const double2 u2c = (k >= 2) ? vload<SINGLE>(um2 + c) : make_double2(0.0, 0.0);
-                  xv = form_u(zc, xv, u2c, c1, c2, (k >= 2) ? c3 : 0.0);
+            for (int q = 0; q < QMAX; ++q) {
+              if (q < cnt[p]) {
+                const uint32_t ct = ccol[p][q];
+                const double2 v = cval[p][q];
+                double2 xg1, xgz, xg2;
+                if (SINGLE) {
+                  const int c = (int)(ct & kColMask);
+                  xg1 = lu[(k + 2) % 3][c];                        // u_{k-1} (u_0 at k = 0)
+                  xgz = (k >= 1) ? lz[(k + 1) & 1][c] : make_double2(0.0, 0.0);
+                  xg2 = (k >= 2) ? lu[(k + 1) % 3][c] : make_double2(0.0, 0.0);
+                  if (k == 0) xg1 = lu[0][c];
+                } else {
+                  xg1 = g1[p][q];
+                  xgz = gz[p][q];
+                  xg2 = (k >= 2) ? g2[p][q] : make_double2(0.0, 0.0);
                 }
+                const double2 xv = (k >= 1) ? form_u(xgz, xg1, xg2, c1, c2, c3) : xg1;
                 const double pr = v.x * xv.x - v.y * xv.y;
                 const double pi = v.x * xv.y + v.y * xv.x;
                 if (NT == 1) {
@@ -337,6 +467,36 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
                   a0r += wt * pr;
                   a0i += wt * pi;
                 }
+              }
+            }
+            for (int64_t e = tail_beg[p]; e < tail_end[p]; e += G) {
+              const uint32_t ct = A.colt[e];
+              const double2 v = A.val[e];
+              const int64_t c = ct & kColMask;
+              double2 xv;
+              if (SINGLE) {
+                xv = (k == 0) ? lu[0][c] : lu[(k + 2) % 3][c];
+                if (k >= 1) {
+                  const double2 zc = lz[(k + 1) & 1][c];
+                  const double2 u2c = (k >= 2) ? lu[(k + 1) % 3][c] : make_double2(0.0, 0.0);
+                  xv = form_u(zc, xv, u2c, c1, c2, c3);
+                }
+              } else {
+                xv = vload<SINGLE>(um1 + c);
+                if (k >= 1) {
+                  const double2 zc = vload<SINGLE>(zm1 + c);
+                  const double2 u2c = (k >= 2) ? vload<SINGLE>(um2 + c) : make_double2(0.0, 0.0);
+                  xv = form_u(zc, xv, u2c, c1, c2, c3);
+                }
+              }
+              const double pr = v.x * xv.x - v.y * xv.y;
+              const double pi = v.x * xv.y + v.y * xv.x;
+              if (NT == 1) {
+                if (ct >> kTermShift) { a1r += pr; a1i += pi; } else { a0r += pr; a0i += pi; }
+              } else {
+                const double wt = sh.w[ct >> kTermShift];
+                a0r += wt * pr;
+                a0i += wt * pi;
               }
             }
           }
@@ -355,48 +515,32 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           }
           if (lane == 0 && rowp[p] >= 0) {
             const double2 zv = make_double2(yr, yi);
-            if (k + 1 < m) vstore<SINGLE>(zk + rowp[p], zv);
-            s_uz += ucur[p].x * zv.x + ucur[p].y * zv.y;
-            s_uu += ucur[p].x * ucur[p].x + ucur[p].y * ucur[p].y;
+            if (SINGLE) lz[k & 1][rowp[p]] = zv;
+            else if (k + 1 < m) vstore<SINGLE>(zk + rowp[p], zv);
+            s_uz += ucur.x * zv.x + ucur.y * zv.y;
+            s_uu += ucur.x * ucur.x + ucur.y * ucur.y;
             u2[p] = u1[p];
-            u1[p] = ucur[p];
+            u1[p] = ucur;
             zp[p] = zv;
           }
         }
-        ok = all_reduce2<SINGLE>(s_uz, s_uu, A, sh, epoch, pc);
-        if (!ok) break;
-        const double nu = sqrt(s_uu);
-        if (k == 0) {
-          nu0 = nu;
-          if (nu == 0.0) {  // psi == 0 stays 0
-            zero = true;
-            break;
-          }
+        tm.lap(A.stats, 0);
+        p_block_sum2(s_uz, s_uu, sh.red);
+        if (SINGLE) {
+          S1 = s_uz;
+          S2 = s_uu;
         } else {
-          // beta_{k-1} = nu_k: the early-stop rule of the recurrence
-          double sc = 0.0;
-          for (int t = 0; t < k - 1; ++t) sc = fmax(sc, fabs(sh.alpha[t]) + sh.beta[t]);
-          sc = fmax(sc, fabs(sh.alpha[k - 1]) + nu);
-          __syncthreads();
-          if (threadIdx.x == 0) sh.beta[k - 1] = nu;
-          __syncthreads();
-          if (nu <= kBreakdownRel * sc) {
-            meff = k;
+          double* P = A.part + (size_t)(pc & 1) * 2 * gridDim.x;
+          if (threadIdx.x == 0) {
+            dstore(P + 2 * blockIdx.x, s_uz);
+            dstore(P + 2 * blockIdx.x + 1, s_uu);
+          }
+          if (!grid_barrier(A.bar, A.fault, epoch, A.spin_limit, &sh.ok)) {
+            ok = false;
             break;
           }
+          pc += 1;
         }
-        const double inv = 1.0 / nu;
-        const double alpha = s_uz * inv * inv;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          sh.alpha[k] = alpha;
-          sh.inv[k] = inv;
-        }
-        __syncthreads();
-        // coefficients of u_{k+1} = (z_k - alpha_k u_k)/nu_k - (nu_k/nu_{k-1}) u_{k-1}
-        c1 = inv;
-        c2 = alpha * inv;
-        c3 = (k >= 1) ? nu * sh.inv[k - 1] : 0.0;
       }
       if (!ok) break;
       if (zero) {
@@ -405,10 +549,10 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           A.stats->breakdowns += 1;
           A.stats->min_m_eff = 0;
         }
-        // u1 already holds psi = 0; restore the own-row state and go on
         continue;
       }
       __syncthreads();
+      tm.lap(A.stats, 1);
       // ---- small exponential (wave 0; identical in every block)
       const double beta0 = nu0;
       if (threadIdx.x < 64) {
@@ -435,14 +579,14 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
         }
       }
       __syncthreads();
+      tm.lap(A.stats, 2);
       // ---- recombination psi = sum_k coef_k u_k on own rows
-      double dummy = 0.0, rp = 0.0;
 #pragma unroll
       for (int p = 0; p < PMAX; ++p) {
         if (lane == 0 && rowp[p] >= 0) {
           double accr = 0.0, acci = 0.0;
           for (int kk = 0; kk < meff; ++kk) {
-            const double2 v = vload<SINGLE>(U(kk) + rowp[p]);
+            const double2 v = (kk == 0) ? vload<SINGLE>(psi + rowp[p]) : vload<SINGLE>(U(kk) + rowp[p]);
             const double2 cf = sh.coef[kk];
             accr += cf.x * v.x - cf.y * v.y;
             acci += cf.x * v.y + cf.y * v.x;
@@ -450,13 +594,37 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           const double2 nv = make_double2(accr, acci);
           vstore<SINGLE>(psi + rowp[p], nv);
           u1[p] = nv;
-          rp += accr * accr + acci * acci;
         }
       }
       // the next exponential gathers psi: every block must have written it
-      ok = all_reduce2<SINGLE>(dummy, rp, A, sh, epoch, pc);
-      if (ok && blockIdx.x == 0 && threadIdx.x == 0) A.stats->last_norm2 = rp;
+      if (SINGLE) {
+        __syncthreads();
+      } else if (!grid_barrier(A.bar, A.fault, epoch, A.spin_limit, &sh.ok)) {
+        ok = false;
+      }
+      tm.lap(A.stats, 3);
     }
+  }
+  if (ok) {
+    // ||psi||^2 after the last exponential, for the statistics
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p)
+      if (lane == 0 && rowp[p] >= 0) s1 += u1[p].x * u1[p].x + u1[p].y * u1[p].y;
+    p_block_sum2(s0, s1, sh.red);
+    if (!SINGLE) {
+      double* P = A.part + (size_t)(pc & 1) * 2 * gridDim.x;
+      if (threadIdx.x == 0) dstore(P + 2 * blockIdx.x + 1, s1);
+      if (grid_barrier(A.bar, A.fault, epoch, A.spin_limit, &sh.ok)) {
+        double sb = 0.0;
+        for (int t = threadIdx.x; t < (int)gridDim.x; t += blockDim.x) sb += dload(P + 2 * t + 1);
+        p_block_sum2(s0, sb, sh.red);
+        s1 = sb;
+      } else {
+        ok = false;
+      }
+    }
+    if (ok && blockIdx.x == 0 && threadIdx.x == 0 && A.nsteps > 0) A.stats->last_norm2 = s1;
   }
   if (!ok && threadIdx.x == 0) {
     // a barrier timed out somewhere: latch a device error
@@ -466,8 +634,8 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
 }
 
 __global__ void k_persist_reset(unsigned long long* bar, int* fault) {
-  *bar = 0ull;
-  *fault = 0;
+  for (int i = threadIdx.x; i < kBarGroupStride * (1 + kBarGroups); i += blockDim.x) bar[i] = 0ull;
+  if (threadIdx.x == 0) *fault = 0;
 }
 
 template <int G, int P, int Q, bool SINGLE>
@@ -476,35 +644,54 @@ const void* pick_nt(int NT) {
                  : (const void*)&k_propagate<G, P, Q, 0, SINGLE>;
 }
 
-template <bool SINGLE>
-const void* pick_kernel(int preset, int NT) {
+const void* pick_coop(int preset, int NT) {
+#define CFET_CP(I) \
+  case I: return pick_nt<kCoopPresets[I].G, kCoopPresets[I].P, kCoopPresets[I].Q, false>(NT);
   switch (preset) {
-    case 0: return pick_nt<kPresets[0].G, kPresets[0].P, kPresets[0].Q, SINGLE>(NT);
-    case 1: return pick_nt<kPresets[1].G, kPresets[1].P, kPresets[1].Q, SINGLE>(NT);
-    case 2: return pick_nt<kPresets[2].G, kPresets[2].P, kPresets[2].Q, SINGLE>(NT);
-    case 3: return pick_nt<kPresets[3].G, kPresets[3].P, kPresets[3].Q, SINGLE>(NT);
+    CFET_CP(0)
+    CFET_CP(1)
+    CFET_CP(2)
+    CFET_CP(3)
     default: return nullptr;
   }
+#undef CFET_CP
+}
+
+const void* pick_single(int preset, int NT) {
+#define CFET_SP(I) \
+  case I: return pick_nt<kSinglePresets[I].G, kSinglePresets[I].P, kSinglePresets[I].Q, true>(NT);
+  switch (preset) {
+    CFET_SP(0)
+    CFET_SP(1)
+    CFET_SP(2)
+    default: return nullptr;
+  }
+#undef CFET_SP
 }
 
 }  // namespace
 
-int persistent_rows_per_block(int preset) {
-  if (preset < 0 || preset >= kNumPresets) return 0;
-  return kPresets[preset].P * (kPersistBlock / kPresets[preset].G);
+int persistent_rows_per_block(int preset, bool single) {
+  const Preset* t = single ? kSinglePresets : kCoopPresets;
+  const int np = single ? kNumSinglePresets : kNumCoopPresets;
+  if (preset < 0 || preset >= np) return 0;
+  const int rows = t[preset].P * (kPersistBlock / t[preset].G);
+  return single ? std::min(rows, kSingleMaxRows) : rows;
 }
 
 // Preset for a matrix: prefer one that holds the longest row in registers,
 // then the one holding the fewest entries per lane (register pressure), among
 // those whose block capacity is at least min_rows_per_block.
-int persistent_choose_preset(int max_row, int64_t min_rows_per_block) {
+int persistent_choose_preset(int max_row, int64_t min_rows_per_block, bool single) {
+  const Preset* t = single ? kSinglePresets : kCoopPresets;
+  const int np = single ? kNumSinglePresets : kNumCoopPresets;
   int best = -1;
   for (int pass = 0; pass < 2 && best < 0; ++pass) {
     int best_cost = 1 << 30;
-    for (int i = 0; i < kNumPresets; ++i) {
-      const Preset& q = kPresets[i];
+    for (int i = 0; i < np; ++i) {
+      const Preset& q = t[i];
       if (pass == 0 && q.G * q.Q < max_row) continue;
-      if (persistent_rows_per_block(i) < min_rows_per_block) continue;
+      if (persistent_rows_per_block(i, single) < min_rows_per_block) continue;
       const int cost = q.P * q.Q;
       if (cost < best_cost) {
         best_cost = cost;
@@ -517,14 +704,14 @@ int persistent_choose_preset(int max_row, int64_t min_rows_per_block) {
 
 const void* persistent_kernel(int preset, int nterms, bool single) {
   const int NT = (nterms == 1) ? 1 : 0;
-  return single ? pick_kernel<true>(preset, NT) : pick_kernel<false>(preset, NT);
+  return single ? pick_single(preset, NT) : pick_coop(preset, NT);
 }
 
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,
                              hipStream_t st) {
   const void* fn = persistent_kernel(preset, args.nterms, single);
   if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_persist_reset, dim3(1), dim3(1), 0, st, args.bar, args.fault);
+  hipLaunchKernelGGL(k_persist_reset, dim3(1), dim3(64), 0, st, args.bar, args.fault);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   PersistArgs a = args;
@@ -548,5 +735,7 @@ hipError_t persistent_max_blocks(int preset, int nterms, int* out) {
   *out = cus * per;
   return hipSuccess;
 }
+
+int persistent_barrier_words() { return kBarGroupStride * (1 + kBarGroups); }
 
 }  // namespace cfet

@@ -249,7 +249,27 @@ __device__ inline int tridiag_exp_e1_cheb(double a, double b, int k, double dt, 
   double cr = lds[0] * tp, ci = 0.0;
   double t = ax * tp + blo * from_lane_below(tp) + bhi * from_lane_above(tp);  // t_1
   ci += 2.0 * sgn * lds[1] * t;
-  for (int j = 2; j <= N; ++j) {
+  // four terms per iteration: j = 2 mod 4 at the top, so the phases (sgn i)^j
+  // are -1, -sgn i, +1, +sgn i; the four Bessel values are read together
+  int j = 2;
+  for (; j + 3 <= N; j += 4) {
+    const double J0 = lds[j], J1 = lds[j + 1], J2 = lds[j + 2], J3 = lds[j + 3];
+    double xt = ax * t + blo * from_lane_below(t) + bhi * from_lane_above(t);
+    double tn = 2.0 * xt - tp;
+    cr -= 2.0 * J0 * tn;
+    xt = ax * tn + blo * from_lane_below(tn) + bhi * from_lane_above(tn);
+    tp = 2.0 * xt - t;
+    ci -= sgn * 2.0 * J1 * tp;
+    xt = ax * tp + blo * from_lane_below(tp) + bhi * from_lane_above(tp);
+    t = 2.0 * xt - tn;
+    cr += 2.0 * J2 * t;
+    xt = ax * t + blo * from_lane_below(t) + bhi * from_lane_above(t);
+    tn = 2.0 * xt - tp;
+    ci += sgn * 2.0 * J3 * tn;
+    tp = t;
+    t = tn;
+  }
+  for (; j <= N; ++j) {
     const double xt = ax * t + blo * from_lane_below(t) + bhi * from_lane_above(t);
     const double tn = 2.0 * xt - tp;
     tp = t;
