@@ -93,28 +93,41 @@ __device__ double p_block_sum(double v, double* red) {
   return red[16];
 }
 
-// device-scope (agent) accesses of cross-block data
-template <bool SINGLE>
-__device__ __forceinline__ double2 vload(const double2* p) {
-  if (SINGLE) return *p;
-  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
-  const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const unsigned long long b =
-      __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
+// Device-scope accesses of cross-block vectors: one 16-byte buffer load or
+// store carrying the device-coherence cache policy, addressed as (base,
+// element index) so the buffer descriptor stays uniform.  The descriptor's
+// record count is the vector's byte size, so an index outside [0, n) reads 0
+// and drops the write instead of touching other memory.
+constexpr int kBufWord3 = 0x00020000;  // descriptor word 3 on gfx9: 32-bit data format
+constexpr int kCpolDevice = 16;        // cache-policy operand: device scope
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const double2* base, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double2*>(base), (short)0, (int)(n * 16),
+                                           kBufWord3);
 }
 
 template <bool SINGLE>
-__device__ __forceinline__ void vstore(double2* p, double2 v) {
+__device__ __forceinline__ double2 vld(const double2* base, int64_t i, int64_t n) {
+  if (SINGLE) return base[i];
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(vec_rsrc(base, n), (int)(i * 16), 0,
+                                                       kCpolDevice);
+  return make_double2(__hiloint2double((int)v[1], (int)v[0]),
+                      __hiloint2double((int)v[3], (int)v[2]));
+}
+
+template <bool SINGLE>
+__device__ __forceinline__ void vst(double2* base, int64_t i, int64_t n, double2 x) {
   if (SINGLE) {
-    *p = v;
+    base[i] = x;
     return;
   }
-  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
-  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 v;
+  v[0] = (unsigned)__double2loint(x.x);
+  v[1] = (unsigned)__double2hiint(x.x);
+  v[2] = (unsigned)__double2loint(x.y);
+  v[3] = (unsigned)__double2hiint(x.y);
+  __builtin_amdgcn_raw_buffer_store_b128(v, vec_rsrc(base, n), (int)(i * 16), 0, kCpolDevice);
 }
 
 __device__ __forceinline__ double dload(const double* p) {
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
 #pragma unroll
   for (int p = 0; p < PMAX; ++p) {
     u1[p] = u2[p] = zp[p] = make_double2(0.0, 0.0);
-    if (lane == 0 && rowp[p] >= 0) u1[p] = vload<SINGLE>(psi + rowp[p]);  // becomes u_0
+    if (lane == 0 && rowp[p] >= 0) u1[p] = vld<SINGLE>(psi, rowp[p], n);  // becomes u_0
   }
   // issue the gathers of phase k: u_{k-1}, z_{k-1}, u_{k-2} (phase 0: psi only)
   auto gather = [&](int k) {
@@ -344,9 +357,9 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
       for (int q = 0; q < QMAX; ++q) {
         if (rowp[p] >= 0 && q < cnt[p]) {
           const int64_t c = ccol[p][q] & kColMask;
-          g1[p][q] = vload<SINGLE>(a1 + c);
-          if (k >= 1) gz[p][q] = vload<SINGLE>(az + c);
-          if (k >= 2) g2[p][q] = vload<SINGLE>(a2 + c);
+          g1[p][q] = vld<SINGLE>(a1, c, n);
+          if (k >= 1) gz[p][q] = vld<SINGLE>(az, c, n);
+          if (k >= 2) g2[p][q] = vld<SINGLE>(a2, c, n);
         }
       }
     }
@@ -435,7 +448,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           double2 ucur = u1[p];
           if (k >= 1 && lane == 0 && rowp[p] >= 0) {
             ucur = form_u(zp[p], u1[p], u2[p], c1, c2, c3);
-            vstore<SINGLE>(uk + rowp[p], ucur);
+            vst<SINGLE>(uk, rowp[p], n, ucur);
             if (SINGLE) lu[k % 3][rowp[p]] = ucur;
           }
           double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
@@ -482,10 +495,10 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
                   xv = form_u(zc, xv, u2c, c1, c2, c3);
                 }
               } else {
-                xv = vload<SINGLE>(um1 + c);
+                xv = vld<SINGLE>(um1, c, n);
                 if (k >= 1) {
-                  const double2 zc = vload<SINGLE>(zm1 + c);
-                  const double2 u2c = (k >= 2) ? vload<SINGLE>(um2 + c) : make_double2(0.0, 0.0);
+                  const double2 zc = vld<SINGLE>(zm1, c, n);
+                  const double2 u2c = (k >= 2) ? vld<SINGLE>(um2, c, n) : make_double2(0.0, 0.0);
                   xv = form_u(zc, xv, u2c, c1, c2, c3);
                 }
               }
@@ -516,7 +529,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           if (lane == 0 && rowp[p] >= 0) {
             const double2 zv = make_double2(yr, yi);
             if (SINGLE) lz[k & 1][rowp[p]] = zv;
-            else if (k + 1 < m) vstore<SINGLE>(zk + rowp[p], zv);
+            else if (k + 1 < m) vst<SINGLE>(zk, rowp[p], n, zv);
             s_uz += ucur.x * zv.x + ucur.y * zv.y;
             s_uu += ucur.x * ucur.x + ucur.y * ucur.y;
             u2[p] = u1[p];
@@ -586,13 +599,13 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
         if (lane == 0 && rowp[p] >= 0) {
           double accr = 0.0, acci = 0.0;
           for (int kk = 0; kk < meff; ++kk) {
-            const double2 v = (kk == 0) ? vload<SINGLE>(psi + rowp[p]) : vload<SINGLE>(U(kk) + rowp[p]);
+            const double2 v = vld<SINGLE>(U(kk), rowp[p], n);
             const double2 cf = sh.coef[kk];
             accr += cf.x * v.x - cf.y * v.y;
             acci += cf.x * v.y + cf.y * v.x;
           }
           const double2 nv = make_double2(accr, acci);
-          vstore<SINGLE>(psi + rowp[p], nv);
+          vst<SINGLE>(psi, rowp[p], n, nv);
           u1[p] = nv;
         }
       }
