@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+DEFAULT_CHUNK = {"hydrogen": 10, "ising": 50, "heisenberg": 1}
 
 
 def log(msg):
@@ -48,6 +50,53 @@ def exponential_algorithmic_bytes(dim, nnz_total, ncsr, m):
             + (m + 1) * 16 * dim)
 
 
+def measured_traffic(kernel, key, chunk):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/<kernel>__<key>.txt (FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    kernel of known size), or None when there is none, when it was taken on
+    other library sources (digest mismatch) or with another launch size."""
+    from paper_1102_5071_amd.build import source_digest
+    path = os.path.join(PROFILES, f"{kernel}__{key}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    try:
+        if fields.get("source_digest") != source_digest():
+            return None
+        if int(fields.get("steps_per_launch", "0")) != chunk:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes, reps):
+    """Plain device copy of a known size (torch elementwise kernel), for the
+    scale factor of the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 8, "bytes_written": n * 8,
+                                           "launches": reps + 1, "avg_ms": round(ms, 4),
+                                           "GB/s": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}}),
+          flush=True)
+
+
 def make_workload(name, L):
     from paper_1102_5071_amd import inputs as I
     if name == "hydrogen":
@@ -55,15 +104,18 @@ def make_workload(name, L):
         p.t0 = 40.0           # inside the pulse
         p.dt = 0.002          # meets the 1e-8 state-error bar (the table's dt is 0.05)
         label = "hydrogen-fd Nr=2000 dr=0.1 l<=63 dim=128000 CF8:11 m=30"
+        key = "hydrogen"
     elif name == "ising":
         p = I.config_ising(L=L or 10)
         label = f"ising L={p.meta['L']} dim={p.dim} CF4:2 m=16"
+        key = f"ising_L{p.meta['L']}"
     elif name == "heisenberg":
         p = I.config_heisenberg(L=L or 24)
         label = f"heisenberg L={p.meta['L']} dim={p.dim} CF6:5Opt m=24"
+        key = f"heisenberg_L{p.meta['L']}"
     else:
         raise SystemExit(f"unknown workload {name}")
-    return p, label
+    return p, label, key
 
 
 def cpu_baseline(p, nsteps_sample, state0):
@@ -96,6 +148,11 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the state-error run")
     ap.add_argument("--path", default=None, choices=["multi", "single", "coop"],
                     help="force an execution path (default: chosen by dimension)")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="steps per propagate call (default per workload); every launch "
+                         "of the timed kernel then covers the same work")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -109,11 +166,21 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
-    p, label = make_workload(args.workload, args.L)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration << 20, max(1, args.steps))
+        return
+    p, label, key = make_workload(args.workload, args.L)
     if args.dt:
         p.dt = args.dt
-    K, W = args.steps, args.warmup
-    log(f"workload {label}, dt={p.dt}, steps={K}, warmup={W}")
+    chunk = args.chunk or DEFAULT_CHUNK[args.workload]
+    K = max(chunk, (args.steps + chunk - 1) // chunk * chunk)
+    W = (args.warmup + chunk - 1) // chunk * chunk
+    log(f"workload {label}, dt={p.dt}, steps={K}, warmup={W}, {chunk} steps per call")
+
+    def run(psi, t0, dt, nsteps, m):
+        for c in range(0, nsteps, chunk):
+            P.propagate(psi, t0 + c * dt, dt, chunk, p.scheme, m)
+
     t = time.perf_counter()
     P = B.Propagator(p.H0, p.Hk, p.drives, path=args.path)
     log(f"context created in {time.perf_counter() - t:.1f}s")
@@ -124,7 +191,7 @@ def main():
     psi = torch.from_numpy(np.ascontiguousarray(p.psi0)).to("cuda")
     stream = torch.cuda.current_stream()
     # warm-up
-    P.propagate(psi, p.t0, p.dt, W, p.scheme, p.m)
+    run(psi, p.t0, p.dt, W, p.m)
     torch.cuda.synchronize()
     t_start = p.t0 + W * p.dt
     psi_start = psi.clone()
@@ -133,7 +200,7 @@ def main():
     # timed region
     torch.cuda.synchronize()
     t = time.perf_counter()
-    P.propagate(psi, t_start, p.dt, K, p.scheme, p.m)
+    run(psi, t_start, p.dt, K, p.m)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     st1 = P.stats()
@@ -150,17 +217,17 @@ def main():
     # whole-call kernel on the persistent paths)
     psi.copy_(psi_start)
     P.profile(True, max_launches=min(K * s * p.m, 1 << 18))
-    P.propagate(psi, t_start, p.dt, K, p.scheme, p.m)
+    run(psi, t_start, p.dt, K, p.m)
     torch.cuda.synchronize()
     stp = P.stats()
     P.profile(False)
     avg_ms = stp["timed_ms"] / max(1, stp["timed_launches"])
     if path == "multi":
-        kernel = "k_lz_spmv"
+        kernel = "k_sell_lz_spmv" if P.uses_sell() else "k_lz_spmv"
         bytes_per_launch = spmv_algorithmic_bytes(p.dim, nnz_total, ncsr)
     else:
         kernel = "k_propagate"
-        bytes_per_launch = K * s * exponential_algorithmic_bytes(p.dim, nnz_total, ncsr, m_eff)
+        bytes_per_launch = chunk * s * exponential_algorithmic_bytes(p.dim, nnz_total, ncsr, m_eff)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     log(f"path {path}: {kernel} {stp['timed_launches']} launches, avg {avg_ms * 1e3:.2f} us, "
         f"{bytes_per_launch / 1e6:.2f} MB algorithmic -> {achieved:.0f} GB/s")
@@ -173,10 +240,15 @@ def main():
     state_error = None
     if not args.no_error:
         ref = psi_start.clone()
-        P.propagate(ref, t_start, p.dt / 4, 4 * K, p.scheme, max(40, p.m))
+        run(ref, t_start, p.dt / 4, 4 * K, max(40, p.m))
         torch.cuda.synchronize()
         state_error = float(torch.linalg.vector_norm(psi_end - ref).item())
         log(f"state error vs dt/4, m=40: {state_error:.3e}")
+
+    traffic = measured_traffic(kernel, key, chunk)
+    if traffic is not None:
+        log(f"{kernel}: measured HBM traffic {traffic / 1e6:.2f} MB per launch "
+            f"({traffic / bytes_per_launch:.3f} x algorithmic)")
 
     # CPU oracle baseline on a bounded sample
     cpu = None
@@ -208,11 +280,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": label, "dim": p.dim, "nnz": nnz_total, "scheme": p.scheme,
                    "krylov_m": p.m, "dt": p.dt, "t0": t_start, "path": path,
+                   "steps_per_call": chunk,
                    "state_error": state_error,
                    "matvecs_per_step": matvecs / K},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": round(avg_ms * 1e3, 3)},
         "cpu_baseline": cpu,

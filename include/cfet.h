@@ -143,6 +143,9 @@ typedef struct {
   double segment_us[4];      /* persistent paths with cfet_profile on: time of block 0 in
                                 SpMV phases, reductions/barriers, small exponentials,
                                 recombinations (microseconds, cumulative) */
+  int32_t layout;            /* operator storage of the multi-kernel path: 0 merged CSR,
+                                1 SELL-64 */
+  int32_t reserved;
 } cfet_stats_t;
 
 /* Build a context for H(t) = H0 + sum_k f_k(t) Hk[k], k < nterms

@@ -51,7 +51,7 @@ class _Stats(ctypes.Structure):
                 ("matvecs", c_int64), ("min_m_eff", c_int32), ("breakdowns", c_int32),
                 ("path", c_int32), ("status", c_int32), ("last_norm", c_double),
                 ("timed_launches", c_int64), ("timed_ms", c_double),
-                ("segment_us", c_double * 4)]
+                ("segment_us", c_double * 4), ("layout", c_int32), ("reserved", c_int32)]
 
 
 _LIB = None
@@ -224,6 +224,10 @@ class Propagator:
         out = {f[0]: getattr(st, f[0]) for f in _Stats._fields_}
         out["segment_us"] = list(out["segment_us"])
         return out
+
+    def uses_sell(self) -> bool:
+        """True when the multi-kernel path runs on the SELL-64 layout."""
+        return self.stats()["layout"] == 1
 
     def profile(self, enable: bool, max_launches: int = 65536):
         _check(load().cfet_profile(self._ctx, 1 if enable else 0, int(max_launches)), self._ctx)

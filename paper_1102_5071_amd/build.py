@@ -25,6 +25,23 @@ FLAGS = [
 ]
 
 
+def source_digest() -> str:
+    """SHA-256 over the library sources, the public header and the compiler
+    flags: a counter measurement taken on one build is valid for another
+    build only if the digests match."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(" ".join(FLAGS).encode())
+    files = sorted(os.listdir(CSRC)) + ["../../include/cfet.h"]
+    for name in files:
+        path = os.path.normpath(os.path.join(CSRC, name))
+        if os.path.isfile(path) and not name.endswith((".so", ".o")):
+            h.update(name.encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):

@@ -908,6 +908,7 @@ int cfet_stats(cfet_ctx* c, cfet_stats_t* s) {
   s->min_m_eff = d.exponentials ? d.min_m_eff : 0;
   s->breakdowns = d.breakdowns;
   s->path = c->last_path;
+  s->layout = c->use_sell ? 1 : 0;
   s->status = d.status;
   s->last_norm = std::sqrt(d.last_norm2);
   harvest_events(c);
