@@ -61,13 +61,19 @@ __device__ __forceinline__ double2 sell_row(const DevSELL& S, int64_t slice, int
   const uint32_t* __restrict__ cp = S.colt + base + lane;
   const dvec2* __restrict__ vp = reinterpret_cast<const dvec2*>(S.val) + base + lane;
   int k = 0;
+  // padded slots (k >= len) are neither loaded nor gathered
   for (; k + 4 <= width; k += 4) {
     uint32_t ct[4];
     dvec2 v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      ct[u] = __builtin_nontemporal_load(cp + (int64_t)(k + u) * 64);
-      v[u] = __builtin_nontemporal_load(vp + (int64_t)(k + u) * 64);
+      if (k + u < len) {
+        ct[u] = __builtin_nontemporal_load(cp + (int64_t)(k + u) * 64);
+        v[u] = __builtin_nontemporal_load(vp + (int64_t)(k + u) * 64);
+      } else {
+        ct[u] = 0u;
+        v[u] = dvec2{0.0, 0.0};
+      }
     }
     double2 xv[4];
 #pragma unroll
@@ -85,10 +91,10 @@ __device__ __forceinline__ double2 sell_row(const DevSELL& S, int64_t slice, int
       }
     }
   }
-  for (; k < width; ++k) {
+  for (; k < len; ++k) {
     const uint32_t ct = __builtin_nontemporal_load(cp + (int64_t)k * 64);
     const dvec2 v = __builtin_nontemporal_load(vp + (int64_t)k * 64);
-    const double2 xv = (k < len) ? x[ct & kColMask] : make_double2(0.0, 0.0);
+    const double2 xv = x[ct & kColMask];
     const double pr = v.x * xv.x - v.y * xv.y;
     const double pi = v.x * xv.y + v.y * xv.x;
     if (NT == 1) {
@@ -103,6 +109,31 @@ __device__ __forceinline__ double2 sell_row(const DevSELL& S, int64_t slice, int
   return make_double2(a0r, a0i);
 }
 
+// Slice schedule: workgroups are dealt to the 8 XCDs round-robin, so block b
+// runs on XCD b % 8.  Each XCD is given one contiguous eighth of the slices,
+// swept by its own blocks in lock-step, so the x lines gathered for nearby
+// rows stay in that XCD's L2.  (Any grid size is valid; for a grid that is not
+// a multiple of 8 the plain grid-stride order is used.)
+struct SliceRange {
+  int64_t first, end, stride;
+};
+
+__device__ __forceinline__ SliceRange slice_range(int64_t nslices) {
+  constexpr int kXcds = 8;
+  constexpr int kWaves = kSellBlock / 64;
+  const int w = threadIdx.x >> 6;
+  const int nb = gridDim.x;
+  if (nb % kXcds != 0) {
+    return {(int64_t)blockIdx.x * kWaves + w, nslices, (int64_t)nb * kWaves};
+  }
+  const int xcd = blockIdx.x % kXcds;
+  const int rank = blockIdx.x / kXcds;
+  const int64_t per = (nslices + kXcds - 1) / kXcds;
+  const int64_t beg = min(nslices, (int64_t)xcd * per);
+  const int64_t end = min(nslices, beg + per);
+  return {beg + (int64_t)rank * kWaves + w, end, (int64_t)(nb / kXcds) * kWaves};
+}
+
 template <int NT>
 __global__ __launch_bounds__(kSellBlock) void k_sell_apply(DevSELL S, TermWeights tw,
                                                            const double2* __restrict__ x,
@@ -111,10 +142,8 @@ __global__ __launch_bounds__(kSellBlock) void k_sell_apply(DevSELL S, TermWeight
   if (threadIdx.x <= kMaxTerms) wl[threadIdx.x] = tw.w[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t nslices = (S.n + 63) / 64;
-  const int64_t wstride = (int64_t)gridDim.x * (kSellBlock / 64);
-  for (int64_t sl = (int64_t)blockIdx.x * (kSellBlock / 64) + (threadIdx.x >> 6); sl < nslices;
-       sl += wstride) {
+  const SliceRange R = slice_range((S.n + 63) / 64);
+  for (int64_t sl = R.first; sl < R.end; sl += R.stride) {
     const int64_t row = sl * 64 + lane;
     const double2 r = sell_row<NT>(S, sl, lane, row, x, wl);
     if (row < S.n) y[row] = r;
@@ -167,11 +196,9 @@ __global__ __launch_bounds__(kSellBlock) void k_sell_lz_spmv(
   if (threadIdx.x <= kMaxTerms) wl[threadIdx.x] = tw.w[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t nslices = (S.n + 63) / 64;
-  const int64_t wstride = (int64_t)gridDim.x * (kSellBlock / 64);
+  const SliceRange R = slice_range((S.n + 63) / 64);
   double apart = 0.0;
-  for (int64_t sl = (int64_t)blockIdx.x * (kSellBlock / 64) + (threadIdx.x >> 6); sl < nslices;
-       sl += wstride) {
+  for (int64_t sl = R.first; sl < R.end; sl += R.stride) {
     const int64_t row = sl * 64 + lane;
     double2 r = sell_row<NT>(S, sl, lane, row, x, wl);
     if (row < S.n) {
