@@ -43,7 +43,8 @@ from .schemes import Scheme, gl_weights, scheme as get_scheme
 BREAKDOWN_REL_TOL = 1e-12
 
 __all__ = ["drive_value", "step_weights", "lanczos", "tridiag_expm_e1", "expv",
-           "expv_dense", "propagate", "LanczosInfo", "BREAKDOWN_REL_TOL"]
+           "expv_adaptive", "expv_dense", "propagate", "propagate_batch", "LanczosInfo",
+           "BREAKDOWN_REL_TOL"]
 
 
 # --------------------------------------------------------------------------
@@ -185,6 +186,71 @@ def expv(H, psi: np.ndarray, dt: float, m: int, return_info: bool = False):
     return (out, info) if return_info else out
 
 
+def expv_adaptive(H, psi: np.ndarray, dt: float, m_max: int, tol: float,
+                  return_info: bool = False):
+    """Krylov exponential with the basis size chosen per call.
+
+    The Lanczos recurrence of ``lanczos`` runs until, after j basis vectors
+    (j < m_max), either the breakdown rule fires or the a-posteriori estimate
+    of the Krylov error relative to ||psi||,
+
+        est_j = |dt| * beta_j * | e_j^T exp(-i dt T_j) e_1 |,
+
+    is at most tol (T_j: the j x j tridiagonal projection, beta_j: the norm of
+    the residual after j steps).  It is the leading term of the expansion of
+    the Krylov error in the residual direction v_{j+1}, with phi_1 replaced by
+    the exponential itself, and like the Krylov approximation it is invariant
+    under H -> c H, dt -> dt / c.  The paper fixes m per run; its conclusions
+    leave the automatic choice of the Krylov dimension open (Sec. 12).  At
+    j = m_max the recurrence stops in any case, exactly as ``expv``.
+    tol <= 0 gives ``expv`` with m = m_max.
+    """
+    dim = psi.shape[0]
+    if hasattr(H, "to_scipy"):
+        H = H.to_scipy()
+    info = LanczosInfo()
+    beta0 = float(np.linalg.norm(psi))
+    info.beta0 = beta0
+    m = min(m_max, dim)
+    if beta0 == 0.0:
+        out = np.zeros_like(psi)
+        return (out, info) if return_info else out
+    V = np.zeros((dim, m), dtype=np.complex128)
+    alpha = np.zeros(m)
+    beta = np.zeros(m)
+    V[:, 0] = psi / beta0
+    scale = 0.0
+    m_eff = m
+    c = None
+    for j in range(m):
+        w = H @ V[:, j]
+        alpha[j] = float(np.real(np.vdot(V[:, j], w)))
+        if j == m - 1:
+            break
+        w = w - alpha[j] * V[:, j]
+        if j > 0:
+            w = w - beta[j - 1] * V[:, j - 1]
+        beta[j] = float(np.linalg.norm(w))
+        scale = max(scale, abs(alpha[j]) + beta[j])
+        if beta[j] <= BREAKDOWN_REL_TOL * scale:
+            m_eff = j + 1
+            break
+        if tol > 0.0:
+            cj = tridiag_expm_e1(alpha[:j + 1], beta[:j], dt)
+            if abs(dt) * beta[j] * abs(cj[j]) <= tol:
+                m_eff = j + 1
+                c = cj
+                break
+        V[:, j + 1] = w / beta[j]
+    info.m_eff = m_eff
+    info.alpha = alpha[:m_eff].copy()
+    info.beta = beta[:m_eff - 1].copy()
+    if c is None:
+        c = tridiag_expm_e1(info.alpha, info.beta, dt)
+    out = beta0 * (V[:, :m_eff] @ c)
+    return (out, info) if return_info else out
+
+
 def expv_dense(H, psi: np.ndarray, dt: float) -> np.ndarray:
     """exp(-i dt H) psi by scipy.linalg.expm on the dense matrix (small dims)."""
     Hd = _as_matrix(H, True)
@@ -206,12 +272,13 @@ def _as_matrix(H, dense: bool):
 
 def propagate(H0, Hk, drives, psi0, t0: float, dt: float, nsteps: int,
               scheme_name: str, m: int | None = None, dense: bool = False,
-              stats: dict | None = None):
+              stats: dict | None = None, tol: float = 0.0):
     """Propagate psi0 over nsteps CFET steps of size dt starting at t0.
 
     H0: sparse/dense Hermitian matrix, Hk: list of matrices, drives: list of
     drive dicts (one per H_k).  With dense=True every exponential is taken
-    exactly (expm), otherwise by Lanczos with m vectors.
+    exactly (expm), otherwise by Lanczos with m vectors (tol > 0: at most m,
+    chosen per exponential by ``expv_adaptive``).
     """
     sc = get_scheme(scheme_name)
     if len(Hk) != len(drives):
@@ -230,7 +297,10 @@ def propagate(H0, Hk, drives, psi0, t0: float, dt: float, nsteps: int,
             if dense:
                 psi = expv_dense(Hi, psi, dt)
             else:
-                psi, info = expv(Hi, psi, dt, m, return_info=True)
+                if tol > 0.0:
+                    psi, info = expv_adaptive(Hi, psi, dt, m, tol, return_info=True)
+                else:
+                    psi, info = expv(Hi, psi, dt, m, return_info=True)
                 n_matvec += info.m_eff
                 if stats is not None:
                     stats.setdefault("m_eff", []).append(info.m_eff)
@@ -239,3 +309,19 @@ def propagate(H0, Hk, drives, psi0, t0: float, dt: float, nsteps: int,
     if stats is not None:
         stats["n_matvec"] = n_matvec
     return psi
+
+
+def propagate_batch(instances, t0: float, dt: float, nsteps: int, scheme_name: str,
+                    m: int, tol: float = 0.0, stats: list | None = None):
+    """Independent trajectories, one after another: each instance is a dict
+    with keys H0, Hk, drives, psi0 and is propagated by ``propagate`` with the
+    same scheme, time grid, m (the upper bound when tol > 0) and tol.
+    Returns the list of final states (and per-instance stats when asked)."""
+    out = []
+    for inst in instances:
+        st = {} if stats is not None else None
+        out.append(propagate(inst["H0"], inst["Hk"], inst["drives"], inst["psi0"], t0, dt,
+                             nsteps, scheme_name, m=m, stats=st, tol=tol))
+        if stats is not None:
+            stats.append(st)
+    return out

@@ -370,5 +370,58 @@ def config_heisenberg(L: int = 24, seed: int = 0, nsteps: int = 200) -> Problem:
                    meta={"L": L, "h": h, "seed": seed})
 
 
+@dataclass
+class Batch:
+    """Independent trajectories sharing one scheme, time grid and Krylov
+    bound.  ops: list of CSR operators; each instance names its H0 and driven
+    terms by index into ops (so a term shared by many instances is stored once)
+    and carries its own drives and initial state."""
+    name: str
+    ops: list
+    instances: list          # dicts: h0 (int), hk (list of int), drives, psi0
+    scheme: str = "CF4:2"
+    dt: float = 0.01
+    nsteps: int = 500
+    m: int = 32
+    tol: float = 1e-10
+    t0: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    def dims(self):
+        return [self.ops[i["h0"]].n for i in self.instances]
+
+    def oracle_instances(self):
+        """The instances with operators resolved (H0, Hk matrices)."""
+        return [{"H0": self.ops[i["h0"]], "Hk": [self.ops[k] for k in i["hk"]],
+                 "drives": i["drives"], "psi0": i["psi0"]} for i in self.instances]
+
+
+def config_batched(n_traj: int = 256, L_min: int = 12, L_max: int = 18, seed: int = 0,
+                   nsteps: int = 500) -> Batch:
+    """Many driven Ising chains in one batch: for each trajectory, in order,
+    L ~ U{L_min..L_max}, A ~ U[0.2, 1.5], omega ~ U[0.5, 3], then h_i ~ U[-1, 1]
+    (i < L); J = 1, H1 = sum sx (one operator per L, shared), f = A cos(omega t),
+    psi0 = all up.  CF4:2, dt = 0.01, adaptive m <= 32 at tol 1e-10."""
+    rng = np.random.default_rng(seed)
+    ops = []
+    sx_index = {}
+    instances = []
+    for _ in range(n_traj):
+        L = int(rng.integers(L_min, L_max + 1))
+        A = float(rng.uniform(0.2, 1.5))
+        omega = float(rng.uniform(0.5, 3.0))
+        h = rng.uniform(-1.0, 1.0, L)
+        if L not in sx_index:
+            sx_index[L] = len(ops)
+            ops.append(sigma_x_sum(L))
+        ops.append(ising_chain(L, 1.0, h))
+        instances.append({"h0": len(ops) - 1, "hk": [sx_index[L]],
+                          "drives": [{"kind": "cos", "A": A, "omega": omega, "phi": 0.0}],
+                          "psi0": basis_state(1 << L, 0), "L": L})
+    return Batch(f"batched-{n_traj}x-ising-L{L_min}-{L_max}", ops, instances,
+                 scheme="CF4:2", dt=0.01, nsteps=nsteps, m=32, tol=1e-10,
+                 meta={"seed": seed, "L_min": L_min, "L_max": L_max})
+
+
 CONFIGS = {"ising": config_ising, "hydrogen": config_hydrogen,
            "heisenberg": config_heisenberg}
