@@ -224,6 +224,85 @@ CFET_API int cfet_tridiag_expm(const double *alpha_dev, const double *beta_dev, 
 
 CFET_API int cfet_version(void);
 
+/* ---------------------------------------------------------------------------
+ * Batched propagation: many independent trajectories advanced together.
+ *
+ * Every instance t is its own problem  i d/dt psi_t = (H0_t + sum_k f_tk(t)
+ * H_tk) psi_t  with its own drives and state; all share the scheme, the time
+ * grid and the Krylov bound of a call.  Operators live in one table and
+ * instances refer to them by index, so an operator used by many instances
+ * (e.g. sum_i sigma^x_i of one chain length) is stored and streamed once for
+ * all of them: instances with the same driven operators and dimension are
+ * grouped (at most 64 per group) and their vectors interleaved, and each
+ * Lanczos phase is one kernel over every instance of the batch.  The
+ * exponentials are those of cfet_propagate (Sec. 8.1); with tol > 0 the
+ * Krylov dimension is chosen per instance and per exponential: the recurrence
+ * stops after j < m vectors when  |dt| beta_j |e_j^T exp(-i dt T_j) e_1| <= tol
+ * (an a-posteriori estimate of the Krylov error relative to ||psi||; the
+ * paper fixes m and leaves this choice open, Sec. 12), or by the breakdown
+ * rule of cfet_propagate.  One CFET step is captured once as a HIP graph and
+ * replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct cfet_batch cfet_batch;
+
+typedef struct {
+  int32_t h0;                         /* operator index of H0 */
+  int32_t nterms;                     /* driven terms, 0..CFET_MAX_TERMS */
+  int32_t hk[CFET_MAX_TERMS];         /* operator indices of H_1..H_nterms */
+  cfet_drive fk[CFET_MAX_TERMS];      /* their drives (PWC arrays: host, copied) */
+} cfet_instance;
+
+/* Flags for cfet_batch_create (CFET_VALIDATE_HERMITIAN applies as well). */
+#define CFET_BATCH_NO_GRAPH 0x1000u     /* enqueue every kernel instead of graph replays */
+#define CFET_BATCH_NO_AUTOTUNE 0x2000u  /* skip the launch-layout timing at create */
+
+typedef struct {
+  int32_t ninst;          /* instances */
+  int32_t ngroups;        /* groups sharing operator reads */
+  int64_t total_dim;      /* sum of the instance dimensions */
+  int64_t matvecs;        /* H applications, summed over instances */
+  int64_t exponentials;   /* exponentials, summed over instances */
+  int64_t breakdowns;     /* exponentials stopped by the breakdown rule (or psi = 0) */
+  int64_t early_stops;    /* exponentials stopped by the error estimate */
+  int32_t min_m_eff;      /* smallest / largest Krylov dimension used */
+  int32_t max_m_eff;
+  int32_t status;         /* latched device status (cleared by this call) */
+  int32_t unroll;         /* launch layout chosen at create: rows per lane and pass */
+  int32_t graph;          /* 1 if the last call replayed the step graph */
+  int32_t reserved;
+  double tune_us[4];      /* create-time SpMM timing of the layouts 1, 2, 4, 8 */
+} cfet_batch_stats_t;
+
+/* Build a batch.  ops: nops CSR matrices (host or device arrays, copied and
+ * validated as by cfet_create).  inst: ninst instances.  The operators of
+ * one instance must have the same dimension (< 2^29).  Times the launch
+ * layouts once on the device unless CFET_BATCH_NO_AUTOTUNE.  *out receives
+ * the batch (NULL on failure); release it with cfet_batch_destroy. */
+CFET_API int cfet_batch_create(int32_t nops, const cfet_csr *ops, int32_t ninst,
+                               const cfet_instance *inst, uint32_t flags, cfet_batch **out);
+
+/* Propagate every instance over nsteps CFET steps of size dt from t0.
+ * psi_dev: complex128 device buffer holding the instances' states one after
+ * another in instance order (length = sum of their dimensions), updated in
+ * place.  krylov_m: 1..CFET_MAX_KRYLOV (upper bound when tol > 0; clipped to
+ * each instance's dimension).  tol >= 0 (0: fixed m).  Stream-ordered; device
+ * faults are latched and reported by cfet_batch_stats. */
+CFET_API int cfet_batch_propagate(cfet_batch *b, void *psi_dev, double t0, double dt,
+                                  int64_t nsteps, int32_t scheme, int32_t krylov_m, double tol,
+                                  void *hip_stream);
+
+/* Synchronise and report statistics; returns the latched device status. */
+CFET_API int cfet_batch_stats(cfet_batch *b, cfet_batch_stats_t *s);
+
+/* Synchronise and write each instance's cumulative H applications to out
+ * (int64[ninst], instance order). */
+CFET_API int cfet_batch_instance_matvecs(cfet_batch *b, int64_t *out);
+
+CFET_API int cfet_batch_destroy(cfet_batch *b);
+
+/* Message of the last failure on b (b == NULL: last batch call on this thread). */
+CFET_API const char *cfet_batch_last_error(const cfet_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

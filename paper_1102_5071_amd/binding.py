@@ -54,6 +54,22 @@ class _Stats(ctypes.Structure):
                 ("segment_us", c_double * 4), ("layout", c_int32), ("reserved", c_int32)]
 
 
+class _Instance(ctypes.Structure):
+    _fields_ = [("h0", c_int32), ("nterms", c_int32), ("hk", c_int32 * 7),
+                ("fk", _Drive * 7)]
+
+
+class _BatchStats(ctypes.Structure):
+    _fields_ = [("ninst", c_int32), ("ngroups", c_int32), ("total_dim", c_int64),
+                ("matvecs", c_int64), ("exponentials", c_int64), ("breakdowns", c_int64),
+                ("early_stops", c_int64), ("min_m_eff", c_int32), ("max_m_eff", c_int32),
+                ("status", c_int32), ("unroll", c_int32), ("graph", c_int32),
+                ("reserved", c_int32), ("tune_us", c_double * 4)]
+
+
+BATCH_NO_GRAPH = 0x1000
+BATCH_NO_AUTOTUNE = 0x2000
+
 _LIB = None
 
 
@@ -86,9 +102,19 @@ def load():
     lib.cfet_profile.argtypes = [c_void_p, c_int32, c_int32]
     lib.cfet_tridiag_expm.argtypes = [c_void_p, c_void_p, c_int32, c_double, c_void_p, c_void_p,
                                       c_void_p]
+    lib.cfet_batch_create.argtypes = [c_int32, POINTER(_CSR), c_int32, POINTER(_Instance),
+                                      c_uint32, POINTER(c_void_p)]
+    lib.cfet_batch_propagate.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int64,
+                                         c_int32, c_int32, c_double, c_void_p]
+    lib.cfet_batch_stats.argtypes = [c_void_p, POINTER(_BatchStats)]
+    lib.cfet_batch_instance_matvecs.argtypes = [c_void_p, c_void_p]
+    lib.cfet_batch_destroy.argtypes = [c_void_p]
+    lib.cfet_batch_last_error.restype = ctypes.c_char_p
+    lib.cfet_batch_last_error.argtypes = [c_void_p]
     for name in ("cfet_create", "cfet_propagate", "cfet_gradient", "cfet_apply", "cfet_stats",
                  "cfet_destroy", "cfet_scheme_info", "cfet_step_weights", "cfet_tridiag_expm",
-                 "cfet_profile"):
+                 "cfet_profile", "cfet_batch_create", "cfet_batch_propagate", "cfet_batch_stats",
+                 "cfet_batch_instance_matvecs", "cfet_batch_destroy"):
         getattr(lib, name).restype = c_int32
     _LIB = lib
     return lib
@@ -240,6 +266,91 @@ class Propagator:
         if getattr(self, "_ctx", None):
             load().cfet_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class BatchPropagator:
+    """Owns a cfet batch: independent instances sharing scheme and time grid.
+
+    ops: list of CSR operators; instances: list of dicts with keys h0 (operator
+    index), hk (list of operator indices) and drives (one drive dict per hk
+    entry).  States are passed as one complex128 CUDA tensor holding the
+    instances one after another (see ``offsets``)."""
+
+    def __init__(self, ops, instances, validate_hermitian: bool = False, graph: bool = True,
+                 autotune: bool = True):
+        lib = load()
+        keep = []
+        cops = (_CSR * len(ops))(*[_csr_struct(m, keep) for m in ops])
+        insts = (_Instance * len(instances))()
+        for t, inst in enumerate(instances):
+            hk = list(inst["hk"])
+            if len(hk) != len(inst["drives"]) or len(hk) > 7:
+                raise ValueError("one drive per driven term, at most 7 terms")
+            insts[t].h0 = int(inst["h0"])
+            insts[t].nterms = len(hk)
+            for k, (h, d) in enumerate(zip(hk, inst["drives"])):
+                insts[t].hk[k] = int(h)
+                insts[t].fk[k] = _drive_struct(d, keep)
+        flags = ((VALIDATE_HERMITIAN if validate_hermitian else 0)
+                 | (0 if graph else BATCH_NO_GRAPH) | (0 if autotune else BATCH_NO_AUTOTUNE))
+        handle = c_void_p()
+        code = lib.cfet_batch_create(len(ops), cops, len(instances), insts, flags,
+                                     ctypes.byref(handle))
+        if code != 0:
+            raise CfetError(code, lib.cfet_batch_last_error(None).decode(errors="replace"))
+        self._b = handle
+        self.dims = [int(ops[i["h0"]].n) for i in instances]
+        self.offsets = np.concatenate([[0], np.cumsum(self.dims)]).astype(np.int64)
+        self.total = int(self.offsets[-1])
+
+    def _check(self, code):
+        if code != 0:
+            raise CfetError(code, load().cfet_batch_last_error(self._b).decode(errors="replace"))
+
+    def propagate(self, psi, t0: float, dt: float, nsteps: int, scheme, m: int,
+                  tol: float = 0.0, stream=None):
+        """psi: complex128 CUDA tensor of length sum(dims), updated in place."""
+        import torch
+        if not (isinstance(psi, torch.Tensor) and psi.is_cuda and psi.dtype == torch.complex128
+                and psi.is_contiguous() and psi.numel() == self.total):
+            raise ValueError("expected a contiguous complex128 CUDA tensor of length sum(dims)")
+        self._check(load().cfet_batch_propagate(self._b, c_void_p(psi.data_ptr()), float(t0),
+                                                float(dt), int(nsteps), scheme_id(scheme),
+                                                int(m), float(tol), _stream_handle(stream)))
+        return psi
+
+    def stats(self) -> dict:
+        st = _BatchStats()
+        self._check(load().cfet_batch_stats(self._b, ctypes.byref(st)))
+        out = {f[0]: getattr(st, f[0]) for f in _BatchStats._fields_}
+        out["tune_us"] = list(out["tune_us"])
+        return out
+
+    def instance_matvecs(self):
+        out = np.zeros(len(self.dims), dtype=np.int64)
+        self._check(load().cfet_batch_instance_matvecs(self._b, out.ctypes.data))
+        return out
+
+    def split(self, psi):
+        """Views of the instances' states in a packed tensor."""
+        return [psi[self.offsets[t]:self.offsets[t + 1]] for t in range(len(self.dims))]
+
+    def close(self):
+        if getattr(self, "_b", None):
+            load().cfet_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -1,0 +1,34 @@
+// Host-side input handling shared by the single-trajectory and batched
+// entry points: staging of caller matrices, CSR validation, drive copies.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cfet.h"
+#include "cfet_internal.h"
+
+namespace cfet {
+
+// A caller CSR viewed on the host (device arrays are copied into the buffers).
+struct HostCSR {
+  int64_t n, nnz;
+  const int64_t* rp;
+  const int32_t* col;
+  const double* val;
+  std::vector<int64_t> rp_buf;
+  std::vector<int32_t> col_buf;
+  std::vector<double> val_buf;
+};
+
+// True if p is device (or managed) memory; false for plain host memory.
+bool is_device_ptr(const void* p);
+
+// Each returns CFET_OK or an error code and sets err to a message.
+int load_csr(std::string& err, const cfet_csr* m, const char* name, HostCSR* h);
+int validate_csr(std::string& err, const HostCSR& h, const char* name);
+int check_hermitian(std::string& err, const HostCSR& h, const char* name);
+int copy_drive(std::string& err, const cfet_drive& d, DriveSpec* out);
+
+}  // namespace cfet

@@ -79,3 +79,54 @@ def test_host_side_argument_errors():
     assert lib.cfet_stats(None, None) == 1
     assert lib.cfet_destroy(None) == 1
     assert b"null" in lib.cfet_last_error(None)
+
+
+def _csr(n, diag):
+    rp = np.arange(n + 1, dtype=np.int64)
+    col = np.arange(n, dtype=np.int32)
+    val = np.asarray(diag, dtype=np.complex128)
+    return rp, col, val
+
+
+def test_batch_host_side_argument_errors():
+    lib = _lib()
+    out = ctypes.c_void_p()
+    assert lib.cfet_batch_create(0, None, 1, None, 0, ctypes.byref(out)) == 1
+    assert lib.cfet_batch_create(1, None, 1, None, 0, None) == 1
+    keep = []
+    rp, col, val = _csr(4, [1, 2, 3, 4])
+    rp2, col2, val2 = _csr(8, np.ones(8))
+    keep += [rp, col, val, rp2, col2, val2]
+    ops = (B._CSR * 2)(B._CSR(4, 4, rp.ctypes.data, col.ctypes.data, val.ctypes.data),
+                       B._CSR(8, 8, rp2.ctypes.data, col2.ctypes.data, val2.ctypes.data))
+    inst = (B._Instance * 1)()
+    inst[0].h0 = 0
+    inst[0].nterms = 1
+    inst[0].hk[0] = 1          # dimension 8 against H0 of dimension 4
+    inst[0].fk[0] = B._Drive(0, 1.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0, None, None)
+    assert lib.cfet_batch_create(2, ops, 1, inst, 0, ctypes.byref(out)) == 1
+    assert b"same n" in lib.cfet_batch_last_error(None)
+    inst[0].hk[0] = 5          # out of range
+    assert lib.cfet_batch_create(2, ops, 1, inst, 0, ctypes.byref(out)) == 1
+    inst[0].hk[0] = 0
+    inst[0].nterms = 8         # too many terms
+    assert lib.cfet_batch_create(2, ops, 1, inst, 0, ctypes.byref(out)) == 1
+    inst[0].nterms = 1
+    inst[0].fk[0] = B._Drive(9, 1.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0, None, None)  # bad drive kind
+    assert lib.cfet_batch_create(2, ops, 1, inst, 0, ctypes.byref(out)) == 1
+    bad = val.copy()
+    bad[2] = np.nan
+    keep.append(bad)
+    ops[0] = B._CSR(4, 4, rp.ctypes.data, col.ctypes.data, bad.ctypes.data)
+    assert lib.cfet_batch_create(2, ops, 1, inst, 0, ctypes.byref(out)) == 4
+    assert out.value is None
+    assert lib.cfet_batch_propagate(None, None, 0.0, 0.1, 1, 1, 4, 0.0, None) == 1
+    assert lib.cfet_batch_stats(None, None) == 1
+    assert lib.cfet_batch_instance_matvecs(None, None) == 1
+    assert lib.cfet_batch_destroy(None) == 0
+
+
+def test_batch_struct_layout():
+    # cfet_instance: 9 int32 then 7 cfet_drive (80 bytes each, 8-byte aligned)
+    assert ctypes.sizeof(B._Drive) == 80
+    assert ctypes.sizeof(B._Instance) == 40 + 7 * 80
