@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
-DEFAULT_CHUNK = {"hydrogen": 10, "ising": 50, "heisenberg": 1}
+DEFAULT_CHUNK = {"hydrogen": 10, "ising": 50, "heisenberg": 1, "batched": 0}
 
 
 def log(msg):
@@ -135,12 +135,140 @@ def cpu_baseline(p, nsteps_sample, state0):
     return nsteps_sample / el, el
 
 
+def run_batched(args):
+    """Many-trajectory workload: 256 driven Ising chains, L ~ U{12..18}, CF4:2,
+    dt = 0.01, adaptive m <= 32 at tol 1e-10, all in one batch (one kernel per
+    Lanczos phase over every trajectory, step replayed from a HIP graph).
+    Reports trajectory-steps/s, and the plain single-trajectory path on one
+    chain of each length for comparison (same steps, m fixed at the largest
+    Krylov dimension the batch used)."""
+    import numpy as np
+    import torch
+    from paper_1102_5071_amd import binding as B
+    from paper_1102_5071_amd import inputs as I
+
+    Bt = I.config_batched(n_traj=args.ntraj, seed=0)
+    K, W = args.steps, args.warmup
+    nin = len(Bt.instances)
+    label = (f"batched {nin} ising chains L={Bt.meta['L_min']}..{Bt.meta['L_max']} "
+             f"CF4:2 dt={Bt.dt} adaptive m<={Bt.m} tol={Bt.tol}")
+    log(f"workload {label}, steps={K}, warmup={W}")
+    t = time.perf_counter()
+    P = B.BatchPropagator(Bt.ops, Bt.instances)
+    log(f"batch created in {time.perf_counter() - t:.1f}s (total dim {P.total})")
+    psi = torch.from_numpy(np.concatenate([i["psi0"] for i in Bt.instances])).to("cuda")
+    P.propagate(psi, 0.0, Bt.dt, W, Bt.scheme, Bt.m, Bt.tol)
+    torch.cuda.synchronize()
+    st0 = P.stats()
+    mv0 = P.instance_matvecs()
+    t_start = W * Bt.dt
+    psi_start = psi.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    P.propagate(psi, t_start, Bt.dt, K, Bt.scheme, Bt.m, Bt.tol)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    st1 = P.stats()
+    mv = P.instance_matvecs() - mv0
+    rate = nin * K / elapsed
+    log(f"timed: {elapsed * 1e3:.1f} ms for {K} steps x {nin} trajectories -> "
+        f"{rate:.1f} trajectory-steps/s; Krylov dimension {st1['min_m_eff']}..{st1['max_m_eff']}, "
+        f"{mv.sum() / (nin * K * 2):.2f} H applications per exponential, unroll {st1['unroll']}, "
+        f"graph {st1['graph']}, create-time layout timing {st1['tune_us']}")
+    # algorithmic bytes, vectors only (shared operators excluded: a lower bound)
+    dims = np.array(P.dims, dtype=np.float64)
+    expos = 2 * K
+    vec_bytes = float(np.sum(mv * (48.0 + 64.0) * dims)
+                      + np.sum(expos * dims * 16.0 * (mv / expos + 2.0)))
+    achieved = vec_bytes / elapsed / 1e9
+    psi_end = psi.clone()
+    state_error = None
+    if not args.no_error:
+        ref = psi_start.clone()
+        P.propagate(ref, t_start, Bt.dt / 4, 4 * K, Bt.scheme, 40, 1e-13)
+        torch.cuda.synchronize()
+        errs = [float(torch.linalg.vector_norm(a - b).item())
+                for a, b in zip(P.split(psi_end), P.split(ref))]
+        state_error = max(errs)
+        log(f"state error vs dt/4, m<=40, tol 1e-13: max over trajectories {state_error:.3e}")
+    # plain path on one chain per length
+    m_plain = int(st1["max_m_eff"])
+    plain_per_L = {}
+    Ks = min(K, args.plain_steps)
+    for t_i, inst in enumerate(Bt.instances):
+        L = inst["L"]
+        if L in plain_per_L:
+            continue
+        Pp = B.Propagator(Bt.ops[inst["h0"]], [Bt.ops[k] for k in inst["hk"]], inst["drives"])
+        x = P.split(psi_start)[t_i].clone()
+        Pp.propagate(x, t_start, Bt.dt, 2, Bt.scheme, m_plain)
+        torch.cuda.synchronize()
+        x = P.split(psi_start)[t_i].clone()
+        tt = time.perf_counter()
+        Pp.propagate(x, t_start, Bt.dt, Ks, Bt.scheme, m_plain)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - tt
+        path = B.PATH_NAMES[Pp.stats()["path"]]
+        plain_per_L[L] = (Ks / el, path)
+        Pp.close()
+    per_step_plain = sum(1.0 / plain_per_L[i["L"]][0] for i in Bt.instances)
+    plain_rate = nin / per_step_plain
+    log("plain path (m=%d): " % m_plain + ", ".join(
+        f"L={L}: {r:.0f} steps/s ({p})" for L, (r, p) in sorted(plain_per_L.items()))
+        + f" -> {plain_rate:.1f} trajectory-steps/s for the batch one after another; "
+        f"batched/plain = {rate / plain_rate:.2f}")
+    cpu = None
+    if args.cpu_steps != 0:
+        from oracle import cfet as O
+        try:
+            from threadpoolctl import threadpool_limits
+            limiter = threadpool_limits(limits=1)
+        except Exception:       # pragma: no cover
+            limiter = None
+        n_cpu = 2 if args.cpu_steps < 0 else args.cpu_steps
+        sample = [i for i in Bt.instances if i["L"] <= 14][:4]
+        tt = time.perf_counter()
+        for inst in sample:
+            O.propagate(Bt.ops[inst["h0"]], [Bt.ops[k] for k in inst["hk"]], inst["drives"],
+                        inst["psi0"], 0.0, Bt.dt, n_cpu, Bt.scheme, m=Bt.m, tol=Bt.tol)
+        el = time.perf_counter() - tt
+        # scale by dimension: the oracle's cost per step is linear in the dimension
+        dim_sample = sum(1 << i["L"] for i in sample)
+        cps = n_cpu * dim_sample / el / float(np.sum(dims)) * nin
+        cpu = {"value": round(cps, 4), "unit": "trajectory-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{len(sample)} chains with L<=14, {n_cpu} steps each ({el:.1f} s), "
+                         f"scaled to the batch by total dimension"}
+        log(f"oracle: {cps:.3f} trajectory-steps/s (scaled)")
+    out = {
+        "metric": "CFET trajectory-steps/s at 1e-8 state error (batched)",
+        "value": round(rate, 3), "unit": "trajectory-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": round(elapsed * 1e3 / K, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": label, "trajectories": nin, "total_dim": P.total,
+                   "state_error": state_error, "matvecs_per_exponential":
+                       round(float(mv.sum()) / (nin * K * 2), 3),
+                   "plain_path_trajectory_steps_per_s": round(plain_rate, 3),
+                   "batched_over_plain": round(rate / plain_rate, 3)},
+        "roofline": {"bound": "hbm", "kernel": "batched step (all kernels, vector bytes only)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    P.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="hydrogen", choices=["hydrogen", "ising", "heisenberg"])
+    ap.add_argument("--workload", default="hydrogen",
+                    choices=["hydrogen", "ising", "heisenberg", "batched"])
+    ap.add_argument("--ntraj", type=int, default=256, help="batched: number of trajectories")
+    ap.add_argument("--plain-steps", type=int, default=20,
+                    help="batched: steps timed on the plain path per chain length")
     ap.add_argument("--L", type=int, default=0)
     ap.add_argument("--dt", type=float, default=0.0, help="override the time step")
     ap.add_argument("--cpu-steps", type=int, default=-1,
@@ -168,6 +296,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     if args.copy_calibration:
         copy_calibration(args.copy_calibration << 20, max(1, args.steps))
+        return
+    if args.workload == "batched":
+        run_batched(args)
         return
     p, label, key = make_workload(args.workload, args.L)
     if args.dt:

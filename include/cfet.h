@@ -270,7 +270,8 @@ typedef struct {
   int32_t unroll;         /* launch layout chosen at create: rows per lane and pass */
   int32_t graph;          /* 1 if the last call replayed the step graph */
   int32_t reserved;
-  double tune_us[4];      /* create-time SpMM timing of the layouts 1, 2, 4, 8 */
+  double tune_us[4];      /* create-time timing (us) of one product and its reduction
+                             for 2, 4, 8 and 16 rows per lane and pass */
 } cfet_batch_stats_t;
 
 /* Build a batch.  ops: nops CSR matrices (host or device arrays, copied and

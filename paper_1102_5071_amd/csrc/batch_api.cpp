@@ -41,7 +41,7 @@ struct cfet_batch {
   std::vector<void*> allocs;       // operator arrays
   int64_t ntot = 0;
   int total_blocks = 0;
-  int max_blocks = 0;              // partial-sum capacity (blocks)
+  int64_t pstride = 0;             // partial sums per instance (most blocks of a group)
   int unroll = 1;                  // rows per lane and pass (autotuned)
   std::vector<double> tune_us;     // timing of each candidate (autotune)
   // workspace
@@ -75,7 +75,7 @@ namespace {
 
 thread_local std::string g_berr;
 
-constexpr int kTuneCandidates[] = {1, 2, 4, 8};
+constexpr int kTuneCandidates[] = {2, 4, 8, 16};
 constexpr size_t kWtsBudget = size_t(64) << 20;  // bytes of weights per upload chunk
 
 int bfail(cfet_batch* b, int code, const std::string& msg) {
@@ -137,6 +137,7 @@ BLaunch launch_of(const cfet_batch* b) {
   L.V = b->V;
   L.Y = b->Y;
   L.part = b->part;
+  L.pstride = b->pstride;
   L.S = b->S;
   L.st = b->st;
   return L;
@@ -178,8 +179,9 @@ hipError_t enqueue_step(const BLaunch& L, int m, int s_count, hipStream_t s) {
   return e;
 }
 
-// Time one SpMM launch per unroll candidate on the real operators and keep the
-// fastest layout (the candidates only change how many rows a block covers).
+// Time one Lanczos product (SpMM and the reduction of its partial sums) per
+// layout candidate on the real operators and keep the fastest; the candidates
+// change how many rows a block covers, and with it the number of partials.
 int autotune(cfet_batch* b) {
   hipError_t e = hipSuccess;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -199,6 +201,11 @@ int autotune(cfet_batch* b) {
   if (e == hipSuccess)
     e = hipMemcpy(b->S.inv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(b->S.done, 0, sizeof(int) * b->ninst);
+  {
+    std::vector<int> caps(size_t(b->ninst), cfet::kMaxM);  // no instance completes at k = 0
+    if (e == hipSuccess)
+      e = hipMemcpy(b->S.mcap, caps.data(), caps.size() * sizeof(int), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMemset(b->V, 0, sizeof(double2) * b->ntot);
   double best = 1e300;
   int best_u = 1;
@@ -212,8 +219,12 @@ int autotune(cfet_batch* b) {
     BLaunch L = launch_of(b);
     L.total_blocks = tb;
     e = cfet::batch_spmm(L, 0, nullptr);  // warm-up
+    if (e == hipSuccess) e = cfet::batch_scalars(L, cfet::kBAlpha, 0, nullptr);
     if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = cfet::batch_spmm(L, 0, nullptr);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+      e = cfet::batch_spmm(L, 0, nullptr);
+      if (e == hipSuccess) e = cfet::batch_scalars(L, cfet::kBAlpha, 0, nullptr);
+    }
     if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -367,8 +378,13 @@ CFET_API int cfet_batch_create(int32_t nops, const cfet_csr* ops, int32_t ninst,
   int64_t voff = 0;
   while (slot < ninst && rc == CFET_OK) {
     const Key key = order[slot].first;
-    int end = slot;
-    while (end < ninst && order[end].first == key && end - slot < cfet::kBatchMaxGroup) ++end;
+    // groups of a power-of-two size (at most 64): every lane of a wavefront
+    // serves an instance, and a row's B complex values fill whole cache lines
+    int same = slot;
+    while (same < ninst && order[same].first == key) ++same;
+    int take = 1;
+    while (take * 2 <= std::min(same - slot, cfet::kBatchMaxGroup)) take *= 2;
+    const int end = slot + take;
     const int t0 = order[slot].second;
     const int64_t n = mats[inst[t0].h0].n;
     const int sh = std::get<2>(key);
@@ -499,12 +515,13 @@ CFET_API int cfet_batch_create(int32_t nops, const cfet_csr* ops, int32_t ninst,
     return rc;
   }
   b->ntot = voff;
-  b->max_blocks = layout_blocks(b->groups, kTuneCandidates[0]);
+  layout_blocks(b->groups, kTuneCandidates[0]);
+  for (const auto& g : b->groups) b->pstride = std::max<int64_t>(b->pstride, g.nblocks);
   // per-slot state and workspace
   const size_t ns = size_t(ninst), nm = ns * cfet::kMaxM;
   e = dalloc(&b->d_groups, b->groups.size());
   if (e == hipSuccess) e = dalloc(&b->Y, size_t(b->ntot));
-  if (e == hipSuccess) e = dalloc(&b->part, size_t(b->max_blocks) * 64);
+  if (e == hipSuccess) e = dalloc(&b->part, size_t(ninst) * size_t(b->pstride));
   if (e == hipSuccess) e = dalloc(&b->st, 1);
   if (e == hipSuccess) e = dalloc(&b->d_uoff, ns);
   if (e == hipSuccess) e = dalloc(&b->S.alpha, nm);
@@ -539,7 +556,7 @@ CFET_API int cfet_batch_create(int32_t nops, const cfet_csr* ops, int32_t ninst,
     return rc;
   }
   if (flags & CFET_BATCH_NO_AUTOTUNE) {
-    b->unroll = 2;
+    b->unroll = 8;
   } else {
     rc = autotune(b);
     if (rc != CFET_OK) {

@@ -81,7 +81,8 @@ struct BLaunch {
   int64_t ntot;          // elements of one packed vector
   double2* V;            // basis: vector l at V + l * ntot (vector 0 = psi)
   double2* Y;            // H v_k
-  double* part;          // [total_blocks][64] partial sums
+  double* part;          // [slot][pstride] partial sums: instance slot, block of its group
+  int64_t pstride;
   BSlots S;
   BState* st;
 };

@@ -150,7 +150,7 @@ def test_split_calls_equal_one_call():
 
 
 def test_more_instances_than_one_group():
-    # 70 instances sharing sum sx of L = 3: split into groups of at most 64
+    # 70 instances sharing sum sx of L = 3: split into groups of at most 64 instances
     rng = np.random.default_rng(7)
     ops = [I.sigma_x_sum(3)]
     insts = []
@@ -162,7 +162,7 @@ def test_more_instances_than_one_group():
                       "psi0": I.random_state(8, rng)})
     ref, ref_mv = oracle_run(ops, insts, 0.0, 0.05, 5, "CF4:2", 8, 1e-10)
     out, mv, st = gpu_run(ops, insts, 0.0, 0.05, 5, "CF4:2", 8, 1e-10)
-    assert st["ngroups"] == 2
+    assert st["ngroups"] == 3          # power-of-two groups: 64 + 4 + 2
     for a, b in zip(out, ref):
         assert rel(a, b) <= TOL
     assert list(mv) == list(ref_mv)
