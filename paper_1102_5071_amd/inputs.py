@@ -423,5 +423,27 @@ def config_batched(n_traj: int = 256, L_min: int = 12, L_max: int = 18, seed: in
                  meta={"seed": seed, "L_min": L_min, "L_max": L_max})
 
 
+def config_adjoint(L: int = 14, K: int = 200, T: float = 20.0, dt: float = 0.01,
+                   seed: int = 0) -> Problem:
+    """Control problem for the fidelity gradient: Ising chain (J = 1,
+    h_i ~ U[-0.5, 0.5]) driven by sum sx with a piecewise-constant amplitude of
+    K equal pieces on [0, T], u_k ~ U[-1, 1]; psi0 = all up; target a
+    complex-Gaussian random state, normalised.  CF6:5Opt, dt = 0.01, m = 20.
+    Draw order: h, then u, then the target."""
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(-0.5, 0.5, L)
+    u = rng.uniform(-1.0, 1.0, K)
+    target = random_state(1 << L, rng)
+    H0 = ising_chain(L, 1.0, h)
+    H1 = sigma_x_sum(L)
+    edges = np.linspace(0.0, T, K + 1)
+    drives = [{"kind": "pwc", "t_edges": edges, "u": u}]
+    nsteps = int(round(T / dt))
+    return Problem(f"adjoint-ising-L{L}-K{K}", H0, [H1], drives, basis_state(1 << L, 0),
+                   scheme="CF6:5Opt", dt=dt, nsteps=nsteps, m=20,
+                   meta={"L": L, "K": K, "T": T, "h": h, "u": u, "target": target,
+                         "seed": seed})
+
+
 CONFIGS = {"ising": config_ising, "hydrogen": config_hydrogen,
            "heisenberg": config_heisenberg}
