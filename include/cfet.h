@@ -170,8 +170,27 @@ CFET_API int cfet_create(const cfet_csr *H0, int32_t nterms, const cfet_csr *Hk,
 CFET_API int cfet_propagate(cfet_ctx *c, void *psi_dev, double t0, double dt, int64_t nsteps,
                             int32_t scheme, int32_t krylov_m, void *hip_stream);
 
-/* Gradient of F = |<target|psi(T)>|^2 with respect to piecewise-constant drive
- * amplitudes.  Not implemented in this build: returns CFET_EUNSUPPORTED. */
+/* Gradient of the final-state fidelity F = |<target|psi_N>|^2, psi_N the
+ * state after nsteps CFET steps from psi0 (exactly the map of cfet_propagate:
+ * same scheme, time grid and Lanczos exponentials with krylov_m vectors), with
+ * respect to the amplitudes u[0..K-1] of the first driven term whose drive is
+ * piecewise constant (CFET_DRIVE_PWC with K pieces).  u == NULL: the
+ * amplitudes given at create; otherwise u (host, K finite values) replaces
+ * them for this call only.
+ * Method (adjoint of the discretised map): the weight of the term in
+ * exponential i of step n is b = sum_m g_{i,m} f(t_n + x_m dt) (Sec. 7), so
+ * db/du_p sums g_{i,m} over the Gauss points in piece p.  With the adjoint
+ * state lambda (phi propagated back by the conjugate exponentials) and the
+ * state psi before each exponential, its derivative is
+ * <lambda| L(Omega, -i dt H_k) |psi>, L the Frechet derivative of the
+ * exponential: the top-right block of exp([[Omega, D], [0, Omega]]), taken by
+ * projecting that block-triangular operator on the Lanczos spaces of lambda
+ * and psi (exact when the spaces are invariant).  The forward states are kept
+ * every ceil(sqrt(nsteps)) steps and recomputed segment by segment.
+ * psi0_dev, target_dev: complex128[n] device buffers (read only).  Writes
+ * *F_out and dFdu_out[0..K-1] (host) and synchronises hip_stream.  Device
+ * workspace O((sqrt(nsteps) s + 2 m) n), allocated for the call.  Needs the
+ * CSR layout (n <= 2^22; CFET_EUNSUPPORTED otherwise). */
 CFET_API int cfet_gradient(cfet_ctx *c, const void *psi0_dev, const void *target_dev, double t0,
                            double dt, int64_t nsteps, int32_t scheme, int32_t krylov_m,
                            const double *u, int32_t K, double *F_out, double *dFdu_out,

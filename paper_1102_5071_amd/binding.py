@@ -90,8 +90,8 @@ def load():
     lib.cfet_propagate.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int64, c_int32,
                                    c_int32, c_void_p]
     lib.cfet_gradient.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_double, c_int64,
-                                  c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
-                                  c_void_p]
+                                  c_int32, c_int32, c_void_p, c_int32, POINTER(c_double),
+                                  c_void_p, c_void_p]
     lib.cfet_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]
     lib.cfet_stats.argtypes = [c_void_p, POINTER(_Stats)]
     lib.cfet_destroy.argtypes = [c_void_p]
@@ -206,6 +206,7 @@ class Propagator:
             raise CfetError(code, lib.cfet_last_error(None).decode(errors="replace"))
         self._ctx = ctx
         self.n = int(H0.n)
+        self._pwc_pieces = next((len(d["u"]) for d in drives if d["kind"] == "pwc"), 0)
 
     # -- helpers ---------------------------------------------------------
     def _check_vec(self, v):
@@ -258,9 +259,31 @@ class Propagator:
     def profile(self, enable: bool, max_launches: int = 65536):
         _check(load().cfet_profile(self._ctx, 1 if enable else 0, int(max_launches)), self._ctx)
 
-    def gradient(self, *args, **kw):
-        _check(load().cfet_gradient(self._ctx, None, None, 0.0, 0.0, 0, 0, 1, None, 0, None, None,
-                                    None), self._ctx)
+    def gradient(self, psi0, target, t0: float, dt: float, nsteps: int, scheme, m: int,
+                 u=None, stream=None):
+        """(F, dF/du): fidelity |<target|psi_N>|^2 of the CFET run from psi0 and its
+        gradient with respect to the pieces of the piecewise-constant drive
+        (u: optional amplitudes replacing those of the drive for this call)."""
+        self._check_vec(psi0)
+        self._check_vec(target)
+        if u is None:
+            K = self.pwc_pieces()
+            uptr = None
+        else:
+            u = np.ascontiguousarray(u, dtype=np.float64)
+            K = len(u)
+            uptr = u.ctypes.data
+        F = c_double()
+        g = np.zeros(K)
+        _check(load().cfet_gradient(self._ctx, c_void_p(psi0.data_ptr()),
+                                    c_void_p(target.data_ptr()), float(t0), float(dt),
+                                    int(nsteps), scheme_id(scheme), int(m), uptr, int(K),
+                                    ctypes.byref(F), g.ctypes.data, _stream_handle(stream)),
+               self._ctx)
+        return F.value, g
+
+    def pwc_pieces(self) -> int:
+        return self._pwc_pieces
 
     def close(self):
         if getattr(self, "_ctx", None):
@@ -363,6 +386,41 @@ class BatchPropagator:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class _FidelityFn:
+    """torch.autograd.Function for F(u) = |<target|psi_N(u)>|^2 (built lazily so
+    that importing the binding does not import torch)."""
+    _cls = None
+
+    @classmethod
+    def get(cls):
+        if cls._cls is None:
+            import torch
+
+            class FidelityFunction(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, u, prop, psi0, target, t0, dt, nsteps, scheme, m):
+                    F, g = prop.gradient(psi0, target, t0, dt, nsteps, scheme, m,
+                                         u=u.detach().cpu().numpy())
+                    ctx.save_for_backward(torch.from_numpy(g).to(u.device, u.dtype))
+                    return u.new_tensor(F)
+
+                @staticmethod
+                def backward(ctx, gF):
+                    (g,) = ctx.saved_tensors
+                    return (gF * g,) + (None,) * 8
+
+            cls._cls = FidelityFunction
+        return cls._cls
+
+
+def fidelity(u, prop, psi0, target, t0: float, dt: float, nsteps: int, scheme, m: int):
+    """Differentiable F(u) = |<target|psi_N>|^2 for the piecewise-constant drive
+    amplitudes u (a float64 torch tensor, CPU or CUDA): the forward call runs
+    the CFET propagation and its adjoint on the GPU (cfet_gradient), backward
+    returns dF/du."""
+    return _FidelityFn.get().apply(u, prop, psi0, target, t0, dt, nsteps, scheme, m)
 
 
 def tridiag_expm(alpha, beta, dt: float, stream=None):

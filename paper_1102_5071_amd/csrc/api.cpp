@@ -328,6 +328,32 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
 
 }  // namespace
 
+namespace {
+
+// Device buffers of one cfet_gradient call (freed when the call returns).
+struct GradBuffers {
+  std::vector<void*> ptrs;
+  ~GradBuffers() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  hipError_t get(T** p, size_t count) {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+};
+
+// Piece of a piecewise-constant drive containing t, or -1 outside.
+int pwc_piece(const DriveSpec& d, double t) {
+  const std::vector<double>& e = d.edges;
+  if (e.size() < 2 || t < e.front() || t >= e.back()) return -1;
+  const size_t p = size_t(std::upper_bound(e.begin(), e.end(), t) - e.begin()) - 1;
+  return int(std::min(p, e.size() - 2));
+}
+
+}  // namespace
+
 extern "C" {
 
 int cfet_version(void) { return CFET_VERSION; }
@@ -737,9 +763,186 @@ int cfet_profile(cfet_ctx* c, int32_t enable, int32_t max_launches) {
   return CFET_OK;
 }
 
-int cfet_gradient(cfet_ctx* c, const void*, const void*, double, double, int64_t, int32_t,
-                  int32_t, const double*, int32_t, double*, double*, void*) {
-  return fail(c, CFET_EUNSUPPORTED, "cfet_gradient is not implemented in this build");
+int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, double t0,
+                  double dt, int64_t nsteps, int32_t scheme, int32_t krylov_m, const double* u,
+                  int32_t K, double* F_out, double* dFdu_out, void* hip_stream) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  if (!psi0_dev || !target_dev || !F_out) return fail(c, CFET_EINVAL, "null psi0, target or F");
+  if (K < 1 || !dFdu_out) return fail(c, CFET_EINVAL, "K must be >= 1 with an output array");
+  if (nsteps < 0) return fail(c, CFET_EINVAL, "nsteps < 0");
+  if (krylov_m < 1 || krylov_m > CFET_MAX_KRYLOV)
+    return fail(c, CFET_EINVAL, "krylov_m must be in 1..64");
+  if (!std::isfinite(t0) || !std::isfinite(dt)) return fail(c, CFET_EINVAL, "non-finite t0/dt");
+  SchemeTable sc;
+  if (!cfet::scheme_build(scheme, &sc)) return fail(c, CFET_EINVAL, "unknown scheme");
+  if (!is_device_ptr(psi0_dev) || !is_device_ptr(target_dev))
+    return fail(c, CFET_EINVAL, "psi0 and target must be device memory");
+  if (!c->A.rowptr)
+    return fail(c, CFET_EUNSUPPORTED, "cfet_gradient needs the CSR layout (dimension <= 2^22)");
+  int kstar = -1;
+  for (int k = 0; k < c->nterms && kstar < 0; ++k)
+    if (c->drives[k].kind == CFET_DRIVE_PWC) kstar = k;
+  if (kstar < 0) return fail(c, CFET_EINVAL, "no driven term has a piecewise-constant drive");
+  if (int(c->drives[kstar].u.size()) != K)
+    return fail(c, CFET_EINVAL, "K differs from the number of pieces of the drive");
+  std::vector<DriveSpec> dmod = c->drives;
+  if (u) {
+    for (int p = 0; p < K; ++p)
+      if (!std::isfinite(u[p])) return fail(c, CFET_EINVAL, "non-finite amplitude");
+    dmod[kstar].u.assign(u, u + K);
+  }
+  DeviceGuard g(c->device);
+  const int64_t n = c->n;
+  const int m = int(std::min<int64_t>(krylov_m, n));
+  int rc = ensure_workspace(c, m);
+  if (rc != CFET_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // the call propagates with the given amplitudes: swap them in for its duration
+  struct DriveSwap {
+    cfet_ctx* c;
+    std::vector<DriveSpec>& d;
+    DriveSwap(cfet_ctx* c_, std::vector<DriveSpec>& d_) : c(c_), d(d_) { std::swap(c->drives, d); }
+    ~DriveSwap() { std::swap(c->drives, d); }
+  } swap_guard(c, dmod);
+
+  const int64_t N = nsteps;
+  const int64_t seg = (N > 0) ? std::max<int64_t>(1, int64_t(std::ceil(std::sqrt(double(N))))) : 1;
+  const int64_t nseg = (N + seg - 1) / seg;
+  GradBuffers gb;
+  double2 *psi = nullptr, *lam = nullptr, *vpsi = nullptr, *vlam = nullptr, *ckpt = nullptr,
+          *before = nullptr, *cpart = nullptr, *cmat = nullptr, *dz = nullptr, *zval = nullptr,
+          *zpart = nullptr;
+  LzScalars *Spsi = nullptr, *Slam = nullptr;
+  const size_t nn = size_t(n);
+  hipError_t e = gb.get(&psi, nn);
+  if (e == hipSuccess) e = gb.get(&lam, nn);
+  if (e == hipSuccess) e = gb.get(&vpsi, size_t(std::max(m - 1, 1)) * nn);
+  if (e == hipSuccess) e = gb.get(&vlam, size_t(std::max(m - 1, 1)) * nn);
+  if (e == hipSuccess) e = gb.get(&ckpt, size_t(std::max<int64_t>(nseg, 1)) * nn);
+  if (e == hipSuccess) e = gb.get(&before, size_t(seg) * size_t(sc.s) * nn);
+  if (e == hipSuccess)
+    e = gb.get(&cpart, size_t(cfet::frechet_c_blocks(n)) * cfet::kMaxM * cfet::kMaxM);
+  if (e == hipSuccess) e = gb.get(&cmat, size_t(cfet::kMaxM) * cfet::kMaxM);
+  if (e == hipSuccess) e = gb.get(&dz, size_t(K));
+  if (e == hipSuccess) e = gb.get(&zval, 1);
+  if (e == hipSuccess) e = gb.get(&zpart, size_t(cfet::zdot_blocks(n)));
+  if (e == hipSuccess) e = gb.get(&Spsi, 1);
+  if (e == hipSuccess) e = gb.get(&Slam, 1);
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: workspace");
+  const size_t vb = nn * sizeof(double2);
+  // ---- forward pass, keeping psi at the start of every segment
+  e = hipMemcpyAsync(psi, psi0_dev, vb, hipMemcpyDeviceToDevice, st);
+  for (int64_t sg = 0; sg < nseg && e == hipSuccess; ++sg) {
+    e = hipMemcpyAsync(ckpt + size_t(sg) * nn, psi, vb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) break;
+    const int64_t s0 = sg * seg, len = std::min(seg, N - s0);
+    rc = cfet_propagate(c, psi, t0 + double(s0) * dt, dt, len, scheme, m, st);
+    if (rc != CFET_OK) return rc;
+  }
+  if (e == hipSuccess) e = cfet::launch_zdot(static_cast<const double2*>(target_dev), psi, n,
+                                             zpart, zval, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(lam, target_dev, vb, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = cfet::launch_zero2(dz, K, st);
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: forward pass");
+
+  // ---- backward sweep, one segment at a time
+  std::vector<double2*> Wf(cfet::kMaxM, nullptr), Wp(cfet::kMaxM, nullptr),
+      Wl(cfet::kMaxM, nullptr);
+  for (int j = 1; j < m; ++j) {
+    Wf[j] = c->h_W[j];
+    Wp[j] = vpsi + size_t(j - 1) * nn;
+    Wl[j] = vlam + size_t(j - 1) * nn;
+  }
+  cfet::ExpWork wf{}, wp{}, wl{};
+  wf.W_host = Wf.data();
+  wp.W_host = Wp.data();
+  wl.W_host = Wl.data();
+  wf.partA = wp.partA = wl.partA = c->partA;
+  wf.partB = wp.partB = wl.partB = c->partB;
+  wf.S = c->S;
+  wp.S = Spsi;
+  wl.S = Slam;
+  wf.stats = wp.stats = wl.stats = c->stats;
+  wf.sell = wp.sell = wl.sell = nullptr;
+  wf.events = wp.events = wl.events = nullptr;
+  const DriveSpec& dk = c->drives[kstar];
+  std::vector<double> a(sc.s), b(size_t(sc.s) * c->nterms);
+  struct ExpRec {
+    cfet::TermWeights tw;
+    int np;
+    int p[4];
+    double w[4];
+  };
+  std::vector<ExpRec> rec(size_t(seg) * sc.s);
+  Wl[0] = lam;
+  for (int64_t sg = nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
+    const int64_t s0 = sg * seg, s1 = std::min(N, s0 + seg);
+    e = hipMemcpyAsync(psi, ckpt + size_t(sg) * nn, vb, hipMemcpyDeviceToDevice, st);
+    Wf[0] = psi;
+    if (e == hipSuccess) e = cfet::launch_norm_start(psi, n, c->plan, c->partA, st);
+    size_t idx = 0;
+    for (int64_t q = s0; q < s1 && e == hipSuccess; ++q) {
+      const double tn = t0 + double(q) * dt;
+      cfet::step_weights(sc, c->drives, tn, dt, a.data(), b.data());
+      for (int i = sc.s - 1; i >= 0 && e == hipSuccess; --i, ++idx) {
+        ExpRec& r = rec[idx];
+        std::memset(&r.tw, 0, sizeof(r.tw));
+        r.tw.w[0] = a[i];
+        for (int k = 0; k < c->nterms; ++k) r.tw.w[k + 1] = b[size_t(i) * c->nterms + k];
+        r.np = 0;
+        for (int mm = 0; mm < sc.M; ++mm) {
+          const int p = pwc_piece(dk, tn + sc.x[mm] * dt);
+          if (p < 0) continue;
+          int slot = 0;
+          while (slot < r.np && r.p[slot] != p) ++slot;
+          if (slot == r.np) {
+            r.p[r.np] = p;
+            r.w[r.np] = 0.0;
+            r.np += 1;
+          }
+          r.w[slot] += sc.g[i][mm];
+        }
+        for (int z = r.np; z < 4; ++z) {
+          r.p[z] = 0;
+          r.w[z] = 0.0;
+        }
+        e = hipMemcpyAsync(before + idx * nn, psi, vb, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = cfet::launch_exponential(c->A, c->nterms, c->plan, r.tw, dt, m, wf, st);
+      }
+    }
+    for (size_t x = idx; x-- > 0 && e == hipSuccess;) {
+      const ExpRec& r = rec[x];
+      double2* pb = before + x * nn;
+      Wp[0] = pb;
+      e = cfet::launch_norm_start(pb, n, c->plan, c->partA, st);
+      if (e == hipSuccess) e = cfet::launch_lanczos(c->A, c->nterms, c->plan, r.tw, dt, m, wp, st);
+      if (e == hipSuccess) e = cfet::launch_norm_start(lam, n, c->plan, c->partA, st);
+      if (e == hipSuccess) e = cfet::launch_lanczos(c->A, c->nterms, c->plan, r.tw, -dt, m, wl, st);
+      if (e == hipSuccess)
+        e = cfet::launch_frechet_c(c->A, kstar + 1, pb, vpsi, lam, vlam, Spsi, Slam, cpart, cmat, st);
+      if (e == hipSuccess && r.np > 0)
+        e = cfet::launch_frechet_small(Spsi, Slam, cmat, dt, r.np, r.p, r.w, dz, c->stats, st);
+      if (e == hipSuccess) e = cfet::launch_combine(n, c->plan, wl, st);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: backward sweep");
+  std::vector<double2> hz(size_t(K) + 1);
+  e = hipMemcpyAsync(hz.data(), dz, sizeof(double2) * K, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hz[K], zval, sizeof(double2), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->stats_host, c->stats, sizeof(DevStats), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: results");
+  c->last_stream = st;
+  c->have_work = true;
+  const double2 z = hz[K];
+  *F_out = z.x * z.x + z.y * z.y;
+  for (int p = 0; p < K; ++p) dFdu_out[p] = 2.0 * (z.x * hz[p].x + z.y * hz[p].y);
+  if (c->stats_host->status != CFET_OK) {
+    const int code = c->stats_host->status;
+    return fail(c, code, "cfet_gradient: device fault (non-finite values or no convergence)");
+  }
+  return CFET_OK;
 }
 
 int cfet_stats(cfet_ctx* c, cfet_stats_t* s) {

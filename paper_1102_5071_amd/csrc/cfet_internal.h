@@ -130,7 +130,28 @@ hipError_t launch_norm_start(const double2* psi, int64_t n, const LaunchPlan& pl
 hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& plan,
                               const TermWeights& tw, double dt, int m, const ExpWork& wk,
                               hipStream_t st);
+// The exponential in two parts: the Lanczos recurrence with the small
+// exponential (basis W[1..], scalars S; W[0] is only read), then the
+// recombination W[0] <- sum_j coef_j W[j].
+hipError_t launch_lanczos(const DevCSR& A, int nterms, const LaunchPlan& plan,
+                          const TermWeights& tw, double dt, int m, const ExpWork& wk,
+                          hipStream_t st);
+hipError_t launch_combine(int64_t n, const LaunchPlan& plan, const ExpWork& wk, hipStream_t st);
 hipError_t launch_final_norm(const double* part, int np, DevStats* st_dev, hipStream_t st);
+
+// Fidelity gradient (grad.hip).
+int frechet_c_blocks(int64_t n);
+hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
+                            const double2* psi_rest, const double2* lam0, const double2* lam_rest,
+                            const LzScalars* Spsi, const LzScalars* Slam, double2* part,
+                            double2* C, hipStream_t st);
+hipError_t launch_frechet_small(const LzScalars* Spsi, const LzScalars* Slam, const double2* C,
+                                double dt, int npairs, const int* p, const double* w,
+                                double2* dz, DevStats* stats, hipStream_t st);
+int zdot_blocks(int64_t n);
+hipError_t launch_zdot(const double2* a, const double2* b, int64_t n, double2* part,
+                       double2* out, hipStream_t st);
+hipError_t launch_zero2(double2* p, int n, hipStream_t st);
 // Persistent propagation (persistent.hip): one launch for a whole call.
 constexpr int kPersistBlock = 512;  // threads per block of the persistent kernels
 

@@ -415,7 +415,7 @@ hipError_t launch_norm_start(const double2* psi, int64_t n, const LaunchPlan& pl
   return hipGetLastError();
 }
 
-hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& plan,
+hipError_t launch_lanczos(const DevCSR& A, int nterms, const LaunchPlan& plan,
                               const TermWeights& tw, double dt, int m, const ExpWork& wk,
                               hipStream_t st) {
   LzScalars* S = wk.S;
@@ -448,11 +448,21 @@ hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& pla
   }
   hipLaunchKernelGGL(k_lz_small, dim3(1), dim3(64), 0, st, wk.partB, plan.nb_spmv, S, m, dt,
                      wk.stats);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lz_combine, dim3(plan.nb_vec), dim3(kBlock), 0, st, wk.W_host[0],
-                     (const double2*)wk.W_host[1], A.n, S, wk.partA);
   return hipGetLastError();
+}
+
+hipError_t launch_combine(int64_t n, const LaunchPlan& plan, const ExpWork& wk, hipStream_t st) {
+  hipLaunchKernelGGL(k_lz_combine, dim3(plan.nb_vec), dim3(kBlock), 0, st, wk.W_host[0],
+                     (const double2*)wk.W_host[1], n, wk.S, wk.partA);
+  return hipGetLastError();
+}
+
+hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& plan,
+                              const TermWeights& tw, double dt, int m, const ExpWork& wk,
+                              hipStream_t st) {
+  const hipError_t e = launch_lanczos(A, nterms, plan, tw, dt, m, wk, st);
+  if (e != hipSuccess) return e;
+  return launch_combine(A.n, plan, wk, st);
 }
 
 hipError_t launch_final_norm(const double* part, int np, DevStats* st_dev, hipStream_t st) {

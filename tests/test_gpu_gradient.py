@@ -1,0 +1,142 @@
+"""GPU parity of the fidelity gradient (cfet_gradient) against the oracle
+(oracle.adjoint.fidelity_gradient), finite-difference checks of the GPU
+gradient against the GPU forward map, and the autograd wrapper.
+
+Bar: F to 1e-12 absolute, dF/du to 1e-10 in relative 2-norm, for the same
+scheme and Krylov dimension.  Finite differences: central, h = 1e-4 (see the
+oracle pins for the choice), 2e-8 of max |dF/du|.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as A
+from paper_1102_5071_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1102_5071_amd.binding")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    B.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.complex128)).to("cuda")
+
+
+def control_problem(L, K, T, seed, edges=None):
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(-0.5, 0.5, L)
+    u = rng.uniform(-1, 1, K)
+    if edges is None:
+        edges = np.linspace(0.0, T, K + 1)
+    H0 = I.ising_chain(L, 1.0, h)
+    H1 = I.sigma_x_sum(L)
+    drives = [{"kind": "pwc", "t_edges": np.asarray(edges, float), "u": u}]
+    return H0, [H1], drives, I.random_state(1 << L, rng), I.random_state(1 << L, rng)
+
+
+def gpu_grad(H0, Hk, drives, psi0, target, t0, dt, N, scheme, m, u=None, path=None):
+    with B.Propagator(H0, Hk, drives, path=path) as P:
+        F, g = P.gradient(dev(psi0), dev(target), t0, dt, N, scheme, m, u=u)
+        st = P.stats()
+    assert st["status"] == 0
+    return F, g
+
+
+@pytest.mark.parametrize("scheme,m", [("CF6:5Opt", 12), ("CF4:2", 16), ("CF8:11", 10)])
+def test_gradient_matches_oracle(scheme, m):
+    H0, Hk, drives, psi0, target = control_problem(5, 8, 0.4, 11)
+    N = 40
+    F, g = gpu_grad(H0, Hk, drives, psi0, target, 0.0, 0.01, N, scheme, m)
+    Fo, go = A.fidelity_gradient(H0, Hk, drives, psi0, target, 0.0, 0.01, N, scheme, m)
+    assert abs(F - Fo) < 1e-12
+    assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)
+
+
+def test_pieces_cutting_steps_and_ragged_segments():
+    # 23 steps (segments of 5: the last one short), edges inside steps
+    edges = [0.0, 0.0137, 0.05, 0.0731, 0.1, 0.2, 0.33, 0.47]
+    H0, Hk, drives, psi0, target = control_problem(4, 7, None, 12, edges=edges)
+    F, g = gpu_grad(H0, Hk, drives, psi0, target, 0.01, 0.02, 23, "CF4:2", 10)
+    Fo, go = A.fidelity_gradient(H0, Hk, drives, psi0, target, 0.01, 0.02, 23, "CF4:2", 10)
+    assert abs(F - Fo) < 1e-12
+    assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)
+
+
+def test_second_term_differentiated_with_general_hermitian_operators():
+    rng = np.random.default_rng(13)
+    n = 40
+    H0 = I.random_hermitian(n, rng, 0.3, 1.0)
+    H1 = I.random_hermitian(n, rng, 0.2, 0.5)
+    H2 = I.random_hermitian(n, rng, 0.2, 0.7)
+    drives = [{"kind": "cos", "A": 0.6, "omega": 1.7, "phi": 0.2},
+              {"kind": "pwc", "t_edges": np.linspace(0, 0.3, 7), "u": rng.uniform(-1, 1, 6)}]
+    psi0, target = I.random_state(n, rng), I.random_state(n, rng)
+    F, g = gpu_grad(H0, [H1, H2], drives, psi0, target, 0.0, 0.015, 20, "CF6:5Opt", 14)
+    Fo, go = A.fidelity_gradient(H0, [H1, H2], drives, psi0, target, 0.0, 0.015, 20,
+                                 "CF6:5Opt", 14, term=1)
+    assert abs(F - Fo) < 1e-12
+    assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)
+
+
+def test_amplitude_override_equals_drive_amplitudes():
+    H0, Hk, drives, psi0, target = control_problem(5, 6, 0.3, 14)
+    u2 = np.linspace(-0.8, 0.9, 6)
+    F1, g1 = gpu_grad(H0, Hk, drives, psi0, target, 0.0, 0.01, 30, "CF4:2", 12, u=u2)
+    d2 = [dict(drives[0], u=u2)]
+    F2, g2 = gpu_grad(H0, Hk, d2, psi0, target, 0.0, 0.01, 30, "CF4:2", 12)
+    assert F1 == F2 and np.array_equal(g1, g2)
+
+
+def _gpu_F(P, psi0, target, t0, dt, N, scheme, m):
+    x = dev(psi0)
+    P.propagate(x, t0, dt, N, scheme, m)
+    return abs(torch.vdot(dev(target), x).item()) ** 2
+
+
+def test_finite_differences_on_the_gpu():
+    H0, Hk, drives, psi0, target = control_problem(10, 20, 2.0, 15)
+    N, m, dt = 200, 20, 0.01
+    F, g = gpu_grad(H0, Hk, drives, psi0, target, 0.0, dt, N, "CF6:5Opt", m)
+    h = 1e-4
+    scale = np.max(np.abs(g))
+    for p in (0, 7, 19):
+        vals = []
+        for sgn in (+1, -1):
+            u = drives[0]["u"].copy()
+            u[p] += sgn * h
+            with B.Propagator(H0, Hk, [dict(drives[0], u=u)], path="multi") as P:
+                vals.append(_gpu_F(P, psi0, target, 0.0, dt, N, "CF6:5Opt", m))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[p]) <= 2e-8 * scale, (p, fd, g[p])
+
+
+def test_zero_steps_and_errors():
+    H0, Hk, drives, psi0, target = control_problem(3, 4, 0.2, 16)
+    F, g = gpu_grad(H0, Hk, drives, psi0, target, 0.0, 0.01, 0, "CF4:2", 6)
+    assert abs(F - abs(np.vdot(target, psi0)) ** 2) < 1e-14 and not g.any()
+    with B.Propagator(H0, Hk, drives) as P:
+        x = dev(psi0)
+        for bad in ([0.1, 0.2], [np.nan, 0, 0, 0]):
+            with pytest.raises(B.CfetError) as e:
+                P.gradient(x, x, 0.0, 0.01, 2, "CF4:2", 6, u=bad)
+            assert e.value.code == 1
+
+
+def test_autograd_function():
+    H0, Hk, drives, psi0, target = control_problem(6, 5, 0.25, 17)
+    with B.Propagator(H0, Hk, drives) as P:
+        u = torch.tensor(drives[0]["u"], dtype=torch.float64, requires_grad=True)
+        F = B.fidelity(u, P, dev(psi0), dev(target), 0.0, 0.01, 25, "CF6:5Opt", 12)
+        (2.0 * F).backward()
+        Fd, g = P.gradient(dev(psi0), dev(target), 0.0, 0.01, 25, "CF6:5Opt", 12)
+    assert abs(F.item() - Fd) == 0.0
+    assert np.array_equal(u.grad.numpy(), 2.0 * g)

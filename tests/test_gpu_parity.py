@@ -326,9 +326,9 @@ def test_error_codes():
             with pytest.raises(B.CfetError) as e:
                 P.propagate(psi, 0.0, 0.01, 1, "CF4:2", m)
             assert e.value.code == 1
-        with pytest.raises(B.CfetError) as e:
-            P.gradient()
-        assert e.value.code == 5
+        with pytest.raises(B.CfetError) as e:       # no piecewise-constant drive
+            P.gradient(psi, psi, 0.0, 0.01, 1, "CF4:2", 4, u=[0.1])
+        assert e.value.code == 1
         lib = B.load()
         code = lib.cfet_propagate(P._ctx, p.psi0.ctypes.data, 0.0, 0.01, 1, 1, 4, None)
         assert code == 1                              # host pointer rejected
