@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
-DEFAULT_CHUNK = {"hydrogen": 10, "ising": 50, "heisenberg": 1, "batched": 0}
+DEFAULT_CHUNK = {"hydrogen": 10, "ising": 50, "heisenberg": 1, "batched": 0, "adjoint": 0}
 
 
 def log(msg):
@@ -259,14 +259,105 @@ def run_batched(args):
     P.close()
 
 
+def run_adjoint(args):
+    """Fidelity gradient of a controlled Ising chain (L = 14, dim 16384): K = 200
+    piecewise-constant amplitudes on sum sx over T = 20, CF6:5Opt, dt = 0.01
+    (2000 steps), m = 20.  Reports gradient steps/s (steps of the forward map
+    per second of the whole gradient), the plain forward path on the same
+    problem, and central finite differences of a few components."""
+    import numpy as np
+    import torch
+    from paper_1102_5071_amd import binding as B
+    from paper_1102_5071_amd import inputs as I
+
+    p = I.config_adjoint(L=args.L or 14)
+    N = p.nsteps if not args.steps_override else args.steps_override
+    label = (f"adjoint ising L={p.meta['L']} dim={p.dim} K={p.meta['K']} T={N * p.dt:g} "
+             f"CF6:5Opt dt={p.dt} m={p.m}")
+    log(f"workload {label}, {N} steps")
+    P = B.Propagator(p.H0, p.Hk, p.drives)
+    psi0 = torch.from_numpy(p.psi0).to("cuda")
+    target = torch.from_numpy(p.meta["target"]).to("cuda")
+    F, g = P.gradient(psi0, target, 0.0, p.dt, min(N, 10), p.scheme, p.m)   # warm-up
+    reps = max(1, args.grad_reps)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        F, g = P.gradient(psi0, target, 0.0, p.dt, N, p.scheme, p.m)
+    elapsed = (time.perf_counter() - t) / reps
+    rate = N / elapsed
+    log(f"gradient: {elapsed:.3f} s for {N} steps -> {rate:.1f} steps/s; F = {F:.6e}, "
+        f"|dF/du| = {np.linalg.norm(g):.3e}")
+    x = psi0.clone()
+    P.propagate(x, 0.0, p.dt, 10, p.scheme, p.m)
+    torch.cuda.synchronize()
+    x = psi0.clone()
+    t = time.perf_counter()
+    P.propagate(x, 0.0, p.dt, N, p.scheme, p.m)
+    torch.cuda.synchronize()
+    el_f = time.perf_counter() - t
+    path = B.PATH_NAMES[P.stats()["path"]]
+    log(f"plain forward ({path} path): {el_f * 1e3:.1f} ms -> {N / el_f:.1f} steps/s; "
+        f"gradient / forward time = {elapsed / el_f:.2f}")
+    # central differences of a few components with the GPU forward map
+    h = 1e-4
+    fd_err = 0.0
+    scale = float(np.max(np.abs(g)))
+    for q in (0, p.meta["K"] // 2, p.meta["K"] - 1):
+        vals = []
+        for sgn in (+1, -1):
+            u = p.drives[0]["u"].copy()
+            u[q] += sgn * h
+            Pq = B.Propagator(p.H0, p.Hk, [dict(p.drives[0], u=u)])
+            y = psi0.clone()
+            Pq.propagate(y, 0.0, p.dt, N, p.scheme, p.m)
+            vals.append(abs(torch.vdot(target, y).item()) ** 2)
+            Pq.close()
+        fd = (vals[0] - vals[1]) / (2 * h)
+        fd_err = max(fd_err, abs(fd - g[q]) / scale)
+    log(f"finite differences (h = 1e-4, 3 components): max error {fd_err:.2e} of max |dF/du|")
+    cpu = None
+    if args.cpu_steps != 0:
+        from oracle import adjoint as OA
+        try:
+            from threadpoolctl import threadpool_limits
+            threadpool_limits(limits=1)
+        except Exception:       # pragma: no cover
+            pass
+        n_cpu = 4 if args.cpu_steps < 0 else args.cpu_steps
+        tt = time.perf_counter()
+        OA.fidelity_gradient(p.H0, p.Hk, p.drives, p.psi0, p.meta["target"], 0.0, p.dt, n_cpu,
+                             p.scheme, p.m)
+        el = time.perf_counter() - tt
+        cpu = {"value": round(n_cpu / el, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"gradient over the first {n_cpu} steps ({el:.1f} s, numpy/scipy FP64)"}
+        log(f"oracle gradient: {n_cpu / el:.3f} steps/s")
+    out = {
+        "metric": "CFET gradient steps/s (adjoint, fidelity wrt 200 drive amplitudes)",
+        "value": round(rate, 3), "unit": "steps/s", "n_gpus": 1, "steps": N,
+        "warmup": 1, "ms_per_step": round(elapsed * 1e3 / N, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": label, "plain_forward_steps_per_s": round(N / el_f, 3),
+                   "gradient_over_forward_time": round(elapsed / el_f, 3),
+                   "fd_max_rel_error": fd_err, "F": F},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    P.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="hydrogen",
-                    choices=["hydrogen", "ising", "heisenberg", "batched"])
+                    choices=["hydrogen", "ising", "heisenberg", "batched", "adjoint"])
     ap.add_argument("--ntraj", type=int, default=256, help="batched: number of trajectories")
+    ap.add_argument("--grad-reps", type=int, default=1, help="adjoint: timed gradient calls")
+    ap.add_argument("--steps-override", type=int, default=0,
+                    help="adjoint: steps of the control window (default T/dt)")
     ap.add_argument("--plain-steps", type=int, default=20,
                     help="batched: steps timed on the plain path per chain length")
     ap.add_argument("--L", type=int, default=0)
@@ -299,6 +390,9 @@ def main():
         return
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "adjoint":
+        run_adjoint(args)
         return
     p, label, key = make_workload(args.workload, args.L)
     if args.dt:
