@@ -53,6 +53,7 @@ constexpr Preset kSinglePresets[] = {{1, 2, 12}, {2, 2, 8}, {4, 2, 8}};
 constexpr int kNumCoopPresets = sizeof(kCoopPresets) / sizeof(kCoopPresets[0]);
 constexpr int kNumSinglePresets = sizeof(kSinglePresets) / sizeof(kSinglePresets[0]);
 constexpr int kSingleMaxRows = 1024;
+constexpr int kCoopMaxRows = kPersistBlock;  // rows of one cooperative block (G = 1, P = 1)
 
 // One DPP step of the wavefront sum: v + (v moved by the DPP pattern), rows
 // outside row_mask add 0.
@@ -281,8 +282,10 @@ template <int G, int PMAX, int QMAX, int NT, bool SINGLE>
 __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
   constexpr int BLOCK = kPersistBlock;
   __shared__ Shared sh;
-  // single workgroup: u_k ring (k mod 3) and z_k ring (k mod 2) in LDS
-  constexpr int LN = SINGLE ? kSingleMaxRows : 1;
+  // u_k ring (k mod 3) and z_k ring (k mod 2) of this block's own rows in LDS,
+  // indexed by row - r0: the single workgroup reads every gathered value from
+  // here, the cooperative blocks the entries whose column is one of their own rows
+  constexpr int LN = SINGLE ? kSingleMaxRows : kCoopMaxRows;
   __shared__ double2 lu[3][LN];
   __shared__ double2 lz[2][LN];
   const int nb = gridDim.x;
@@ -310,6 +313,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
   int cnt[PMAX];
   uint32_t ccol[PMAX][QMAX];
   double2 cval[PMAX][QMAX];
+  uint32_t lmask[PMAX];  // bit q: entry q's column is a row of this block (read from LDS)
 #pragma unroll
   for (int p = 0; p < PMAX; ++p) {
     const int64_t row = r0 + grp + (int64_t)p * NGRP;
@@ -332,6 +336,12 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
     }
     tail_beg[p] = beg + (int64_t)QMAX * G + lane;
     tail_end[p] = end;
+    lmask[p] = 0u;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int64_t c = ccol[p][q] & kColMask;
+      if (SINGLE || (c >= r0 && c < r1)) lmask[p] |= (1u << q);
+    }
     const int64_t len = end - beg;
     cnt[p] = (len > lane) ? (int)min<int64_t>(QMAX, (len - lane + G - 1) / G) : 0;
   }
@@ -355,7 +365,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
     for (int p = 0; p < PMAX; ++p) {
 #pragma unroll
       for (int q = 0; q < QMAX; ++q) {
-        if (rowp[p] >= 0 && q < cnt[p]) {
+        if (rowp[p] >= 0 && q < cnt[p] && !((lmask[p] >> q) & 1u)) {
           const int64_t c = ccol[p][q] & kColMask;
           g1[p][q] = vld<SINGLE>(a1, c, n);
           if (k >= 1) gz[p][q] = vld<SINGLE>(az, c, n);
@@ -379,29 +389,43 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
       double nu0 = 0.0;
       double c1 = 0.0, c2 = 0.0, c3 = 0.0;
       double S1 = 0.0, S2 = 0.0;  // block sums of <u, z> and ||u||^2 of the last phase
-      if (SINGLE) {
+      double scale = 0.0, alpha_prev = 0.0, inv_prev = 0.0;
+      // u_0 = psi on the own rows (the previous exponential's barrier or the
+      // weights' __syncthreads above ended every read of the ring)
 #pragma unroll
-        for (int p = 0; p < PMAX; ++p)
-          if (lane == 0 && rowp[p] >= 0) lu[0][rowp[p]] = u1[p];
-        __syncthreads();
-      }
+      for (int p = 0; p < PMAX; ++p)
+        if (lane == 0 && rowp[p] >= 0) lu[0][rowp[p] - r0] = u1[p];
+      __syncthreads();
       gather(0);
       for (int k = 0; k <= m; ++k) {
         if (k >= 1) {
           tm.lap(A.stats, 1);
           // ---- reduction of phase k-1; the gathers of phase k fly meanwhile
           if (!SINGLE) {
-            const double* P = A.part + (size_t)((pc - 1) & 1) * 2 * gridDim.x;
+            // wave 0 re-sums the block partials in a fixed order (the same in
+            // every block); the loads are issued before the gathers so that
+            // waiting for them does not wait for the gathers
             double sa = 0.0, sb = 0.0;
-            for (int t = threadIdx.x; t < (int)gridDim.x; t += blockDim.x) {
-              sa += dload(P + 2 * t);
-              sb += dload(P + 2 * t + 1);
+            if (threadIdx.x < 64) {
+              const double* P = A.part + (size_t)((pc - 1) & 1) * 2 * gridDim.x;
+              for (int t = threadIdx.x; t < (int)gridDim.x; t += 64) {
+                sa += dload(P + 2 * t);
+                sb += dload(P + 2 * t + 1);
+              }
             }
-            S1 = sa;
-            S2 = sb;
+            if (k < m) gather(k);
+            if (threadIdx.x < 64) {
+              sa = p_wave_sum(sa);
+              sb = p_wave_sum(sb);
+              if (threadIdx.x == 0) {
+                sh.red[16] = sa;
+                sh.red[17] = sb;
+              }
+            }
+            __syncthreads();
+            S1 = sh.red[16];
+            S2 = sh.red[17];
           }
-          if (k < m) gather(k);
-          if (!SINGLE) p_block_sum2(S1, S2, sh.red);
           const double nu = sqrt(S2);
           if (k == 1) {
             nu0 = nu;
@@ -410,31 +434,28 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
               break;
             }
           } else {
-            // beta_{k-2} = nu_{k-1}: early-stop rule of the recurrence
-            double sc = 0.0;
-            for (int t = 0; t < k - 2; ++t) sc = fmax(sc, fabs(sh.alpha[t]) + sh.beta[t]);
-            sc = fmax(sc, fabs(sh.alpha[k - 2]) + nu);
-            __syncthreads();
+            // beta_{k-2} = nu_{k-1}: early-stop rule of the recurrence, with the
+            // running max over t <= k-2 of |alpha_t| + beta_t
+            scale = fmax(scale, fabs(alpha_prev) + nu);
             if (threadIdx.x == 0) sh.beta[k - 2] = nu;
-            __syncthreads();
-            if (nu <= kBreakdownRel * sc) {
+            if (nu <= kBreakdownRel * scale) {
               meff = k - 1;
               break;
             }
           }
           const double inv = 1.0 / nu;
           const double alpha = S1 * inv * inv;
-          __syncthreads();
           if (threadIdx.x == 0) {
             sh.alpha[k - 1] = alpha;
             sh.inv[k - 1] = inv;
           }
-          __syncthreads();
-          if (k == m) break;
           // u_k = (z_{k-1} - alpha_{k-1} u_{k-1})/nu_{k-1} - (nu_{k-1}/nu_{k-2}) u_{k-2}
+          c3 = (k >= 2) ? nu * inv_prev : 0.0;
+          inv_prev = inv;
+          alpha_prev = alpha;
+          if (k == m) break;
           c1 = inv;
           c2 = alpha * inv;
-          c3 = (k >= 2) ? nu * sh.inv[k - 2] : 0.0;
         }
         // ---- phase k: u_k on own rows, z_k = H_w u_k, partial sums
         double2* __restrict__ uk = U(k);
@@ -449,7 +470,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           if (k >= 1 && lane == 0 && rowp[p] >= 0) {
             ucur = form_u(zp[p], u1[p], u2[p], c1, c2, c3);
             vst<SINGLE>(uk, rowp[p], n, ucur);
-            if (SINGLE) lu[k % 3][rowp[p]] = ucur;
+            lu[k % 3][rowp[p] - r0] = ucur;
           }
           double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
           if (rowp[p] >= 0) {
@@ -459,8 +480,8 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
                 const uint32_t ct = ccol[p][q];
                 const double2 v = cval[p][q];
                 double2 xg1, xgz, xg2;
-                if (SINGLE) {
-                  const int c = (int)(ct & kColMask);
+                if ((lmask[p] >> q) & 1u) {
+                  const int c = (int)((int64_t)(ct & kColMask) - r0);
                   xg1 = lu[(k + 2) % 3][c];                        // u_{k-1} (u_0 at k = 0)
                   xgz = (k >= 1) ? lz[(k + 1) & 1][c] : make_double2(0.0, 0.0);
                   xg2 = (k >= 2) ? lu[(k + 1) % 3][c] : make_double2(0.0, 0.0);
@@ -528,8 +549,8 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           }
           if (lane == 0 && rowp[p] >= 0) {
             const double2 zv = make_double2(yr, yi);
-            if (SINGLE) lz[k & 1][rowp[p]] = zv;
-            else if (k + 1 < m) vst<SINGLE>(zk, rowp[p], n, zv);
+            lz[k & 1][rowp[p] - r0] = zv;
+            if (!SINGLE && k + 1 < m) vst<SINGLE>(zk, rowp[p], n, zv);
             s_uz += ucur.x * zv.x + ucur.y * zv.y;
             s_uu += ucur.x * ucur.x + ucur.y * ucur.y;
             u2[p] = u1[p];
@@ -538,15 +559,29 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           }
         }
         tm.lap(A.stats, 0);
-        p_block_sum2(s_uz, s_uu, sh.red);
         if (SINGLE) {
+          p_block_sum2(s_uz, s_uu, sh.red);
           S1 = s_uz;
           S2 = s_uu;
         } else {
+          // wave sums to LDS, thread 0 adds them in order and publishes the
+          // block partial (the barrier's own __syncthreads follows)
+          s_uz = p_wave_sum(s_uz);
+          s_uu = p_wave_sum(s_uu);
+          if ((threadIdx.x & 63) == 0) {
+            sh.red[threadIdx.x >> 6] = s_uz;
+            sh.red[8 + (threadIdx.x >> 6)] = s_uu;
+          }
+          __syncthreads();
           double* P = A.part + (size_t)(pc & 1) * 2 * gridDim.x;
           if (threadIdx.x == 0) {
-            dstore(P + 2 * blockIdx.x, s_uz);
-            dstore(P + 2 * blockIdx.x + 1, s_uu);
+            double ta = 0.0, tb = 0.0;
+            for (int wv = 0; wv < BLOCK / 64; ++wv) {
+              ta += sh.red[wv];
+              tb += sh.red[8 + wv];
+            }
+            dstore(P + 2 * blockIdx.x, ta);
+            dstore(P + 2 * blockIdx.x + 1, tb);
           }
           if (!grid_barrier(A.bar, A.fault, epoch, A.spin_limit, &sh.ok)) {
             ok = false;
