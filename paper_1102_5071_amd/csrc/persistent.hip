@@ -263,18 +263,41 @@ __device__ __forceinline__ bool all_reduce2(double& a, double& b, const PersistA
 }
 
 // Segment timer (block 0, thread 0, only when A.timing is set).
+// Accumulated in registers and written once at the end of the launch, so that
+// timing adds no memory round trip to the path it measures.
 struct SegTimer {
   long long last;
+  long long acc[4];
   bool on;
   __device__ void start(bool enable) {
     on = enable && blockIdx.x == 0 && threadIdx.x == 0;
+    acc[0] = acc[1] = acc[2] = acc[3] = 0;
     if (on) last = wall_clock64();
   }
-  __device__ void lap(DevStats* st, int seg) {
+  __device__ void lap(DevStats*, int seg) {
     if (!on) return;
     const long long t = wall_clock64();
-    st->seg[seg] += t - last;
+    acc[seg] += t - last;
     last = t;
+  }
+  __device__ void flush(DevStats* st) {
+    if (!on) return;
+    for (int i = 0; i < 4; ++i) st->seg[i] += acc[i];
+  }
+};
+
+// Statistics of the launch, kept by thread 0 of block 0 and added to the
+// device statistics once at the end.
+struct LaunchStats {
+  unsigned long long expo = 0, mv = 0;
+  int minm = 1 << 30, brk = 0, status = CFET_OK;
+  __device__ void flush(DevStats* st) {
+    if (expo == 0) return;
+    st->exponentials += expo;
+    st->matvecs += mv;
+    if (minm < st->min_m_eff) st->min_m_eff = minm;
+    st->breakdowns += brk;
+    if (status != CFET_OK && st->status == CFET_OK) st->status = status;
   }
 };
 
@@ -377,6 +400,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
 
   SegTimer tm;
   tm.start(A.timing != 0);
+  LaunchStats ls;
   for (int64_t step = 0; ok && step < A.nsteps; ++step) {
     for (int i = A.s - 1; ok && i >= 0; --i) {
       if (threadIdx.x < nt1)
@@ -593,9 +617,9 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
       if (!ok) break;
       if (zero) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-          A.stats->exponentials += 1;
-          A.stats->breakdowns += 1;
-          A.stats->min_m_eff = 0;
+          ls.expo += 1;
+          ls.brk += 1;
+          ls.minm = 0;
         }
         continue;
       }
@@ -617,13 +641,11 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           sh.coef[l] = make_double2(c.x * scl, c.y * scl);
         }
         if (l == 0 && blockIdx.x == 0) {
-          DevStats* st = A.stats;
-          st->exponentials += 1;
-          st->matvecs += (unsigned long long)meff;
-          if (meff < st->min_m_eff) st->min_m_eff = meff;
-          if (meff < m) st->breakdowns += 1;
-          if (status != CFET_OK && st->status == CFET_OK) st->status = status;
-          st->last_norm2 = beta0 * beta0;
+          ls.expo += 1;
+          ls.mv += (unsigned long long)meff;
+          if (meff < ls.minm) ls.minm = meff;
+          if (meff < m) ls.brk += 1;
+          if (status != CFET_OK && ls.status == CFET_OK) ls.status = status;
         }
       }
       __syncthreads();
@@ -633,7 +655,20 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
       for (int p = 0; p < PMAX; ++p) {
         if (lane == 0 && rowp[p] >= 0) {
           double accr = 0.0, acci = 0.0;
-          for (int kk = 0; kk < meff; ++kk) {
+          int kk = 0;
+          // eight basis entries in flight at a time, summed in order
+          for (; kk + 8 <= meff; kk += 8) {
+            double2 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = vld<SINGLE>(U(kk + q), rowp[p], n);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const double2 cf = sh.coef[kk + q];
+              accr += cf.x * v[q].x - cf.y * v[q].y;
+              acci += cf.x * v[q].y + cf.y * v[q].x;
+            }
+          }
+          for (; kk < meff; ++kk) {
             const double2 v = vld<SINGLE>(U(kk), rowp[p], n);
             const double2 cf = sh.coef[kk];
             accr += cf.x * v.x - cf.y * v.y;
@@ -673,6 +708,10 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
       }
     }
     if (ok && blockIdx.x == 0 && threadIdx.x == 0 && A.nsteps > 0) A.stats->last_norm2 = s1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ls.flush(A.stats);
+    tm.flush(A.stats);
   }
   if (!ok && threadIdx.x == 0) {
     // a barrier timed out somewhere: latch a device error

@@ -149,15 +149,22 @@ __device__ __forceinline__ double wave_min(double v) {
 // Number of eigenvalues of T below x (Sylvester inertia of the LDL^T
 // factorisation of T - x I); x may differ per lane.
 __device__ inline int sturm_count(double a, double b, int k, double x) {
+  // q_r = det(T_r - x I) = (a_r - x) q_{r-1} - b_{r-1}^2 q_{r-2}, q_0 = 1: the
+  // count is the number of sign changes along q_0..q_k (no division: both
+  // terms are rescaled together when |q_r| leaves [1e-100, 1e100]; an exact
+  // zero takes the sign opposite to its predecessor)
   int cnt = 0;
-  double d = 1.0;
-  double bprev = 0.0;
+  double q = 1.0, qp = 0.0;
   for (int r = 0; r < k; ++r) {
     const double ar = lane_read(a, r);
-    d = (ar - x) - ((r > 0) ? bprev * bprev / d : 0.0);
-    if (d == 0.0) d = -1e-300;
-    cnt += (d < 0.0) ? 1 : 0;
-    bprev = lane_read(b, r);
+    const double br = (r > 0) ? lane_read(b, r - 1) : 0.0;
+    double qn = (ar - x) * q - (br * br) * qp;
+    if (qn == 0.0) qn = (q < 0.0) ? 1e-300 : -1e-300;
+    cnt += ((qn < 0.0) != (q < 0.0)) ? 1 : 0;
+    const double aq = fabs(qn);
+    const double sc = (aq > 1e100) ? 1e-100 : ((aq < 1e-100) ? 1e100 : 1.0);
+    qp = q * sc;
+    q = qn * sc;
   }
   return cnt;
 }
@@ -175,6 +182,9 @@ constexpr double kChebMaxTheta = 7000.0; // beyond this the QR path is cheaper
 __device__ inline int tridiag_exp_e1_cheb(double a, double b, int k, double dt, double* lds,
                                           double2& c) {
   const int lane = threadIdx.x & 63;
+  // k and the term counts are the same in every lane: keep them (and the loops
+  // over them) scalar so that the recurrences below run without exec masking
+  k = __builtin_amdgcn_readfirstlane(k);
   if (lane >= k - 1) b = 0.0;
   if (lane >= k) a = 0.0;
   const double bl = from_lane_below(b);      // b_{r-1}
@@ -216,62 +226,100 @@ __device__ inline int tridiag_exp_e1_cheb(double a, double b, int k, double dt, 
     c = (lane == 0) ? make_double2(cs, -sn) : make_double2(0.0, 0.0);
     return 0;
   }
-  const int N = (int)ceil(theta + 12.0 * cbrt(theta) + 20.0);
-  const int Nm = N + 30;
-  // Miller: f_{Nm+1} = 0, f_{Nm} = tiny, f_{j-1} = (2j/theta) f_j - f_{j+1}
-  double f1 = 0.0, f0 = 1e-30, S = 0.0;
-  const double it2 = 2.0 / theta;
-  for (int j = Nm; j >= 1; --j) {
-    if (j <= N) {
-      if (lane == 0) lds[j] = f0;
-      if ((j & 1) == 0) S += 2.0 * f0;
-    }
-    const double fm = (double)j * it2 * f0 - f1;
-    f1 = f0;
-    f0 = fm;
-    if (fabs(f0) > 1e200) {  // rescale everything computed so far
-      f0 *= 1e-200;
-      f1 *= 1e-200;
-      S *= 1e-200;
-      if (lane == 0)
-        for (int q = j; q <= N; ++q) lds[q] *= 1e-200;
-    }
-  }
-  if (lane == 0) lds[0] = f0;
-  S += f0;
-  wave_sync();
-  // forward Chebyshev recurrence on the real vectors t_k = T_k(X) e_1
   const double inv_h = 1.0 / h;
   const double ax = (lane < k) ? (a - sigma) * inv_h : 0.0;
   const double blo = bl * inv_h, bhi = b * inv_h;
+  if (theta < 1e-6) {
+    // exp(-i s X) e_1 = e_1 - i s X e_1 - (s^2 / 2) X^2 e_1 + O(s^3), s = dt h
+    const double sx = dt * h;
+    const double e1 = (lane == 0) ? 1.0 : 0.0;
+    const double x1 = ax * e1 + blo * from_lane_below(e1) + bhi * from_lane_above(e1);
+    const double x2 = ax * x1 + blo * from_lane_below(x1) + bhi * from_lane_above(x1);
+    const double cr = e1 - 0.5 * sx * sx * x2, ci = -sx * x1;
+    c = (lane < k) ? make_double2(cs * cr + sn * ci, cs * ci - sn * cr) : make_double2(0.0, 0.0);
+    return 0;
+  }
+  const int N = __builtin_amdgcn_readfirstlane((int)ceil(theta + 12.0 * cbrt(theta) + 20.0));
+  // Miller: f_{Nm+1} = 0, f_{Nm} = tiny, f_{j-1} = (2j/theta) f_j - f_{j+1}, with
+  // Nm >= N + 30 a multiple of 16.  Every lane runs the same scalar recurrence;
+  // lane (j mod 64) keeps f_j and each completed run of 64 values is stored with
+  // one LDS write per lane.  The recurrence runs in unrolled chunks of 16 steps
+  // without branches on its critical path (|f| grows by at most 2 Nm/theta + 1
+  // <= 1e8 per step here, so a rescale test after each chunk at 1e150 cannot be
+  // overtaken by an overflow); the coefficient j (2/theta) of the next step is
+  // formed one step ahead.
+  const int Nm = (N + 30 + 15) & ~15;
+  double f1 = 0.0, f0 = 1e-30, S = 0.0;
+  const double it2 = 2.0 / theta;
+  double mine = 0.0;
+  double jt = (double)Nm * it2;
+  for (int j0 = Nm; j0 >= 16; j0 -= 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = j0 - u;
+      const double jn = (double)(j - 1) * it2;
+      const int pick = (j <= N) ? (j & 63) : 64;     // lane that keeps f_j (64: none)
+      mine = (lane == pick) ? f0 : mine;
+      // the run j .. j + 63 is complete (j0 is a multiple of 16: only u = 0 can
+      // be a multiple of 64)
+      if (u == 0 && j <= N && (j & 63) == 0) lds[j + lane] = mine;
+      const double fm = jt * f0 - f1;
+      f1 = f0;
+      f0 = fm;
+      jt = jn;
+    }
+    if (__builtin_amdgcn_readfirstlane(fabs(f0) > 1e150 ? 1 : 0)) {  // rescale all so far (rare)
+      f0 *= 1e-200;
+      f1 *= 1e-200;
+      mine *= 1e-200;
+      for (int q = (j0 - 15 + 63) & ~63; q <= N; q += 64) lds[q + lane] *= 1e-200;
+    }
+  }
+  // the lowest run 0 .. 63 (f_0 now in f0)
+  mine = (lane == 0) ? f0 : mine;
+  lds[lane] = mine;
+  wave_sync();
+  // normalisation J_0 + 2 sum_{k >= 1} J_2k = 1, summed from the stored values
+  // (each lane over its column, then across lanes in a fixed order)
+  for (int q = 0; q <= N; q += 64) {
+    const int jj = q + lane;
+    if (jj <= N && ((jj & 1) == 0)) S += (jj == 0 ? 1.0 : 2.0) * lds[jj];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) S += __shfl_xor(S, off, 64);
+  // forward Chebyshev recurrence on the real vectors t_k = T_k(X) e_1:
+  // t_{k+1} = 2 X t_k - t_{k-1}, with the diagonal term first so that the
+  // neighbour exchange overlaps it
+  const double a2 = 2.0 * ax, b2lo = 2.0 * blo, b2hi = 2.0 * bhi;
   const double sgn = (dt >= 0.0) ? -1.0 : 1.0;   // phase (sgn i)^k
   double tp = (lane == 0) ? 1.0 : 0.0;           // t_0
   double cr = lds[0] * tp, ci = 0.0;
   double t = ax * tp + blo * from_lane_below(tp) + bhi * from_lane_above(tp);  // t_1
   ci += 2.0 * sgn * lds[1] * t;
+  auto next = [&](double cur, double prev) {
+    const double lo = from_lane_below(cur), hi = from_lane_above(cur);
+    double r = a2 * cur - prev;
+    r = b2lo * lo + r;
+    return b2hi * hi + r;
+  };
   // four terms per iteration: j = 2 mod 4 at the top, so the phases (sgn i)^j
   // are -1, -sgn i, +1, +sgn i; the four Bessel values are read together
   int j = 2;
   for (; j + 3 <= N; j += 4) {
     const double J0 = lds[j], J1 = lds[j + 1], J2 = lds[j + 2], J3 = lds[j + 3];
-    double xt = ax * t + blo * from_lane_below(t) + bhi * from_lane_above(t);
-    double tn = 2.0 * xt - tp;
+    const double tn = next(t, tp);
     cr -= 2.0 * J0 * tn;
-    xt = ax * tn + blo * from_lane_below(tn) + bhi * from_lane_above(tn);
-    tp = 2.0 * xt - t;
+    tp = next(tn, t);
     ci -= sgn * 2.0 * J1 * tp;
-    xt = ax * tp + blo * from_lane_below(tp) + bhi * from_lane_above(tp);
-    t = 2.0 * xt - tn;
+    t = next(tp, tn);
     cr += 2.0 * J2 * t;
-    xt = ax * t + blo * from_lane_below(t) + bhi * from_lane_above(t);
-    tn = 2.0 * xt - tp;
-    ci += sgn * 2.0 * J3 * tn;
+    const double t4 = next(t, tp);
+    ci += sgn * 2.0 * J3 * t4;
     tp = t;
-    t = tn;
+    t = t4;
   }
   for (; j <= N; ++j) {
-    const double xt = ax * t + blo * from_lane_below(t) + bhi * from_lane_above(t);
-    const double tn = 2.0 * xt - tp;
+    const double tn = next(t, tp);
     tp = t;
     t = tn;
     const double w = 2.0 * lds[j];
