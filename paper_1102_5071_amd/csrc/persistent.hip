@@ -143,9 +143,9 @@ __device__ __forceinline__ void dstore(double* p, double v) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Barrier state: word 0 = top arrival counter, words kBarGroupStride*(1+g) =
-// arrival counter of group g (blocks b with b % groups == g), one 128-byte
-// line each, so arrivals of different groups do not serialise on one address.
+// Barrier state: words kBarGroupStride*(1+g) = arrival counter of group g
+// (blocks b with b % groups == g), one 128-byte line each, so arrivals of
+// different groups do not serialise on one address; word 0 is unused.
 constexpr int kBarGroups = 16;
 constexpr int kBarGroupStride = 16;  // 64-bit words per 128-byte line
 
@@ -154,35 +154,42 @@ __device__ bool grid_barrier(unsigned long long* bar, int* fault, unsigned long 
   // all memory operations of this wave (device-scope stores included) are done
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
+  epoch += 1ull;
+  const int nb = gridDim.x;
+  const int ng = nb < kBarGroups ? nb : kBarGroups;
+  // arrive on the group counter (no return value is needed)
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(bar + kBarGroupStride * (1 + blockIdx.x % ng), 1ull,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64) {
+    // wavefront 0 watches every group counter at once (lane g: group g) and,
+    // in the same round, the fault flag (lane ng)
+    const int l = threadIdx.x;
+    const unsigned long long members =
+        (l < ng) ? (unsigned long long)((nb - 1 - l) / ng + 1) : 0ull;
+    const unsigned long long target = epoch * members;
     int ok = 1;
-    epoch += 1ull;
-    const int nb = gridDim.x;
-    const int ng = nb < kBarGroups ? nb : kBarGroups;
-    const int g = blockIdx.x % ng;
-    const unsigned long long members = (unsigned long long)((nb - 1 - g) / ng + 1);
-    const unsigned long long gv =
-        __hip_atomic_fetch_add(bar + kBarGroupStride * (1 + g), 1ull, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT) + 1ull;
-    if (gv == epoch * members)  // last of its group: arrive at the top level
-      __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long target = epoch * (unsigned long long)ng;
     const long long t0 = wall_clock64();
     for (;;) {
-      const unsigned long long v = __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v >= target) break;
-      if (__hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      bool waiting = false, faulted = false;
+      if (l < ng)
+        waiting = __hip_atomic_load(bar + kBarGroupStride * (1 + l), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) < target;
+      else if (l == ng)
+        faulted = __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      if (__ballot(waiting) == 0ull) break;
+      if (__ballot(faulted) != 0ull) {
         ok = 0;
         break;
       }
       if (wall_clock64() - t0 > limit) {
-        __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (l == 0) __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    *s_ok = ok;
+    if (l == 0) *s_ok = ok;
   }
   __syncthreads();
   return *s_ok != 0;
