@@ -204,7 +204,9 @@ __global__ __launch_bounds__(kSellBlock) void k_sell_lz_spmv(
     if (row < S.n) {
       r.x *= inv;
       r.y *= inv;
-      if (y) y[row] = r;
+      // the product is read by the next kernel only: stream it past the caches
+      if (y) __builtin_nontemporal_store(*reinterpret_cast<const dvec2*>(&r),
+                                         reinterpret_cast<dvec2*>(y) + row);
       const double2 xr = x[row];
       apart += (xr.x * r.x + xr.y * r.y) * inv;
     }
