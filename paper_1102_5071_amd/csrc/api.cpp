@@ -217,7 +217,8 @@ int choose_path(const cfet_ctx* c) {
 }
 
 int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
-                         const SchemeTable& sc, int m, int path, hipStream_t st) {
+                         const SchemeTable& sc, int m, int path, hipStream_t st,
+                         double2* save = nullptr) {
   const int nt1 = c->nterms + 1;
   if (c->profiling && c->events.used > 0) {
     (void)hipStreamSynchronize(c->last_stream);
@@ -309,6 +310,7 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
   pa.stats = c->stats;
   pa.spin_limit = c->spin_limit;
   pa.timing = c->profiling ? 1 : 0;
+  pa.save = save;
   const bool timed = c->profiling && c->events.used < c->events.cap;
   if (timed) (void)hipEventRecord(c->events.begin[c->events.used], st);
   e = cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop, path == 2,
@@ -875,11 +877,21 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
   };
   std::vector<ExpRec> rec(size_t(seg) * sc.s);
   Wl[0] = lam;
+  // the segment recomputation runs on the persistent path when the operator fits
+  // it (one launch per segment, the kernel stores the state before each
+  // exponential); otherwise exponential by exponential on the multi-kernel path
+  const int rpath = choose_path(c);
   for (int64_t sg = nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
     const int64_t s0 = sg * seg, s1 = std::min(N, s0 + seg);
     e = hipMemcpyAsync(psi, ckpt + size_t(sg) * nn, vb, hipMemcpyDeviceToDevice, st);
     Wf[0] = psi;
-    if (e == hipSuccess) e = cfet::launch_norm_start(psi, n, c->plan, c->partA, st);
+    if (e == hipSuccess && rpath != 1) {
+      rc = propagate_persistent(c, psi, t0 + double(s0) * dt, dt, s1 - s0, sc, m, rpath, st,
+                                before);
+      if (rc != CFET_OK) return rc;
+    } else if (e == hipSuccess) {
+      e = cfet::launch_norm_start(psi, n, c->plan, c->partA, st);
+    }
     size_t idx = 0;
     for (int64_t q = s0; q < s1 && e == hipSuccess; ++q) {
       const double tn = t0 + double(q) * dt;
@@ -906,8 +918,11 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
           r.p[z] = 0;
           r.w[z] = 0.0;
         }
-        e = hipMemcpyAsync(before + idx * nn, psi, vb, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = cfet::launch_exponential(c->A, c->nterms, c->plan, r.tw, dt, m, wf, st);
+        if (rpath == 1) {
+          e = hipMemcpyAsync(before + idx * nn, psi, vb, hipMemcpyDeviceToDevice, st);
+          if (e == hipSuccess)
+            e = cfet::launch_exponential(c->A, c->nterms, c->plan, r.tw, dt, m, wf, st);
+        }
       }
     }
     for (size_t x = idx; x-- > 0 && e == hipSuccess;) {

@@ -175,6 +175,7 @@ struct PersistArgs {
   DevStats* stats;
   long long spin_limit;     // barrier wait limit in wall-clock ticks
   int timing;               // accumulate per-segment wall-clock time (block 0)
+  double2* save;            // optional: psi before exponential e of the call at save + e*n
 };
 
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,

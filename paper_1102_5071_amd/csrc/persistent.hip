@@ -425,7 +425,13 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
       // weights' __syncthreads above ended every read of the ring)
 #pragma unroll
       for (int p = 0; p < PMAX; ++p)
-        if (lane == 0 && rowp[p] >= 0) lu[0][rowp[p] - r0] = u1[p];
+        if (lane == 0 && rowp[p] >= 0) {
+          lu[0][rowp[p] - r0] = u1[p];
+          if (A.save) {  // the state before this exponential, in application order
+            const int64_t e = step * A.s + (A.s - 1 - i);
+            A.save[e * n + rowp[p]] = u1[p];
+          }
+        }
       __syncthreads();
       gather(0);
       for (int k = 0; k <= m; ++k) {

@@ -51,11 +51,15 @@ def gpu_grad(H0, Hk, drives, psi0, target, t0, dt, N, scheme, m, u=None, path=No
     return F, g
 
 
-@pytest.mark.parametrize("scheme,m", [("CF6:5Opt", 12), ("CF4:2", 16), ("CF8:11", 10)])
-def test_gradient_matches_oracle(scheme, m):
+@pytest.mark.parametrize("scheme,m,path", [("CF6:5Opt", 12, None), ("CF4:2", 16, None),
+                                           ("CF8:11", 10, None), ("CF6:5Opt", 12, "multi"),
+                                           ("CF4:2", 16, "coop")])
+def test_gradient_matches_oracle(scheme, m, path):
+    # the segment recomputation runs on the persistent kernels (single workgroup
+    # here, or cooperative when forced) or exponential by exponential (multi)
     H0, Hk, drives, psi0, target = control_problem(5, 8, 0.4, 11)
     N = 40
-    F, g = gpu_grad(H0, Hk, drives, psi0, target, 0.0, 0.01, N, scheme, m)
+    F, g = gpu_grad(H0, Hk, drives, psi0, target, 0.0, 0.01, N, scheme, m, path=path)
     Fo, go = A.fidelity_gradient(H0, Hk, drives, psi0, target, 0.0, 0.01, N, scheme, m)
     assert abs(F - Fo) < 1e-12
     assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)
