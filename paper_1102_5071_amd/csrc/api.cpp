@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -311,6 +312,8 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
   pa.spin_limit = c->spin_limit;
   pa.timing = c->profiling ? 1 : 0;
   pa.save = save;
+  pa.export_T = nullptr;
+  pa.no_combine = 0;
   const bool timed = c->profiling && c->events.used < c->events.cap;
   if (timed) (void)hipEventRecord(c->events.begin[c->events.used], st);
   e = cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop, path == 2,
@@ -326,6 +329,40 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
   c->have_work = true;
   c->last_path = path;
   return CFET_OK;
+}
+
+// One exponential exp(-i dt H_w) on the persistent path for the gradient's
+// backward sweep: weights read from the device (wts_dev, 1 + nterms values),
+// Lanczos basis kept in psi (vector 0) and basis, the projection exported to
+// X; with no_combine psi is left unchanged.
+hipError_t persistent_exponential(cfet_ctx* c, int path, double2* psi, double2* basis,
+                                  const double* wts_dev, double dt, int m, LzScalars* X,
+                                  bool no_combine, hipStream_t st) {
+  cfet::PersistArgs pa{};
+  pa.rowptr = c->A.rowptr;
+  pa.colt = c->A.colt;
+  pa.val = c->A.val;
+  pa.n = c->n;
+  pa.nterms = c->nterms;
+  pa.wts = wts_dev;
+  pa.s = 1;
+  pa.nsteps = 1;
+  pa.m = m;
+  pa.dt = dt;
+  pa.psi = psi;
+  pa.basis = basis;
+  pa.zbuf = c->zbuf;
+  pa.part = c->d_part;
+  pa.bar = c->d_bar;
+  pa.fault = c->d_fault;
+  pa.stats = c->stats;
+  pa.spin_limit = c->spin_limit;
+  pa.timing = 0;
+  pa.save = nullptr;
+  pa.export_T = X;
+  pa.no_combine = no_combine ? 1 : 0;
+  return cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop, path == 2,
+                                 path == 3 ? c->coop_blocks : 1, st);
 }
 
 }  // namespace
@@ -869,18 +906,76 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
   wf.events = wp.events = wl.events = nullptr;
   const DriveSpec& dk = c->drives[kstar];
   std::vector<double> a(sc.s), b(size_t(sc.s) * c->nterms);
-  struct ExpRec {
-    cfet::TermWeights tw;
-    int np;
-    int p[4];
-    double w[4];
-  };
-  std::vector<ExpRec> rec(size_t(seg) * sc.s);
   Wl[0] = lam;
-  // the segment recomputation runs on the persistent path when the operator fits
-  // it (one launch per segment, the kernel stores the state before each
-  // exponential); otherwise exponential by exponential on the multi-kernel path
+  // One backward exponential: Lanczos from psi (before the exponential) and
+  // from lambda, the Frechet term, lambda moved back.  It reads its weights,
+  // its db/du pairs and the state before it from device memory (record
+  // *cursor, uploaded once per segment), so the same launches serve every
+  // exponential.  (Replaying them as a captured graph measured 9 % slower than
+  // enqueueing them: the kernels, not their submission, set the time.)
+  cfet::GradRec *d_recs = nullptr, *d_cur = nullptr;
+  int* d_cursor = nullptr;
+  double2* pb = nullptr;
+  double2* lam0 = nullptr;  // lambda after the exponential, kept as the first basis vector
+  if (e == hipSuccess) e = gb.get(&d_recs, size_t(seg) * sc.s);
+  if (e == hipSuccess) e = gb.get(&lam0, nn);
+  if (e == hipSuccess) e = gb.get(&d_cur, 1);
+  if (e == hipSuccess) e = gb.get(&d_cursor, 1);
+  if (e == hipSuccess) e = gb.get(&pb, nn);
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: workspace");
+  cfet::GradRec* h_recs = nullptr;  // pinned staging of one segment's records and cursor
+  e = hipHostMalloc(reinterpret_cast<void**>(&h_recs), (size_t(seg) * sc.s + 1) * sizeof(cfet::GradRec));
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: pinned staging");
+  struct PinnedGuard {
+    void* p;
+    ~PinnedGuard() { (void)hipHostFree(p); }
+  } pin_guard{h_recs};
+  const cfet::TermWeights* dtw = reinterpret_cast<const cfet::TermWeights*>(
+      reinterpret_cast<const char*>(d_cur) + offsetof(cfet::GradRec, tw));
+  Wp[0] = pb;
+  wp.twp = dtw;
+  wl.twp = dtw;
+  cfet::TermWeights tw0;
+  std::memset(&tw0, 0, sizeof(tw0));
+  // the segment recomputation and the backward exponentials run on the
+  // persistent path when the operator fits it (the recomputation is one launch
+  // per segment that stores the state before each exponential); otherwise
+  // exponential by exponential on the multi-kernel path
   const int rpath = choose_path(c);
+  const double* dw = reinterpret_cast<const double*>(dtw);
+  auto enqueue_back = [&](hipStream_t s_) -> hipError_t {
+    // the persistent exponential of lambda overwrites lambda with its result:
+    // its first basis vector is then read from the copy lam0
+    hipError_t x = cfet::launch_grad_prologue(d_recs, d_cursor, d_cur, before, n, pb, lam,
+                                              rpath != 1 ? lam0 : nullptr, s_);
+    if (rpath != 1) {
+      // two persistent launches: the recurrence from psi (kept, not combined)
+      // and the exponential of lambda (with -dt), both exporting their projection
+      if (x == hipSuccess) x = persistent_exponential(c, rpath, pb, vpsi, dw, dt, m, Spsi, true, s_);
+      if (x == hipSuccess) x = persistent_exponential(c, rpath, lam, vlam, dw, -dt, m, Slam, false, s_);
+    } else {
+      if (x == hipSuccess) x = cfet::launch_norm_start(pb, n, c->plan, c->partA, s_);
+      if (x == hipSuccess) x = cfet::launch_lanczos(c->A, c->nterms, c->plan, tw0, dt, m, wp, s_);
+      if (x == hipSuccess) x = cfet::launch_norm_start(lam, n, c->plan, c->partA, s_);
+      if (x == hipSuccess) x = cfet::launch_lanczos(c->A, c->nterms, c->plan, tw0, -dt, m, wl, s_);
+    }
+    if (x == hipSuccess)
+      x = cfet::launch_frechet_c(c->A, kstar + 1, pb, vpsi, rpath != 1 ? lam0 : lam, vlam, Spsi,
+                                 Slam, cpart, cmat, s_);
+    if (x == hipSuccess) x = cfet::launch_frechet_small_rec(Spsi, Slam, cmat, dt, d_cur, dz, c->stats, s_);
+    if (x == hipSuccess && rpath == 1) x = cfet::launch_combine(n, c->plan, wl, s_);
+    if (x == hipSuccess) x = cfet::launch_grad_epilogue(d_cursor, s_);
+    return x;
+  };
+  hipEvent_t staged = nullptr;
+  e = hipEventCreateWithFlags(&staged, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: event");
+  struct EventGuard {
+    hipEvent_t ev;
+    ~EventGuard() { (void)hipEventDestroy(ev); }
+  } ev_guard{staged};
+  bool staged_pending = false;
+
   for (int64_t sg = nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
     const int64_t s0 = sg * seg, s1 = std::min(N, s0 + seg);
     e = hipMemcpyAsync(psi, ckpt + size_t(sg) * nn, vb, hipMemcpyDeviceToDevice, st);
@@ -892,13 +987,16 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
     } else if (e == hipSuccess) {
       e = cfet::launch_norm_start(psi, n, c->plan, c->partA, st);
     }
+    // records of this segment's exponentials (application order)
+    if (staged_pending) (void)hipEventSynchronize(staged);
+    staged_pending = false;
     size_t idx = 0;
     for (int64_t q = s0; q < s1 && e == hipSuccess; ++q) {
       const double tn = t0 + double(q) * dt;
       cfet::step_weights(sc, c->drives, tn, dt, a.data(), b.data());
       for (int i = sc.s - 1; i >= 0 && e == hipSuccess; --i, ++idx) {
-        ExpRec& r = rec[idx];
-        std::memset(&r.tw, 0, sizeof(r.tw));
+        cfet::GradRec& r = h_recs[idx];
+        std::memset(&r, 0, sizeof(r));
         r.tw.w[0] = a[i];
         for (int k = 0; k < c->nterms; ++k) r.tw.w[k + 1] = b[size_t(i) * c->nterms + k];
         r.np = 0;
@@ -914,10 +1012,6 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
           }
           r.w[slot] += sc.g[i][mm];
         }
-        for (int z = r.np; z < 4; ++z) {
-          r.p[z] = 0;
-          r.w[z] = 0.0;
-        }
         if (rpath == 1) {
           e = hipMemcpyAsync(before + idx * nn, psi, vb, hipMemcpyDeviceToDevice, st);
           if (e == hipSuccess)
@@ -925,20 +1019,15 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
         }
       }
     }
-    for (size_t x = idx; x-- > 0 && e == hipSuccess;) {
-      const ExpRec& r = rec[x];
-      double2* pb = before + x * nn;
-      Wp[0] = pb;
-      e = cfet::launch_norm_start(pb, n, c->plan, c->partA, st);
-      if (e == hipSuccess) e = cfet::launch_lanczos(c->A, c->nterms, c->plan, r.tw, dt, m, wp, st);
-      if (e == hipSuccess) e = cfet::launch_norm_start(lam, n, c->plan, c->partA, st);
-      if (e == hipSuccess) e = cfet::launch_lanczos(c->A, c->nterms, c->plan, r.tw, -dt, m, wl, st);
-      if (e == hipSuccess)
-        e = cfet::launch_frechet_c(c->A, kstar + 1, pb, vpsi, lam, vlam, Spsi, Slam, cpart, cmat, st);
-      if (e == hipSuccess && r.np > 0)
-        e = cfet::launch_frechet_small(Spsi, Slam, cmat, dt, r.np, r.p, r.w, dz, c->stats, st);
-      if (e == hipSuccess) e = cfet::launch_combine(n, c->plan, wl, st);
-    }
+    // the cursor starts at the last exponential of the segment
+    int* hcur = reinterpret_cast<int*>(&h_recs[idx]);
+    *hcur = int(idx) - 1;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_recs, h_recs, idx * sizeof(cfet::GradRec), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_cursor, hcur, sizeof(int), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(staged, st);
+    if (e == hipSuccess) staged_pending = true;
+    for (size_t x = idx; x-- > 0 && e == hipSuccess;) e = enqueue_back(st);
   }
   if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: backward sweep");
   std::vector<double2> hz(size_t(K) + 1);

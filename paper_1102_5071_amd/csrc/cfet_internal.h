@@ -123,6 +123,7 @@ struct ExpWork {
   double* partB;         // partial sums (alpha)
   LzScalars* S;          // scalar block of the exponential
   DevStats* stats;
+  const TermWeights* twp = nullptr;  // if set, the SpMV reads the weights here (device)
 };
 
 hipError_t launch_norm_start(const double2* psi, int64_t n, const LaunchPlan& plan, double* part,
@@ -140,6 +141,22 @@ hipError_t launch_combine(int64_t n, const LaunchPlan& plan, const ExpWork& wk, 
 hipError_t launch_final_norm(const double* part, int np, DevStats* st_dev, hipStream_t st);
 
 // Fidelity gradient (grad.hip).
+// One exponential of the backward sweep, as read by its replayed kernel graph.
+struct GradRec {
+  TermWeights tw;  // weights of H0 and the driven terms
+  int np;          // (piece, weight) pairs of db/du
+  int p[4];
+  double w[4];
+};
+// Copies record *cursor to cur, the state before that exponential to pb and,
+// if lam_copy is set, lam to lam_copy.
+hipError_t launch_grad_prologue(const GradRec* recs, const int* cursor, GradRec* cur,
+                                const double2* before, int64_t n, double2* pb,
+                                const double2* lam, double2* lam_copy, hipStream_t st);
+hipError_t launch_grad_epilogue(int* cursor, hipStream_t st);
+hipError_t launch_frechet_small_rec(const LzScalars* Spsi, const LzScalars* Slam,
+                                    const double2* C, double dt, const GradRec* cur,
+                                    double2* dz, DevStats* stats, hipStream_t st);
 int frechet_c_blocks(int64_t n);
 hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
                             const double2* psi_rest, const double2* lam0, const double2* lam_rest,
@@ -176,6 +193,9 @@ struct PersistArgs {
   long long spin_limit;     // barrier wait limit in wall-clock ticks
   int timing;               // accumulate per-segment wall-clock time (block 0)
   double2* save;            // optional: psi before exponential e of the call at save + e*n
+  LzScalars* export_T;      // optional: Lanczos scalars of the (last) exponential, with the
+                            // stored basis psi, basis[..] scaled as v_j = w_j * inv_nrm[j]
+  int no_combine;           // 1: stop after the Lanczos recurrence (psi unchanged)
 };
 
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,

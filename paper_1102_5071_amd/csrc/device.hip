@@ -141,11 +141,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(const int64_t* __restrict__ ro
 template <int G, int NT>
 __global__ __launch_bounds__(kBlock) void k_lz_spmv(
     const int64_t* __restrict__ rowptr, const uint32_t* __restrict__ colt,
-    const double2* __restrict__ val, int64_t n, TermWeights tw, const double2* __restrict__ x,
-    double2* __restrict__ y, const double* __restrict__ part_in, int np_in,
-    double* __restrict__ part_out, LzScalars* S, int j) {
+    const double2* __restrict__ val, int64_t n, TermWeights tw, const TermWeights* twp,
+    const double2* __restrict__ x, double2* __restrict__ y, const double* __restrict__ part_in,
+    int np_in, double* __restrict__ part_out, LzScalars* S, int j) {
   __shared__ double red[17];
   __shared__ double wl[kMaxTerms + 1];
+  if (twp) tw = *twp;  // weights from device memory (replayed graphs)
   // stopped at an earlier step: pass the flag on and do nothing
   if (j > 0 && S->brk[j - 1]) {
     if (block0_thread0()) S->brk[j] = 1;
@@ -366,13 +367,13 @@ hipError_t dispatch_apply(int G, const DevCSR& A, int nb, const TermWeights& tw,
 }
 
 template <int NT>
-hipError_t dispatch_spmv(int G, const DevCSR& A, int nb, const TermWeights& tw, const double2* x,
-                         double2* y, const double* pin, int npin, double* pout, LzScalars* S,
-                         int j, hipStream_t st) {
+hipError_t dispatch_spmv(int G, const DevCSR& A, int nb, const TermWeights& tw,
+                         const TermWeights* twp, const double2* x, double2* y, const double* pin,
+                         int npin, double* pout, LzScalars* S, int j, hipStream_t st) {
 #define CFET_SPMV_CASE(GG)                                                                      \
   case GG:                                                                                     \
     hipLaunchKernelGGL((k_lz_spmv<GG, NT>), dim3(nb), dim3(kBlock), 0, st, A.rowptr, A.colt,  \
-                       A.val, A.n, tw, x, y, pin, npin, pout, S, j);                          \
+                       A.val, A.n, tw, twp, x, y, pin, npin, pout, S, j);                     \
     break;
   switch (G) {
     CFET_SPMV_CASE(1)
@@ -428,11 +429,11 @@ hipError_t launch_lanczos(const DevCSR& A, int nterms, const LaunchPlan& plan,
     if (wk.sell)
       e = launch_sell_lz_spmv(*wk.sell, nterms, tw, x, y, wk.partA, plan.nb_vec, wk.partB, S, j, st);
     else if (nterms == 1)
-      e = dispatch_spmv<1>(plan.G, A, plan.nb_spmv, tw, x, y, wk.partA, plan.nb_vec, wk.partB, S,
-                           j, st);
+      e = dispatch_spmv<1>(plan.G, A, plan.nb_spmv, tw, wk.twp, x, y, wk.partA, plan.nb_vec,
+                           wk.partB, S, j, st);
     else
-      e = dispatch_spmv<0>(plan.G, A, plan.nb_spmv, tw, x, y, wk.partA, plan.nb_vec, wk.partB, S,
-                           j, st);
+      e = dispatch_spmv<0>(plan.G, A, plan.nb_spmv, tw, wk.twp, x, y, wk.partA, plan.nb_vec,
+                           wk.partB, S, j, st);
     if (e != hipSuccess) return e;
     if (ev) {
       (void)hipEventRecord(ev->end[ev->used], st);

@@ -121,7 +121,8 @@ __global__ __launch_bounds__(256) void k_frechet_c_reduce(const double2* __restr
 __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
     const LzScalars* __restrict__ Spsi, const LzScalars* __restrict__ Slam,
     const double2* __restrict__ C, double dt, int npairs, int p0, double w0, int p1, double w1,
-    int p2, double w2, int p3, double w3, double2* __restrict__ dz, DevStats* stats) {
+    int p2, double w2, int p3, double w3, double2* __restrict__ dz, DevStats* stats,
+    const GradRec* __restrict__ rec) {
   __shared__ double2 v[2 * kMaxM], term[2 * kMaxM];
   __shared__ double red[2];
   __shared__ int again;
@@ -197,8 +198,15 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
   if (r == 0) {
     const double bb = Slam->beta0 * Spsi->beta0;
     const double2 g = make_double2(bb * v[0].x, bb * v[0].y);
-    const int ps[4] = {p0, p1, p2, p3};
-    const double ws[4] = {w0, w1, w2, w3};
+    int ps[4] = {p0, p1, p2, p3};
+    double ws[4] = {w0, w1, w2, w3};
+    if (rec) {  // pairs from device memory (replayed graphs)
+      npairs = rec->np;
+      for (int q = 0; q < 4; ++q) {
+        ps[q] = rec->p[q];
+        ws[q] = rec->w[q];
+      }
+    }
     for (int q = 0; q < npairs; ++q) {
       dz[ps[q]].x += ws[q] * g.x;
       dz[ps[q]].y += ws[q] * g.y;
@@ -243,6 +251,29 @@ __global__ void k_zdot_reduce(const double2* __restrict__ part, int nb, double2*
   *out = make_double2(sr, si);
 }
 
+// Start of one replayed backward exponential: take record *cursor and the
+// state before that exponential into fixed buffers.
+__global__ __launch_bounds__(256) void k_grad_prologue(const GradRec* __restrict__ recs,
+                                                       const int* __restrict__ cursor,
+                                                       GradRec* __restrict__ cur,
+                                                       const double2* __restrict__ before,
+                                                       int64_t n, double2* __restrict__ pb,
+                                                       const double2* __restrict__ lam,
+                                                       double2* __restrict__ lam_copy) {
+  const int idx = *cursor;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cur = recs[idx];
+  const double2* __restrict__ src = before + (int64_t)idx * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    pb[i] = src[i];
+    if (lam_copy) lam_copy[i] = lam[i];
+  }
+}
+
+__global__ void k_grad_epilogue(int* cursor) {
+  if (threadIdx.x == 0) *cursor -= 1;
+}
+
 __global__ void k_zero2(double2* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = make_double2(0.0, 0.0);
@@ -273,7 +304,30 @@ hipError_t launch_frechet_small(const LzScalars* Spsi, const LzScalars* Slam, co
                                 double dt, int npairs, const int* p, const double* w,
                                 double2* dz, DevStats* stats, hipStream_t st) {
   hipLaunchKernelGGL(k_frechet_small, dim3(1), dim3(kSmallThreads), 0, st, Spsi, Slam, C, dt,
-                     npairs, p[0], w[0], p[1], w[1], p[2], w[2], p[3], w[3], dz, stats);
+                     npairs, p[0], w[0], p[1], w[1], p[2], w[2], p[3], w[3], dz, stats,
+                     (const GradRec*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_frechet_small_rec(const LzScalars* Spsi, const LzScalars* Slam,
+                                    const double2* C, double dt, const GradRec* cur,
+                                    double2* dz, DevStats* stats, hipStream_t st) {
+  hipLaunchKernelGGL(k_frechet_small, dim3(1), dim3(kSmallThreads), 0, st, Spsi, Slam, C, dt, 0,
+                     0, 0.0, 0, 0.0, 0, 0.0, 0, 0.0, dz, stats, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_prologue(const GradRec* recs, const int* cursor, GradRec* cur,
+                                const double2* before, int64_t n, double2* pb,
+                                const double2* lam, double2* lam_copy, hipStream_t st) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_grad_prologue, dim3(nb), dim3(256), 0, st, recs, cursor, cur, before, n,
+                     pb, lam, lam_copy);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_epilogue(int* cursor, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_epilogue, dim3(1), dim3(64), 0, st, cursor);
   return hipGetLastError();
 }
 

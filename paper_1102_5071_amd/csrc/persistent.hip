@@ -633,10 +633,29 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           ls.expo += 1;
           ls.brk += 1;
           ls.minm = 0;
+          if (A.export_T) {
+            A.export_T->beta0 = 0.0;
+            A.export_T->m_eff = 0;
+          }
         }
         continue;
       }
       __syncthreads();
+      if (A.export_T && blockIdx.x == 0) {
+        // the projection of this exponential: u_j = nu_j v_j, so inv_nrm = 1 / nu
+        LzScalars* X = A.export_T;
+        const int t = threadIdx.x;
+        if (t < meff) {
+          X->alpha[t] = sh.alpha[t];
+          X->inv_nrm[t] = sh.inv[t];
+        }
+        if (t < meff - 1) X->beta[t] = sh.beta[t];
+        if (t == 0) {
+          X->beta0 = nu0;
+          X->m_eff = meff;
+        }
+      }
+      if (A.no_combine) continue;
       tm.lap(A.stats, 1);
       // ---- small exponential (wave 0; identical in every block)
       const double beta0 = nu0;
