@@ -23,6 +23,7 @@ namespace {
 constexpr int kCRows = 16;      // rows per tile of k_frechet_c
 constexpr int kCBlock = 256;
 constexpr int kSmallThreads = 128;
+constexpr int kSmallC = 32;  // C held in LDS by k_frechet_small up to 32 x 32
 
 __device__ __forceinline__ const double2* basis_vec(const double2* w0, const double2* rest,
                                                     int64_t n, int j) {
@@ -30,7 +31,10 @@ __device__ __forceinline__ const double2* basis_vec(const double2* w0, const dou
 }
 
 // Partial C_kj (raw: stored vectors, no inv scaling) over the rows of this
-// block's tiles.  part: [gridDim.x][kMaxM * kMaxM] complex.
+// block's tiles, for the ml x mp pairs in use (pair = k * mp + j).
+// part: [gridDim.x][kMaxM * kMaxM] complex.
+constexpr int kCPairsPerThread = (kMaxM * kMaxM + kCBlock - 1) / kCBlock;
+
 __global__ __launch_bounds__(kCBlock) void k_frechet_c(
     const int64_t* __restrict__ rowptr, const uint32_t* __restrict__ colt,
     const double2* __restrict__ val, int64_t n, int term, const double2* __restrict__ psi0,
@@ -40,15 +44,17 @@ __global__ __launch_bounds__(kCBlock) void k_frechet_c(
   __shared__ double2 Y[kCRows][kMaxM];
   __shared__ double2 U[kCRows][kMaxM];
   const int mp = Spsi->m_eff, ml = Slam->m_eff;
-  double2 acc[(kMaxM * kMaxM + kCBlock - 1) / kCBlock];
+  const int mx = max(mp, ml);
+  const int npairs = ml * mp;
+  double2 acc[kCPairsPerThread];
 #pragma unroll
-  for (int q = 0; q < (kMaxM * kMaxM + kCBlock - 1) / kCBlock; ++q) acc[q] = make_double2(0, 0);
+  for (int q = 0; q < kCPairsPerThread; ++q) acc[q] = make_double2(0, 0);
   const int64_t ntiles = (n + kCRows - 1) / kCRows;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int64_t tile = blockIdx.x; tile < ntiles && mx > 0; tile += gridDim.x) {
     const int64_t r0 = tile * kCRows;
     __syncthreads();
-    for (int t = threadIdx.x; t < kCRows * kMaxM; t += blockDim.x) {
-      const int rl = t / kMaxM, j = t % kMaxM;
+    for (int t = threadIdx.x; t < kCRows * mx; t += blockDim.x) {
+      const int rl = t / mx, j = t % mx;
       const int64_t r = r0 + rl;
       double2 y = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
       if (r < n) {
@@ -70,10 +76,10 @@ __global__ __launch_bounds__(kCBlock) void k_frechet_c(
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < (kMaxM * kMaxM + kCBlock - 1) / kCBlock; ++q) {
+    for (int q = 0; q < kCPairsPerThread; ++q) {
       const int pair = threadIdx.x + q * kCBlock;
-      const int k = pair / kMaxM, j = pair % kMaxM;
-      if (pair < kMaxM * kMaxM && k < ml && j < mp) {
+      if (pair < npairs) {
+        const int k = pair / mp, j = pair % mp;
         double2 a = acc[q];
         for (int rl = 0; rl < kCRows; ++rl) {
           const double2 uu = U[rl][k], yy = Y[rl][j];
@@ -86,22 +92,26 @@ __global__ __launch_bounds__(kCBlock) void k_frechet_c(
     }
   }
 #pragma unroll
-  for (int q = 0; q < (kMaxM * kMaxM + kCBlock - 1) / kCBlock; ++q) {
+  for (int q = 0; q < kCPairsPerThread; ++q) {
     const int pair = threadIdx.x + q * kCBlock;
-    if (pair < kMaxM * kMaxM) part[(int64_t)blockIdx.x * kMaxM * kMaxM + pair] = acc[q];
+    if (pair < npairs) part[(int64_t)blockIdx.x * kMaxM * kMaxM + pair] = acc[q];
   }
 }
 
-// C[k][j] = inv_lam[k] inv_psi[j] * sum over blocks of the partials (fixed order).
+// C[k][j] = inv_lam[k] inv_psi[j] * sum over blocks of the partials (fixed
+// order; one thread per pair, consecutive pairs read consecutive partials).
 __global__ __launch_bounds__(256) void k_frechet_c_reduce(const double2* __restrict__ part,
                                                           int nb, const LzScalars* Spsi,
                                                           const LzScalars* Slam,
                                                           double2* __restrict__ C) {
   const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+  const int mp = Spsi->m_eff, ml = Slam->m_eff;
   if (pair >= kMaxM * kMaxM) return;
-  const int k = pair / kMaxM, j = pair % kMaxM;
   double sr = 0.0, si = 0.0;
-  if (k < Slam->m_eff && j < Spsi->m_eff) {
+  int k = pair / kMaxM, j = pair % kMaxM;  // pairs past the used ones clear C
+  if (pair < ml * mp) {
+    k = pair / mp;
+    j = pair % mp;
     for (int b = 0; b < nb; ++b) {
       const double2 v = part[(int64_t)b * kMaxM * kMaxM + pair];
       sr += v.x;
@@ -110,8 +120,8 @@ __global__ __launch_bounds__(256) void k_frechet_c_reduce(const double2* __restr
     const double sc = Slam->inv_nrm[k] * Spsi->inv_nrm[j];
     sr *= sc;
     si *= sc;
+    C[k * kMaxM + j] = make_double2(sr, si);
   }
-  C[pair] = make_double2(sr, si);
 }
 
 // g = beta_lam beta_psi [exp(M) e_{ml}]_0,  M = -i dt [[S, C], [0, T]] of order
@@ -124,12 +134,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
     int p2, double w2, int p3, double w3, double2* __restrict__ dz, DevStats* stats,
     const GradRec* __restrict__ rec) {
   __shared__ double2 v[2 * kMaxM], term[2 * kMaxM];
+  __shared__ double2 Cs[kSmallC][kSmallC];  // C when ml, mp <= kSmallC
   __shared__ double red[2];
   __shared__ int again;
   const int ml = Slam->m_eff, mp = Spsi->m_eff;
   const int nm = ml + mp;
   const int r = threadIdx.x;
   if (ml == 0 || mp == 0) return;  // a zero state: no contribution
+  const bool lds_c = ml <= kSmallC && mp <= kSmallC;
+  if (lds_c) {
+    for (int t = r; t < ml * mp; t += blockDim.x) Cs[t / mp][t % mp] = C[(t / mp) * kMaxM + t % mp];
+    __syncthreads();
+  }
   // row r of M: coefficients (times -i dt) and the infinity norm
   double rowsum = 0.0;
   if (r < ml) {
@@ -163,7 +179,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
         if (r > 0) { ar += Slam->beta[r - 1] * term[r - 1].x; ai += Slam->beta[r - 1] * term[r - 1].y; }
         if (r + 1 < ml) { ar += Slam->beta[r] * term[r + 1].x; ai += Slam->beta[r] * term[r + 1].y; }
         for (int j = 0; j < mp; ++j) {
-          const double2 c = C[r * kMaxM + j], x = term[ml + j];
+          const double2 c = lds_c ? Cs[r][j] : C[r * kMaxM + j], x = term[ml + j];
           ar += c.x * x.x - c.y * x.y;
           ai += c.x * x.y + c.y * x.x;
         }
@@ -283,7 +299,7 @@ __global__ void k_zero2(double2* p, int n) {
 
 int frechet_c_blocks(int64_t n) {
   const int64_t tiles = (n + kCRows - 1) / kCRows;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 512));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 128));
 }
 
 hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
