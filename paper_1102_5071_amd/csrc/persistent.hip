@@ -312,12 +312,11 @@ template <int G, int PMAX, int QMAX, int NT, bool SINGLE>
 __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
   constexpr int BLOCK = kPersistBlock;
   __shared__ Shared sh;
-  // u_k ring (k mod 3) and z_k ring (k mod 2) of this block's own rows in LDS,
-  // indexed by row - r0: the single workgroup reads every gathered value from
-  // here, the cooperative blocks the entries whose column is one of their own rows
+  // u_k ring (k mod 3) of this block's own rows in LDS, indexed by row - r0:
+  // the single workgroup reads every gathered value from here, the cooperative
+  // blocks the entries whose column is one of their own rows
   constexpr int LN = SINGLE ? kSingleMaxRows : kCoopMaxRows;
   __shared__ double2 lu[3][LN];
-  __shared__ double2 lz[2][LN];
   const int nb = gridDim.x;
   const int64_t n = A.n;
   const int64_t per = (n + nb - 1) / nb;
@@ -501,14 +500,22 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
         const double2* __restrict__ zm1 = Zb(k - 1);
         const double2* __restrict__ um2 = U(k - 2);
         double s_uz = 0.0, s_uu = 0.0;
+        // u_k on the own rows first; after one block barrier every column that
+        // is a row of this block reads it from LDS (the value its owner formed)
+        double2 ucurs[PMAX];
 #pragma unroll
         for (int p = 0; p < PMAX; ++p) {
-          double2 ucur = u1[p];
+          ucurs[p] = u1[p];
           if (k >= 1 && lane == 0 && rowp[p] >= 0) {
-            ucur = form_u(zp[p], u1[p], u2[p], c1, c2, c3);
-            vst<SINGLE>(uk, rowp[p], n, ucur);
-            lu[k % 3][rowp[p] - r0] = ucur;
+            ucurs[p] = form_u(zp[p], u1[p], u2[p], c1, c2, c3);
+            vst<SINGLE>(uk, rowp[p], n, ucurs[p]);
+            lu[k % 3][rowp[p] - r0] = ucurs[p];
           }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PMAX; ++p) {
+          const double2 ucur = ucurs[p];
           double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
           if (rowp[p] >= 0) {
 #pragma unroll
@@ -516,19 +523,13 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
               if (q < cnt[p]) {
                 const uint32_t ct = ccol[p][q];
                 const double2 v = cval[p][q];
-                double2 xg1, xgz, xg2;
+                double2 xv;
                 if ((lmask[p] >> q) & 1u) {
-                  const int c = (int)((int64_t)(ct & kColMask) - r0);
-                  xg1 = lu[(k + 2) % 3][c];                        // u_{k-1} (u_0 at k = 0)
-                  xgz = (k >= 1) ? lz[(k + 1) & 1][c] : make_double2(0.0, 0.0);
-                  xg2 = (k >= 2) ? lu[(k + 1) % 3][c] : make_double2(0.0, 0.0);
-                  if (k == 0) xg1 = lu[0][c];
+                  xv = lu[k % 3][(int)((int64_t)(ct & kColMask) - r0)];  // u_k, own block
                 } else {
-                  xg1 = g1[p][q];
-                  xgz = gz[p][q];
-                  xg2 = (k >= 2) ? g2[p][q] : make_double2(0.0, 0.0);
+                  const double2 xg2 = (k >= 2) ? g2[p][q] : make_double2(0.0, 0.0);
+                  xv = (k >= 1) ? form_u(gz[p][q], g1[p][q], xg2, c1, c2, c3) : g1[p][q];
                 }
-                const double2 xv = (k >= 1) ? form_u(xgz, xg1, xg2, c1, c2, c3) : xg1;
                 const double pr = v.x * xv.x - v.y * xv.y;
                 const double pi = v.x * xv.y + v.y * xv.x;
                 if (NT == 1) {
@@ -546,12 +547,7 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
               const int64_t c = ct & kColMask;
               double2 xv;
               if (SINGLE) {
-                xv = (k == 0) ? lu[0][c] : lu[(k + 2) % 3][c];
-                if (k >= 1) {
-                  const double2 zc = lz[(k + 1) & 1][c];
-                  const double2 u2c = (k >= 2) ? lu[(k + 1) % 3][c] : make_double2(0.0, 0.0);
-                  xv = form_u(zc, xv, u2c, c1, c2, c3);
-                }
+                xv = lu[k % 3][c];  // u_k (every row is the block's own)
               } else {
                 xv = vld<SINGLE>(um1, c, n);
                 if (k >= 1) {
@@ -586,7 +582,6 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           }
           if (lane == 0 && rowp[p] >= 0) {
             const double2 zv = make_double2(yr, yi);
-            lz[k & 1][rowp[p] - r0] = zv;
             if (!SINGLE && k + 1 < m) vst<SINGLE>(zk, rowp[p], n, zv);
             s_uz += ucur.x * zv.x + ucur.y * zv.y;
             s_uu += ucur.x * ucur.x + ucur.y * ucur.y;
