@@ -367,6 +367,8 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the state-error run")
     ap.add_argument("--path", default=None, choices=["multi", "single", "coop"],
                     help="force an execution path (default: chosen by dimension)")
+    ap.add_argument("--layout", default=None, choices=["sell", "sell_uniform"],
+                    help="operator layout of the multi-kernel path (default: by dimension)")
     ap.add_argument("--chunk", type=int, default=0,
                     help="steps per propagate call (default per workload); every launch "
                          "of the timed kernel then covers the same work")
@@ -407,7 +409,7 @@ def main():
             P.propagate(psi, t0 + c * dt, dt, chunk, p.scheme, m)
 
     t = time.perf_counter()
-    P = B.Propagator(p.H0, p.Hk, p.drives, path=args.path)
+    P = B.Propagator(p.H0, p.Hk, p.drives, path=args.path, layout=args.layout)
     log(f"context created in {time.perf_counter() - t:.1f}s")
     nnz_total = p.H0.nnz + sum(h.nnz for h in p.Hk)
     ncsr = 1 + len(p.Hk)
@@ -447,9 +449,15 @@ def main():
     stp = P.stats()
     P.profile(False)
     avg_ms = stp["timed_ms"] / max(1, stp["timed_launches"])
+    layout = ["csr", "sell", "sell_uniform"][stp["layout"]]
     if path == "multi":
         kernel = "k_sell_lz_spmv" if P.uses_sell() else "k_lz_spmv"
-        bytes_per_launch = spmv_algorithmic_bytes(p.dim, nnz_total, ncsr)
+        if layout == "sell_uniform":
+            # the stored bytes of this layout (per-slice shared entries once)
+            bytes_per_launch = stp["matrix_bytes"] + 32 * p.dim
+            key += "_uniform"
+        else:
+            bytes_per_launch = spmv_algorithmic_bytes(p.dim, nnz_total, ncsr)
     else:
         kernel = "k_propagate"
         bytes_per_launch = chunk * s * exponential_algorithmic_bytes(p.dim, nnz_total, ncsr, m_eff)
@@ -505,6 +513,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": label, "dim": p.dim, "nnz": nnz_total, "scheme": p.scheme,
                    "krylov_m": p.m, "dt": p.dt, "t0": t_start, "path": path,
+                   "layout": layout if path == "multi" else "csr",
                    "steps_per_call": chunk,
                    "state_error": state_error,
                    "matvecs_per_step": matvecs / K},

@@ -24,7 +24,8 @@ ERRORS = {0: "CFET_OK", 1: "CFET_EINVAL", 2: "CFET_ENOMEM", 3: "CFET_EDEVICE",
           4: "CFET_ENONFINITE", 5: "CFET_EUNSUPPORTED", 6: "CFET_ENOCONV"}
 VALIDATE_HERMITIAN = 0x1
 PATH_FLAGS = {None: 0, "auto": 0, "multi": 0x10, "single": 0x20, "coop": 0x40,
-              "sell": 0x10 | 0x100}
+              "sell": 0x10 | 0x100, "sell_uniform": 0x10 | 0x200}
+LAYOUT_FLAGS = {None: 0, "auto": 0, "sell": 0x100, "sell_uniform": 0x200}
 PATH_NAMES = {0: "none", 1: "multi", 2: "single", 3: "coop"}
 MAX_KRYLOV = 64
 
@@ -51,7 +52,8 @@ class _Stats(ctypes.Structure):
                 ("matvecs", c_int64), ("min_m_eff", c_int32), ("breakdowns", c_int32),
                 ("path", c_int32), ("status", c_int32), ("last_norm", c_double),
                 ("timed_launches", c_int64), ("timed_ms", c_double),
-                ("segment_us", c_double * 4), ("layout", c_int32), ("reserved", c_int32)]
+                ("segment_us", c_double * 4), ("layout", c_int32), ("reserved", c_int32),
+                ("matrix_bytes", c_int64)]
 
 
 class _Instance(ctypes.Structure):
@@ -190,7 +192,8 @@ def _stream_handle(stream):
 class Propagator:
     """Owns a cfet context for H(t) = H0 + sum_k f_k(t) Hk[k]."""
 
-    def __init__(self, H0, Hk, drives, validate_hermitian: bool = False, path=None):
+    def __init__(self, H0, Hk, drives, validate_hermitian: bool = False, path=None,
+                 layout=None):
         lib = load()
         keep = []
         self.nterms = len(Hk)
@@ -200,7 +203,8 @@ class Propagator:
         hk = (_CSR * self.nterms)(*[_csr_struct(h, keep) for h in Hk])
         dv = (_Drive * self.nterms)(*[_drive_struct(d, keep) for d in drives])
         ctx = c_void_p()
-        flags = (VALIDATE_HERMITIAN if validate_hermitian else 0) | PATH_FLAGS[path]
+        flags = ((VALIDATE_HERMITIAN if validate_hermitian else 0) | PATH_FLAGS[path]
+                 | LAYOUT_FLAGS[layout])
         code = lib.cfet_create(ctypes.byref(h0), self.nterms, hk, dv, flags, ctypes.byref(ctx))
         if code != 0:
             raise CfetError(code, lib.cfet_last_error(None).decode(errors="replace"))
@@ -253,8 +257,8 @@ class Propagator:
         return out
 
     def uses_sell(self) -> bool:
-        """True when the multi-kernel path runs on the SELL-64 layout."""
-        return self.stats()["layout"] == 1
+        """True when the multi-kernel path runs on a SELL-64 layout."""
+        return self.stats()["layout"] in (1, 2)
 
     def profile(self, enable: bool, max_launches: int = 65536):
         _check(load().cfet_profile(self._ctx, 1 if enable else 0, int(max_launches)), self._ctx)

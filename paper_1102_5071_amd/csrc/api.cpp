@@ -28,6 +28,7 @@ struct cfet_ctx {
   DevCSR A;
   cfet::DevSELL sell;
   bool use_sell = false;
+  int64_t sell_bytes = 0;   // stored SELL data one application reads
   cfet::LaunchPlan plan{};
   std::vector<DriveSpec> drives;
   // Krylov workspace (grown on demand)
@@ -75,6 +76,8 @@ thread_local std::string g_err;
 // automatic path choice by dimension
 constexpr int64_t kAutoSingleMaxN = 4096;
 constexpr int64_t kAutoCoopMaxN = int64_t(1) << 22;
+static_assert(sizeof(cfet_stats_t) == 120 && offsetof(cfet_stats_t, matrix_bytes) == 112,
+              "cfet_stats_t layout is part of the ABI");
 
 int fail(cfet_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -151,6 +154,10 @@ void free_ctx(cfet_ctx* c) {
   if (c->sell.rowlen) (void)hipFree(c->sell.rowlen);
   if (c->sell.colt) (void)hipFree(c->sell.colt);
   if (c->sell.val) (void)hipFree(c->sell.val);
+  if (c->sell.nuni) (void)hipFree(c->sell.nuni);
+  if (c->sell.uptr) (void)hipFree(c->sell.uptr);
+  if (c->sell.ucolt) (void)hipFree(c->sell.ucolt);
+  if (c->sell.uval) (void)hipFree(c->sell.uval);
   if (c->basis) (void)hipFree(c->basis);
   if (c->partA) (void)hipFree(c->partA);
   if (c->partB) (void)hipFree(c->partB);
@@ -383,6 +390,189 @@ struct GradBuffers {
   }
 };
 
+// Host staging of the SELL-64 layout.  Row r lists the driven terms' entries
+// (H1, H2, ... each in the caller's order) and then H0's.  With `uniform`, the
+// entries that every row of a slice holds with the same (row XOR column,
+// term, value) go to the slice's uniform part, in the slice's first row's
+// order, and are left out of the per-row slots.
+struct SellStage {
+  std::vector<int64_t> sptr;
+  std::vector<int32_t> swid;
+  std::vector<uint32_t> scol;
+  std::vector<double> sval;
+  std::vector<int32_t> nuni;
+  std::vector<int64_t> uptr;
+  std::vector<uint32_t> ucol;
+  std::vector<double> uval;
+};
+
+template <class F>
+void for_sell_row(const std::vector<HostCSR>& mats, int nterms, int64_t r, F f) {
+  for (int tt = 1; tt <= nterms + 1; ++tt) {
+    const int term = (tt == nterms + 1) ? 0 : tt;  // driven terms first, then H0
+    const HostCSR& h = mats[term];
+    for (int64_t q = h.rp[r]; q < h.rp[r + 1]; ++q) f(term, h.col[q], &h.val[2 * q]);
+  }
+}
+
+// Entries shared by all rows of one slice: candidates are the first row's
+// entries keyed by (row XOR column, term); a candidate is kept if every row
+// holds it exactly once with bit-identical value.
+struct SliceUniform {
+  std::vector<uint32_t> key;
+  std::vector<double> val;
+  std::vector<int32_t> cnt;
+  std::vector<int64_t> last;
+  std::vector<char> keep;
+  std::vector<int32_t> table;  // open addressing: candidate index + 1, 0 = empty
+  uint32_t mask = 0;
+  int bits = 0;
+
+  int find(uint32_t k) const {
+    if (table.empty()) return -1;
+    uint32_t h = (k * 0x9E3779B1u) >> (32 - bits);
+    while (table[h]) {
+      const int i = table[h] - 1;
+      if (key[i] == k) return i;
+      h = (h + 1) & mask;
+    }
+    return -1;
+  }
+
+  static uint32_t make_key(int64_t r, int32_t col, int term) {
+    return uint32_t(int64_t(col) ^ r) | (uint32_t(term) << cfet::kTermShift);
+  }
+
+  // Returns the number of kept entries of rows [r0, r1).
+  int run(const std::vector<HostCSR>& mats, int nterms, int64_t r0, int64_t r1) {
+    key.clear();
+    val.clear();
+    for_sell_row(mats, nterms, r0, [&](int term, int32_t col, const double* v) {
+      key.push_back(make_key(r0, col, term));
+      val.push_back(v[0]);
+      val.push_back(v[1]);
+    });
+    const int nc = int(key.size());
+    table.clear();
+    if (nc == 0) return 0;
+    bits = 1;
+    while ((1 << bits) < 2 * nc) ++bits;
+    mask = (1u << bits) - 1u;
+    table.assign(size_t(1) << bits, 0);
+    cnt.assign(nc, 0);
+    last.assign(nc, -1);
+    keep.assign(nc, 1);
+    for (int i = 0; i < nc; ++i) {
+      const int j = find(key[i]);
+      if (j >= 0) {  // repeated in the first row: neither copy is uniform
+        keep[j] = keep[i] = 0;
+        continue;
+      }
+      uint32_t h = (key[i] * 0x9E3779B1u) >> (32 - bits);
+      while (table[h]) h = (h + 1) & mask;
+      table[h] = i + 1;
+    }
+    for (int64_t r = r0; r < r1; ++r) {
+      for_sell_row(mats, nterms, r, [&](int term, int32_t col, const double* v) {
+        const int j = find(make_key(r, col, term));
+        if (j < 0) return;
+        if (last[j] == r || std::memcmp(v, &val[2 * j], 2 * sizeof(double)) != 0) keep[j] = 0;
+        last[j] = r;
+        ++cnt[j];
+      });
+    }
+    int nu = 0;
+    for (int i = 0; i < nc; ++i) {
+      if (cnt[i] != r1 - r0) keep[i] = 0;
+      nu += keep[i];
+    }
+    return nu;
+  }
+
+  bool kept(int64_t r, int32_t col, int term) const {
+    const int j = find(make_key(r, col, term));
+    return j >= 0 && keep[j];
+  }
+};
+
+// Returns false when the host buffers cannot be allocated.
+bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
+                const std::vector<int32_t>& rowlen, bool uniform, unsigned nth, SellStage* S) {
+  const int64_t nsl = (n + 63) / 64;
+  try {
+    S->sptr.assign(nsl + 1, 0);
+    S->swid.assign(nsl, 0);
+    if (uniform) {
+      S->nuni.assign(nsl, 0);
+      S->uptr.assign(nsl + 1, 0);
+    }
+  } catch (const std::bad_alloc&) {
+    return false;
+  }
+  auto run_threads = [&](auto body) {
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nth; ++t)
+      pool.emplace_back([&, t]() { body(nsl * t / nth, nsl * (t + 1) / nth); });
+    for (auto& th : pool) th.join();
+  };
+  if (uniform) {
+    run_threads([&](int64_t s0, int64_t s1) {
+      SliceUniform U;
+      for (int64_t sl = s0; sl < s1; ++sl)
+        S->nuni[sl] = U.run(mats, nterms, sl * 64, std::min<int64_t>(n, sl * 64 + 64));
+    });
+  }
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    int w = 0;
+    for (int64_t r = sl * 64; r < std::min<int64_t>(n, sl * 64 + 64); ++r) w = std::max(w, rowlen[r]);
+    const int nu = uniform ? S->nuni[sl] : 0;
+    S->swid[sl] = w - nu;
+    S->sptr[sl + 1] = S->sptr[sl] + 64 * int64_t(w - nu);
+    if (uniform) S->uptr[sl + 1] = S->uptr[sl] + nu;
+  }
+  const int64_t slots = S->sptr[nsl];
+  const int64_t uslots = uniform ? S->uptr[nsl] : 0;
+  try {
+    S->scol.assign(slots, 0u);
+    S->sval.assign(2 * slots, 0.0);
+    S->ucol.assign(uslots, 0u);
+    S->uval.assign(2 * uslots, 0.0);
+  } catch (const std::bad_alloc&) {
+    return false;
+  }
+  run_threads([&](int64_t s0, int64_t s1) {
+    SliceUniform U;
+    for (int64_t sl = s0; sl < s1; ++sl) {
+      const int64_t r0 = sl * 64, r1 = std::min<int64_t>(n, sl * 64 + 64);
+      const bool uni = uniform && S->nuni[sl] > 0;
+      if (uni) {
+        U.run(mats, nterms, r0, r1);
+        int64_t u = S->uptr[sl];
+        for (size_t i = 0; i < U.key.size(); ++i) {
+          if (!U.keep[i]) continue;
+          S->ucol[u] = U.key[i];
+          S->uval[2 * u] = U.val[2 * i];
+          S->uval[2 * u + 1] = U.val[2 * i + 1];
+          ++u;
+        }
+      }
+      for (int64_t r = r0; r < r1; ++r) {
+        const int64_t lane = r - r0;
+        int64_t k = 0;
+        for_sell_row(mats, nterms, r, [&](int term, int32_t col, const double* v) {
+          if (uni && U.kept(r, col, term)) return;
+          const int64_t pos = S->sptr[sl] + 64 * k + lane;
+          S->scol[pos] = uint32_t(col) | (uint32_t(term) << cfet::kTermShift);
+          S->sval[2 * pos] = v[0];
+          S->sval[2 * pos + 1] = v[1];
+          ++k;
+        });
+      }
+    }
+  });
+  return true;
+}
+
 // Piece of a piecewise-constant drive containing t, or -1 outside.
 int pwc_piece(const DriveSpec& d, double t) {
   const std::vector<double>& e = d.edges;
@@ -472,7 +662,8 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     rowlen[r] = int32_t(std::min<int64_t>(len, INT32_MAX));
     c->max_row = std::max<int>(c->max_row, rowlen[r]);
   }
-  const bool use_sell = (flags & CFET_LAYOUT_SELL) || n > kAutoCoopMaxN;
+  const bool use_sell =
+      (flags & (CFET_LAYOUT_SELL | CFET_LAYOUT_SELL_UNIFORM)) || n > kAutoCoopMaxN;
   const bool need_csr = !use_sell || n <= kAutoCoopMaxN;
   c->A.n = n;
   c->A.nnz = nnz;
@@ -523,50 +714,17 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
   }
   if (e == hipSuccess && use_sell) {
     const int64_t nsl = (n + 63) / 64;
-    std::vector<int64_t> sptr(nsl + 1);
-    std::vector<int32_t> swid(nsl);
-    sptr[0] = 0;
-    for (int64_t sl = 0; sl < nsl; ++sl) {
-      int w = 0;
-      for (int64_t r = sl * 64; r < std::min<int64_t>(n, sl * 64 + 64); ++r) w = std::max(w, rowlen[r]);
-      swid[sl] = w;
-      sptr[sl + 1] = sptr[sl] + 64 * int64_t(w);
-    }
-    const int64_t slots = sptr[nsl];
-    std::vector<uint32_t> scol;
-    std::vector<double> sval;
-    try {
-      scol.assign(slots, 0u);
-      sval.assign(2 * slots, 0.0);
-    } catch (const std::bad_alloc&) {
+    // large dimensions default to the uniform-part layout; CFET_LAYOUT_SELL
+    // alone asks for plain SELL-64
+    const bool uniform = (flags & CFET_LAYOUT_SELL_UNIFORM) ||
+                         (!(flags & CFET_LAYOUT_SELL) && n > kAutoCoopMaxN);
+    SellStage S;
+    if (!stage_sell(mats, nterms, n, rowlen, uniform, (n < 65536) ? 1u : nth_all, &S)) {
       rc = fail(c, CFET_ENOMEM, "cannot stage the SELL matrix on the host");
       free_ctx(c);
       return rc;
     }
-    const unsigned nth = (n < 65536) ? 1u : nth_all;
-    std::vector<std::thread> pool;
-    for (unsigned t = 0; t < nth; ++t) {
-      pool.emplace_back([&, t]() {
-        const int64_t s0 = nsl * t / nth, s1 = nsl * (t + 1) / nth;
-        for (int64_t sl = s0; sl < s1; ++sl) {
-          for (int64_t r = sl * 64; r < std::min<int64_t>(n, sl * 64 + 64); ++r) {
-            const int64_t lane = r - sl * 64;
-            int64_t k = 0;
-            for (int tt = 1; tt <= nterms + 1; ++tt) {
-              const int term = (tt == nterms + 1) ? 0 : tt;  // driven terms first, then H0
-              const HostCSR& h = mats[term];
-              for (int64_t q = h.rp[r]; q < h.rp[r + 1]; ++q, ++k) {
-                const int64_t pos = sptr[sl] + 64 * k + lane;
-                scol[pos] = uint32_t(h.col[q]) | (uint32_t(term) << cfet::kTermShift);
-                sval[2 * pos] = h.val[2 * q];
-                sval[2 * pos + 1] = h.val[2 * q + 1];
-              }
-            }
-          }
-        }
-      });
-    }
-    for (auto& th : pool) th.join();
+    const int64_t slots = S.sptr[nsl];
     c->sell.n = n;
     c->sell.slots = slots;
     e = hipMalloc(&c->sell.slice_ptr, (nsl + 1) * sizeof(int64_t));
@@ -575,15 +733,37 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     if (e == hipSuccess) e = hipMalloc(&c->sell.colt, std::max<int64_t>(slots, 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&c->sell.val, std::max<int64_t>(slots, 1) * sizeof(double2));
     if (e == hipSuccess)
-      e = hipMemcpy(c->sell.slice_ptr, sptr.data(), (nsl + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+      e = hipMemcpy(c->sell.slice_ptr, S.sptr.data(), (nsl + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-      e = hipMemcpy(c->sell.slice_width, swid.data(), nsl * sizeof(int32_t), hipMemcpyHostToDevice);
+      e = hipMemcpy(c->sell.slice_width, S.swid.data(), nsl * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(c->sell.rowlen, rowlen.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && slots)
-      e = hipMemcpy(c->sell.colt, scol.data(), slots * sizeof(uint32_t), hipMemcpyHostToDevice);
+      e = hipMemcpy(c->sell.colt, S.scol.data(), slots * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && slots)
-      e = hipMemcpy(c->sell.val, sval.data(), slots * sizeof(double2), hipMemcpyHostToDevice);
+      e = hipMemcpy(c->sell.val, S.sval.data(), slots * sizeof(double2), hipMemcpyHostToDevice);
+    int64_t stored = nnz;  // per-row entries actually present (padding excluded)
+    if (uniform)
+      for (int64_t sl = 0; sl < nsl; ++sl)
+        stored -= int64_t(S.nuni[sl]) * (std::min<int64_t>(n, sl * 64 + 64) - sl * 64);
+    c->sell_bytes = 20 * stored + 4 * n + 12 * nsl;
+    if (uniform) {
+      const int64_t us = S.uptr[nsl];
+      c->sell.uslots = us;
+      if (e == hipSuccess) e = hipMalloc(&c->sell.nuni, nsl * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc(&c->sell.uptr, (nsl + 1) * sizeof(int64_t));
+      if (e == hipSuccess) e = hipMalloc(&c->sell.ucolt, std::max<int64_t>(us, 1) * sizeof(uint32_t));
+      if (e == hipSuccess) e = hipMalloc(&c->sell.uval, std::max<int64_t>(us, 1) * sizeof(double2));
+      if (e == hipSuccess)
+        e = hipMemcpy(c->sell.nuni, S.nuni.data(), nsl * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(c->sell.uptr, S.uptr.data(), (nsl + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess && us)
+        e = hipMemcpy(c->sell.ucolt, S.ucol.data(), us * sizeof(uint32_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess && us)
+        e = hipMemcpy(c->sell.uval, S.uval.data(), us * sizeof(double2), hipMemcpyHostToDevice);
+      c->sell_bytes += 20 * us + 12 * nsl;
+    }
     c->use_sell = true;
   }
   c->plan = cfet::make_plan(n, nnz);
@@ -1066,7 +1246,8 @@ int cfet_stats(cfet_ctx* c, cfet_stats_t* s) {
   s->min_m_eff = d.exponentials ? d.min_m_eff : 0;
   s->breakdowns = d.breakdowns;
   s->path = c->last_path;
-  s->layout = c->use_sell ? 1 : 0;
+  s->layout = !c->use_sell ? 0 : (c->sell.nuni ? 2 : 1);
+  s->matrix_bytes = c->use_sell ? c->sell_bytes : 20 * c->A.nnz + 8 * (c->n + 1);
   s->status = d.status;
   s->last_norm = std::sqrt(d.last_norm2);
   harvest_events(c);

@@ -86,6 +86,15 @@ struct DevSELL {
   uint32_t* colt = nullptr;      // column | term << kTermShift (padding: 0)
   double2* val = nullptr;        // padding: 0
   int64_t slots = 0;
+  // Optional uniform part (null nuni: none).  nuni[s] entries that every row
+  // of slice s holds with the same column offset (column = row XOR offset),
+  // term and value are stored once, at uptr[s]; rowlen counts them too, and
+  // slice_width / slice_ptr cover only the remaining per-row entries.
+  int32_t* nuni = nullptr;
+  int64_t* uptr = nullptr;
+  uint32_t* ucolt = nullptr;     // offset | term << kTermShift
+  double2* uval = nullptr;
+  int64_t uslots = 0;
 };
 
 int sell_grid(int64_t n);

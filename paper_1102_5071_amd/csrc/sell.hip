@@ -10,6 +10,10 @@
 // every row) entry k of 64 consecutive rows then gathers 64 consecutive x
 // values.  Matrix streams are read non-temporally so they do not evict x from
 // the caches; padded slots are skipped (row lengths are stored per row).
+// Optionally the entries that every row of a slice holds with the same column
+// offset (column = row XOR offset), term and value, such as a site term's
+// flip with a uniform coupling, are stored once per slice ahead of the
+// per-row slots, so their values and columns are not streamed per row.
 #include <hip/hip_runtime.h>
 
 #include "cfet_internal.h"
@@ -50,14 +54,62 @@ __device__ double s_sum_partials(const double* __restrict__ part, int np, double
   return s_block_sum(s, red);
 }
 
-// y_row = sum_k w_{term} val x[col] over the row's entries (lane = row).
 template <int NT>
-__device__ __forceinline__ double2 sell_row(const DevSELL& S, int64_t slice, int lane, int64_t row,
+__device__ __forceinline__ void sell_acc(uint32_t ct, dvec2 v, double2 xv, const double* wl,
+                                         double& a0r, double& a0i, double& a1r, double& a1i) {
+  const double pr = v.x * xv.x - v.y * xv.y;
+  const double pi = v.x * xv.y + v.y * xv.x;
+  if (NT == 1) {
+    if (ct >> kTermShift) { a1r += pr; a1i += pi; } else { a0r += pr; a0i += pi; }
+  } else {
+    const double wt = wl[ct >> kTermShift];
+    a0r += wt * pr;
+    a0i += wt * pi;
+  }
+}
+
+// y_row = sum_k w_{term} val x[col] over the row's entries (lane = row; the
+// slice index is the same for the whole wavefront).
+template <int NT>
+__device__ __forceinline__ double2 sell_row(const DevSELL& S, int64_t slice_in, int lane, int64_t row,
                                             const double2* __restrict__ x, const double* wl) {
+  // slices number below 2^23 (rows below 2^29): the index fits a scalar register
+  const int64_t slice = __builtin_amdgcn_readfirstlane((int)slice_in);
   const int64_t base = S.slice_ptr[slice];
   const int width = S.slice_width[slice];
-  const int len = (row < S.n) ? (int)S.rowlen[row] : 0;
+  const bool valid = row < S.n;
+  int len = valid ? (int)S.rowlen[row] : 0;
   double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+  // uniform prefix: one (offset, term, value) per slot for the whole slice,
+  // column = row ^ offset; every row of the slice holds these entries
+  const int nu = S.nuni ? S.nuni[slice] : 0;
+  if (nu > 0) {
+    const int64_t ub = S.uptr[slice];
+    const uint32_t* __restrict__ uc = S.ucolt + ub;
+    const dvec2* __restrict__ uv = reinterpret_cast<const dvec2*>(S.uval) + ub;
+    int k = 0;
+    for (; k + 4 <= nu; k += 4) {
+      uint32_t ct[4];
+      dvec2 v[4];
+      double2 xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ct[u] = uc[k + u];
+        v[u] = uv[k + u];
+      }
+      // rows past n (last slice only) gather x[0] and are never stored
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = x[valid ? row ^ (int64_t)(ct[u] & kColMask) : 0];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sell_acc<NT>(ct[u], v[u], xv[u], wl, a0r, a0i, a1r, a1i);
+    }
+    for (; k < nu; ++k) {
+      const uint32_t ct = uc[k];
+      const double2 xv = x[valid ? row ^ (int64_t)(ct & kColMask) : 0];
+      sell_acc<NT>(ct, uv[k], xv, wl, a0r, a0i, a1r, a1i);
+    }
+    len = valid ? len - nu : 0;  // entries of this row in the per-row slots
+  }
   const uint32_t* __restrict__ cp = S.colt + base + lane;
   const dvec2* __restrict__ vp = reinterpret_cast<const dvec2*>(S.val) + base + lane;
   int k = 0;
@@ -79,31 +131,12 @@ __device__ __forceinline__ double2 sell_row(const DevSELL& S, int64_t slice, int
 #pragma unroll
     for (int u = 0; u < 4; ++u) xv[u] = (k + u < len) ? x[ct[u] & kColMask] : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double pr = v[u].x * xv[u].x - v[u].y * xv[u].y;
-      const double pi = v[u].x * xv[u].y + v[u].y * xv[u].x;
-      if (NT == 1) {
-        if (ct[u] >> kTermShift) { a1r += pr; a1i += pi; } else { a0r += pr; a0i += pi; }
-      } else {
-        const double wt = wl[ct[u] >> kTermShift];
-        a0r += wt * pr;
-        a0i += wt * pi;
-      }
-    }
+    for (int u = 0; u < 4; ++u) sell_acc<NT>(ct[u], v[u], xv[u], wl, a0r, a0i, a1r, a1i);
   }
   for (; k < len; ++k) {
     const uint32_t ct = __builtin_nontemporal_load(cp + (int64_t)k * 64);
     const dvec2 v = __builtin_nontemporal_load(vp + (int64_t)k * 64);
-    const double2 xv = x[ct & kColMask];
-    const double pr = v.x * xv.x - v.y * xv.y;
-    const double pi = v.x * xv.y + v.y * xv.x;
-    if (NT == 1) {
-      if (ct >> kTermShift) { a1r += pr; a1i += pi; } else { a0r += pr; a0i += pi; }
-    } else {
-      const double wt = wl[ct >> kTermShift];
-      a0r += wt * pr;
-      a0i += wt * pi;
-    }
+    sell_acc<NT>(ct, v, x[ct & kColMask], wl, a0r, a0i, a1r, a1i);
   }
   if (NT == 1) return make_double2(wl[0] * a0r + wl[1] * a1r, wl[0] * a0i + wl[1] * a1i);
   return make_double2(a0r, a0i);
@@ -121,7 +154,7 @@ struct SliceRange {
 __device__ __forceinline__ SliceRange slice_range(int64_t nslices) {
   constexpr int kXcds = 8;
   constexpr int kWaves = kSellBlock / 64;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index (uniform)
   const int nb = gridDim.x;
   if (nb % kXcds != 0) {
     return {(int64_t)blockIdx.x * kWaves + w, nslices, (int64_t)nb * kWaves};

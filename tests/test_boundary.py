@@ -130,3 +130,10 @@ def test_batch_struct_layout():
     # cfet_instance: 9 int32 then 7 cfet_drive (80 bytes each, 8-byte aligned)
     assert ctypes.sizeof(B._Drive) == 80
     assert ctypes.sizeof(B._Instance) == 40 + 7 * 80
+
+
+def test_stats_struct_layout():
+    # cfet_stats_t: 4 int64, 4 int32, double, int64, double, 4 double, 2 int32,
+    # int64 (the library static-asserts the same size)
+    assert ctypes.sizeof(B._Stats) == 120
+    assert B._Stats.matrix_bytes.offset == 112

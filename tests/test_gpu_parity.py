@@ -20,7 +20,7 @@ torch = pytest.importorskip("torch")
 B = pytest.importorskip("paper_1102_5071_amd.binding")
 
 PROP_TOL = 1e-10
-PATHS = ["multi", "single", "coop", "sell"]
+PATHS = ["multi", "single", "coop", "sell", "sell_uniform"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -54,8 +54,10 @@ def run_gpu(prob_H0, Hk, drives, psi0, t0, dt, nsteps, scheme, m, path=None):
         st = P.stats()
     if path is not None:
         # a persistent path whose rows do not fit falls back to the multi-kernel one
-        # ("sell" is the multi-kernel path on the sliced-ELL layout)
+        # ("sell", "sell_uniform": the multi-kernel path on the sliced-ELL layouts)
         assert B.PATH_NAMES[st["path"]] in (path, "multi")
+        if path.startswith("sell"):
+            assert st["layout"] == (2 if path == "sell_uniform" else 1)
         if path in ("single", "coop") and prob_H0.n <= 1024:
             assert B.PATH_NAMES[st["path"]] == path
     assert st["status"] == 0, st
@@ -91,8 +93,18 @@ def _apply_ref(H0, Hk, a, b, x):
     return y
 
 
-@pytest.mark.parametrize("layout", ["multi", "sell"])
-@pytest.mark.parametrize("case", ["ising10", "hydrogen_small", "ragged", "two_term", "heis12"])
+def heisenberg_principal(L, n, seed):
+    """Leading n x n block of a disordered Heisenberg chain and of sum sx: spin
+    structure with a ragged last slice (flips leaving the block are dropped)."""
+    rng = np.random.default_rng(seed)
+    H0 = I.heisenberg_chain(L, 1.0, rng.uniform(-1, 1, L)).toarray()[:n, :n]
+    H1 = I.sigma_x_sum(L).toarray()[:n, :n]
+    return I._dense_to_csr(H0), I._dense_to_csr(H1)
+
+
+@pytest.mark.parametrize("layout", ["multi", "sell", "sell_uniform"])
+@pytest.mark.parametrize("case", ["ising10", "hydrogen_small", "ragged", "two_term", "heis12",
+                                  "heis_block"])
 def test_apply_matches_reference(case, layout):
     rng = np.random.default_rng(5)
     if case == "ising10":
@@ -108,6 +120,10 @@ def test_apply_matches_reference(case, layout):
         drives = [{"kind": "cos", "A": 1.0, "omega": 1.0}]
     elif case == "two_term":
         H0, Hk, drives = I.noninteracting_spins(8, 0.3, 0.7, 1.1)
+    elif case == "heis_block":
+        H0, H1 = heisenberg_principal(10, 1000, 3)
+        Hk = [H1]
+        drives = [{"kind": "cos", "A": 1.0, "omega": 1.0}]
     else:
         p = I.config_heisenberg(L=12)
         H0, Hk, drives = p.H0, p.Hk, p.drives
@@ -118,6 +134,21 @@ def test_apply_matches_reference(case, layout):
         y = host(P.apply(dev(x), a, b))
     ref = _apply_ref(H0, Hk, a, b, x)
     assert rel(y, ref) < 1e-14
+
+
+def test_sell_uniform_stores_shared_flips_once():
+    # every row of sum sx holds one entry per site at column row ^ (1 << i) with
+    # value 1, so each 64-row slice stores those L entries once instead of 64 times
+    L = 12
+    p = I.config_heisenberg(L=L)
+    n, nsl = p.dim, p.dim // 64
+    with B.Propagator(p.H0, p.Hk, p.drives, path="sell") as P:
+        st1 = P.stats()
+    with B.Propagator(p.H0, p.Hk, p.drives, path="sell_uniform") as P:
+        st2 = P.stats()
+    assert (st1["layout"], st2["layout"]) == (1, 2)
+    assert st1["matrix_bytes"] == 20 * (p.H0.nnz + p.Hk[0].nnz) + 4 * n + 12 * nsl
+    assert st2["matrix_bytes"] <= st1["matrix_bytes"] - 20 * L * n + (20 * L + 12) * nsl
 
 
 # --------------------------------------------------------------------------
