@@ -76,6 +76,8 @@ thread_local std::string g_err;
 // automatic path choice by dimension
 constexpr int64_t kAutoSingleMaxN = 4096;
 constexpr int64_t kAutoCoopMaxN = int64_t(1) << 22;
+// device bytes the gradient may spend on keeping the recomputed projections
+constexpr size_t kGradStoreMax = size_t(16) << 30;
 static_assert(sizeof(cfet_stats_t) == 120 && offsetof(cfet_stats_t, matrix_bytes) == 112,
               "cfet_stats_t layout is part of the ABI");
 
@@ -226,7 +228,8 @@ int choose_path(const cfet_ctx* c) {
 
 int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
                          const SchemeTable& sc, int m, int path, hipStream_t st,
-                         double2* save = nullptr) {
+                         double2* save = nullptr, LzScalars* export_T = nullptr,
+                         double2* export_Y = nullptr) {
   const int nt1 = c->nterms + 1;
   if (c->profiling && c->events.used > 0) {
     (void)hipStreamSynchronize(c->last_stream);
@@ -298,7 +301,7 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
       return fail(c, CFET_ENOMEM, "cannot allocate the persistent z buffers");
     }
   }
-  cfet::PersistArgs pa;
+  cfet::PersistArgs pa{};
   pa.rowptr = c->A.rowptr;
   pa.colt = c->A.colt;
   pa.val = c->A.val;
@@ -319,8 +322,10 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
   pa.spin_limit = c->spin_limit;
   pa.timing = c->profiling ? 1 : 0;
   pa.save = save;
-  pa.export_T = nullptr;
+  pa.export_T = export_T;  // one record per exponential of the call
   pa.no_combine = 0;
+  pa.export_Y = export_Y;
+  pa.export_each = (export_T || export_Y) ? 1 : 0;
   const bool timed = c->profiling && c->events.used < c->events.cap;
   if (timed) (void)hipEventRecord(c->events.begin[c->events.used], st);
   e = cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop, path == 2,
@@ -344,7 +349,8 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
 // X; with no_combine psi is left unchanged.
 hipError_t persistent_exponential(cfet_ctx* c, int path, double2* psi, double2* basis,
                                   const double* wts_dev, double dt, int m, LzScalars* X,
-                                  bool no_combine, hipStream_t st) {
+                                  bool no_combine, hipStream_t st, double2* Y = nullptr,
+                                  unsigned long long* bar = nullptr) {
   cfet::PersistArgs pa{};
   pa.rowptr = c->A.rowptr;
   pa.colt = c->A.colt;
@@ -368,8 +374,10 @@ hipError_t persistent_exponential(cfet_ctx* c, int path, double2* psi, double2* 
   pa.save = nullptr;
   pa.export_T = X;
   pa.no_combine = no_combine ? 1 : 0;
+  pa.export_Y = Y;
+  if (bar) pa.bar = bar;  // cleared by the caller on the stream
   return cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop, path == 2,
-                                 path == 3 ? c->coop_blocks : 1, st);
+                                 path == 3 ? c->coop_blocks : 1, st, bar == nullptr);
 }
 
 }  // namespace
@@ -1033,14 +1041,33 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
           *zpart = nullptr;
   LzScalars *Spsi = nullptr, *Slam = nullptr;
   const size_t nn = size_t(n);
+  // The segment recomputation and the backward exponentials run on the
+  // persistent path when the operator fits it; otherwise exponential by
+  // exponential on the multi-kernel path.  With one driven term on a
+  // persistent path the recomputation also keeps, for every exponential, its
+  // projection and Y_j = H_1 w_j (the kernel forms that term apart anyway):
+  // the backward sweep then runs no Lanczos recurrence from psi.  That store
+  // takes seg * s * m vectors; above kGradStoreMax (or half the free device
+  // memory) the recurrence from psi is rerun instead, with the same result.
+  const int rpath = choose_path(c);
+  const size_t ystore = size_t(seg) * size_t(sc.s) * size_t(m) * nn * sizeof(double2);
+  bool keep = rpath != 1 && c->nterms == 1 && ystore <= kGradStoreMax;
+  if (keep) {
+    size_t free_b = 0, total_b = 0;
+    keep = hipMemGetInfo(&free_b, &total_b) == hipSuccess && ystore <= free_b / 2;
+  }
+  double2* Yall = nullptr;
+  LzScalars* Tall = nullptr;
   hipError_t e = gb.get(&psi, nn);
   if (e == hipSuccess) e = gb.get(&lam, nn);
   if (e == hipSuccess) e = gb.get(&vpsi, size_t(std::max(m - 1, 1)) * nn);
   if (e == hipSuccess) e = gb.get(&vlam, size_t(std::max(m - 1, 1)) * nn);
   if (e == hipSuccess) e = gb.get(&ckpt, size_t(std::max<int64_t>(nseg, 1)) * nn);
-  if (e == hipSuccess) e = gb.get(&before, size_t(seg) * size_t(sc.s) * nn);
+  if (e == hipSuccess && !keep) e = gb.get(&before, size_t(seg) * size_t(sc.s) * nn);
+  if (e == hipSuccess && keep) e = gb.get(&Yall, size_t(seg) * size_t(sc.s) * size_t(m) * nn);
+  if (e == hipSuccess && keep) e = gb.get(&Tall, size_t(seg) * size_t(sc.s));
   if (e == hipSuccess)
-    e = gb.get(&cpart, size_t(cfet::frechet_c_blocks(n)) * cfet::kMaxM * cfet::kMaxM);
+    e = gb.get(&cpart, size_t(cfet::frechet_part_blocks(n)) * cfet::kMaxM * cfet::kMaxM);
   if (e == hipSuccess) e = gb.get(&cmat, size_t(cfet::kMaxM) * cfet::kMaxM);
   if (e == hipSuccess) e = gb.get(&dz, size_t(K));
   if (e == hipSuccess) e = gb.get(&zval, 1);
@@ -1117,34 +1144,69 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
   wl.twp = dtw;
   cfet::TermWeights tw0;
   std::memset(&tw0, 0, sizeof(tw0));
-  // the segment recomputation and the backward exponentials run on the
-  // persistent path when the operator fits it (the recomputation is one launch
-  // per segment that stores the state before each exponential); otherwise
-  // exponential by exponential on the multi-kernel path
-  const int rpath = choose_path(c);
   const double* dw = reinterpret_cast<const double*>(dtw);
-  auto enqueue_back = [&](hipStream_t s_) -> hipError_t {
+  // one driven term without the store: the recurrence from psi still exports
+  // Y_j, and C is the product of two stored blocks of vectors
+  double2* vY = nullptr;
+  if (rpath != 1 && c->nterms == 1 && !keep) {
+    e = gb.get(&vY, size_t(m) * nn);
+    if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: workspace");
+  }
+  // barrier state of the two persistent launches per exponential, cleared by
+  // the prologue (one launch fewer each)
+  const int bw = cfet::persistent_barrier_words();
+  unsigned long long* gbar = nullptr;
+  if (rpath != 1) {
+    e = gb.get(&gbar, size_t(2) * bw);
+    if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: workspace");
+  }
+  auto enqueue_back = [&](hipStream_t s_, size_t ix) -> hipError_t {
     // the persistent exponential of lambda overwrites lambda with its result:
     // its first basis vector is then read from the copy lam0
+    if (keep) {
+      // record ix: weights, pieces, and the projection and Y of the recurrence
+      // from psi kept by the recomputation
+      const cfet::GradRec* rx = d_recs + ix;
+      const double* wx = reinterpret_cast<const double*>(reinterpret_cast<const char*>(rx) +
+                                                         offsetof(cfet::GradRec, tw));
+      LzScalars* Tx = Tall + ix;
+      hipError_t x = cfet::launch_grad_prologue(nullptr, nullptr, nullptr, nullptr, n, nullptr,
+                                                lam, lam0, gbar, bw, c->d_fault, s_);
+      if (x == hipSuccess)
+        x = persistent_exponential(c, rpath, lam, vlam, wx, -dt, m, Slam, false, s_, nullptr,
+                                   gbar);
+      if (x == hipSuccess)
+        x = cfet::launch_frechet_dots(n, lam0, vlam, Yall + ix * size_t(m) * nn, Tx, Slam, cpart,
+                                      cmat, s_);
+      if (x == hipSuccess)
+        x = cfet::launch_frechet_small_rec(Tx, Slam, cmat, dt, rx, dz, c->stats, nullptr, s_);
+      return x;
+    }
     hipError_t x = cfet::launch_grad_prologue(d_recs, d_cursor, d_cur, before, n, pb, lam,
-                                              rpath != 1 ? lam0 : nullptr, s_);
+                                              rpath != 1 ? lam0 : nullptr, gbar, 2 * bw,
+                                              c->d_fault, s_);
     if (rpath != 1) {
       // two persistent launches: the recurrence from psi (kept, not combined)
       // and the exponential of lambda (with -dt), both exporting their projection
-      if (x == hipSuccess) x = persistent_exponential(c, rpath, pb, vpsi, dw, dt, m, Spsi, true, s_);
-      if (x == hipSuccess) x = persistent_exponential(c, rpath, lam, vlam, dw, -dt, m, Slam, false, s_);
+      if (x == hipSuccess)
+        x = persistent_exponential(c, rpath, pb, vpsi, dw, dt, m, Spsi, true, s_, vY, gbar);
+      if (x == hipSuccess)
+        x = persistent_exponential(c, rpath, lam, vlam, dw, -dt, m, Slam, false, s_, nullptr,
+                                   gbar + bw);
     } else {
       if (x == hipSuccess) x = cfet::launch_norm_start(pb, n, c->plan, c->partA, s_);
       if (x == hipSuccess) x = cfet::launch_lanczos(c->A, c->nterms, c->plan, tw0, dt, m, wp, s_);
       if (x == hipSuccess) x = cfet::launch_norm_start(lam, n, c->plan, c->partA, s_);
       if (x == hipSuccess) x = cfet::launch_lanczos(c->A, c->nterms, c->plan, tw0, -dt, m, wl, s_);
     }
-    if (x == hipSuccess)
+    if (x == hipSuccess && vY)
+      x = cfet::launch_frechet_dots(n, lam0, vlam, vY, Spsi, Slam, cpart, cmat, s_);
+    else if (x == hipSuccess)
       x = cfet::launch_frechet_c(c->A, kstar + 1, pb, vpsi, rpath != 1 ? lam0 : lam, vlam, Spsi,
                                  Slam, cpart, cmat, s_);
-    if (x == hipSuccess) x = cfet::launch_frechet_small_rec(Spsi, Slam, cmat, dt, d_cur, dz, c->stats, s_);
+    if (x == hipSuccess)
+      x = cfet::launch_frechet_small_rec(Spsi, Slam, cmat, dt, d_cur, dz, c->stats, d_cursor, s_);
     if (x == hipSuccess && rpath == 1) x = cfet::launch_combine(n, c->plan, wl, s_);
-    if (x == hipSuccess) x = cfet::launch_grad_epilogue(d_cursor, s_);
     return x;
   };
   hipEvent_t staged = nullptr;
@@ -1162,7 +1224,7 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
     Wf[0] = psi;
     if (e == hipSuccess && rpath != 1) {
       rc = propagate_persistent(c, psi, t0 + double(s0) * dt, dt, s1 - s0, sc, m, rpath, st,
-                                before);
+                                before, Tall, Yall);
       if (rc != CFET_OK) return rc;
     } else if (e == hipSuccess) {
       e = cfet::launch_norm_start(psi, n, c->plan, c->partA, st);
@@ -1207,7 +1269,7 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
     if (e == hipSuccess) e = hipMemcpyAsync(d_cursor, hcur, sizeof(int), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(staged, st);
     if (e == hipSuccess) staged_pending = true;
-    for (size_t x = idx; x-- > 0 && e == hipSuccess;) e = enqueue_back(st);
+    for (size_t x = idx; x-- > 0 && e == hipSuccess;) e = enqueue_back(st, x);
   }
   if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: backward sweep");
   std::vector<double2> hz(size_t(K) + 1);

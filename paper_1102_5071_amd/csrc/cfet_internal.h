@@ -161,12 +161,18 @@ struct GradRec {
 // if lam_copy is set, lam to lam_copy.
 hipError_t launch_grad_prologue(const GradRec* recs, const int* cursor, GradRec* cur,
                                 const double2* before, int64_t n, double2* pb,
-                                const double2* lam, double2* lam_copy, hipStream_t st);
-hipError_t launch_grad_epilogue(int* cursor, hipStream_t st);
+                                const double2* lam, double2* lam_copy, unsigned long long* bar,
+                                int bar_words, int* fault, hipStream_t st);
 hipError_t launch_frechet_small_rec(const LzScalars* Spsi, const LzScalars* Slam,
                                     const double2* C, double dt, const GradRec* cur,
-                                    double2* dz, DevStats* stats, hipStream_t st);
+                                    double2* dz, DevStats* stats, int* cursor, hipStream_t st);
 int frechet_c_blocks(int64_t n);
+int frechet_part_blocks(int64_t n);  // blocks of partials either C kernel writes, at most
+// C from the stored lambda basis and Y_j = H_k* w_psi,j (exported by the
+// persistent recurrence from psi), same output as launch_frechet_c
+hipError_t launch_frechet_dots(int64_t n, const double2* lam0, const double2* lam_rest,
+                               const double2* Y, const LzScalars* Spsi, const LzScalars* Slam,
+                               double2* part, double2* C, hipStream_t st);
 hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
                             const double2* psi_rest, const double2* lam0, const double2* lam_rest,
                             const LzScalars* Spsi, const LzScalars* Slam, double2* part,
@@ -205,10 +211,16 @@ struct PersistArgs {
   LzScalars* export_T;      // optional: Lanczos scalars of the (last) exponential, with the
                             // stored basis psi, basis[..] scaled as v_j = w_j * inv_nrm[j]
   int no_combine;           // 1: stop after the Lanczos recurrence (psi unchanged)
+  double2* export_Y;        // optional, one driven term only: H_1 w_k of every stored
+                            // Lanczos vector w_k (k < m) at export_Y + k*n
+  int export_each;          // 1: export_T / export_Y hold one record per exponential of
+                            // the call (application order e: export_T + e,
+                            // export_Y + e*m*n) instead of the last one only
 };
 
+// reset = false: the caller has cleared args.bar and args.fault on the stream
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,
-                             hipStream_t st);
+                             hipStream_t st, bool reset = true);
 hipError_t persistent_max_blocks(int preset, int nterms, int* out);
 int persistent_rows_per_block(int preset, bool single);
 int persistent_barrier_words();

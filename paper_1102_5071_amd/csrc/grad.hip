@@ -8,9 +8,11 @@
 // Krylov spaces:
 //     g = beta_lam beta_psi e_1^T exp(M) e_{m_lam + 1},
 //     M = -i dt [[S, C], [0, T]],   C_kj = <v_lam,k | H_k* | v_psi,j>.
-// k_frechet_c forms C (partials per block, fixed-order reduction after), and
-// k_frechet_small exponentiates M against one unit vector by a Taylor series
-// with substeps and accumulates g into dz/du.
+// k_frechet_c forms C from the operator (partials per block, fixed-order
+// reduction after); k_frechet_dots forms it from Y_j = H_k* w_psi,j when the
+// recurrence from psi has stored those; k_frechet_small exponentiates M
+// against one unit vector by a Taylor series with substeps and accumulates g
+// into dz/du.
 #include <hip/hip_runtime.h>
 
 #include "cfet_internal.h"
@@ -23,7 +25,7 @@ namespace {
 constexpr int kCRows = 16;      // rows per tile of k_frechet_c
 constexpr int kCBlock = 256;
 constexpr int kSmallThreads = 128;
-constexpr int kSmallC = 32;  // C held in LDS by k_frechet_small up to 32 x 32
+constexpr int kSmallC = 32;  // k_frechet_small keeps a row of C in registers up to 32 wide
 
 __device__ __forceinline__ const double2* basis_vec(const double2* w0, const double2* rest,
                                                     int64_t n, int j) {
@@ -32,7 +34,7 @@ __device__ __forceinline__ const double2* basis_vec(const double2* w0, const dou
 
 // Partial C_kj (raw: stored vectors, no inv scaling) over the rows of this
 // block's tiles, for the ml x mp pairs in use (pair = k * mp + j).
-// part: [gridDim.x][kMaxM * kMaxM] complex.
+// part: [gridDim.x][ml * mp] complex.
 constexpr int kCPairsPerThread = (kMaxM * kMaxM + kCBlock - 1) / kCBlock;
 
 __global__ __launch_bounds__(kCBlock) void k_frechet_c(
@@ -94,33 +96,95 @@ __global__ __launch_bounds__(kCBlock) void k_frechet_c(
 #pragma unroll
   for (int q = 0; q < kCPairsPerThread; ++q) {
     const int pair = threadIdx.x + q * kCBlock;
-    if (pair < npairs) part[(int64_t)blockIdx.x * kMaxM * kMaxM + pair] = acc[q];
+    if (pair < npairs) part[(int64_t)blockIdx.x * npairs + pair] = acc[q];
   }
 }
 
-// C[k][j] = inv_lam[k] inv_psi[j] * sum over blocks of the partials (fixed
-// order; one thread per pair, consecutive pairs read consecutive partials).
+// The same partials from stored vectors: Y_j = H_k* w_psi,j (j < mp, at
+// Y + j n) and the lambda basis.  Each block takes one contiguous range of
+// rows in tiles of kDRows staged in LDS.
+constexpr int kDRows = 32;
+
+__global__ __launch_bounds__(kCBlock) void k_frechet_dots(
+    int64_t n, const double2* __restrict__ lam0, const double2* __restrict__ lam_rest,
+    const double2* __restrict__ Y, const LzScalars* __restrict__ Spsi,
+    const LzScalars* __restrict__ Slam, double2* __restrict__ part) {
+  __shared__ double2 Ys[kDRows][kMaxM];
+  __shared__ double2 Us[kDRows][kMaxM];
+  const int mp = Spsi->m_eff, ml = Slam->m_eff;
+  const int mx = max(mp, ml);
+  const int npairs = ml * mp;
+  double2 acc[kCPairsPerThread];
+#pragma unroll
+  for (int q = 0; q < kCPairsPerThread; ++q) acc[q] = make_double2(0, 0);
+  const int64_t ntiles = (n + kDRows - 1) / kDRows;
+  const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * per, t1 = min(ntiles, t0 + per);
+  for (int64_t tile = t0; tile < t1 && mx > 0; ++tile) {
+    const int64_t r0 = tile * kDRows;
+    __syncthreads();
+    // consecutive threads take consecutive rows of one vector
+    for (int t = threadIdx.x; t < kDRows * mx; t += blockDim.x) {
+      const int j = t / kDRows, rl = t % kDRows;
+      const int64_t r = r0 + rl;
+      double2 y = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
+      if (r < n) {
+        if (j < mp) y = Y[(int64_t)j * n + r];
+        if (j < ml) u = basis_vec(lam0, lam_rest, n, j)[r];
+      }
+      Ys[rl][j] = y;
+      Us[rl][j] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kCPairsPerThread; ++q) {
+      const int pair = threadIdx.x + q * kCBlock;
+      if (pair < npairs) {
+        const int k = pair / mp, j = pair % mp;
+        double2 a = acc[q];
+        for (int rl = 0; rl < kDRows; ++rl) {
+          const double2 uu = Us[rl][k], yy = Ys[rl][j];
+          a.x += uu.x * yy.x + uu.y * yy.y;
+          a.y += uu.x * yy.y - uu.y * yy.x;
+        }
+        acc[q] = a;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kCPairsPerThread; ++q) {
+    const int pair = threadIdx.x + q * kCBlock;
+    if (pair < npairs) part[(int64_t)blockIdx.x * npairs + pair] = acc[q];
+  }
+}
+
+// C[k][j] = inv_lam[k] inv_psi[j] * sum over blocks of the partials, one
+// wavefront per pair: lane l adds blocks l, l + 64, ... in order, then a fixed
+// butterfly over the lanes (the same order on every run).
 __global__ __launch_bounds__(256) void k_frechet_c_reduce(const double2* __restrict__ part,
                                                           int nb, const LzScalars* Spsi,
                                                           const LzScalars* Slam,
                                                           double2* __restrict__ C) {
-  const int pair = blockIdx.x * blockDim.x + threadIdx.x;
   const int mp = Spsi->m_eff, ml = Slam->m_eff;
-  if (pair >= kMaxM * kMaxM) return;
+  const int npairs = ml * mp;
+  const int pair = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (pair >= npairs) return;  // whole wavefronts leave together
   double sr = 0.0, si = 0.0;
-  int k = pair / kMaxM, j = pair % kMaxM;  // pairs past the used ones clear C
-  if (pair < ml * mp) {
-    k = pair / mp;
-    j = pair % mp;
-    for (int b = 0; b < nb; ++b) {
-      const double2 v = part[(int64_t)b * kMaxM * kMaxM + pair];
-      sr += v.x;
-      si += v.y;
-    }
+  for (int b = l; b < nb; b += 64) {
+    const double2 v = part[(int64_t)b * npairs + pair];
+    sr += v.x;
+    si += v.y;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
+  }
+  if (l == 0) {
+    const int k = pair / mp, j = pair % mp;
     const double sc = Slam->inv_nrm[k] * Spsi->inv_nrm[j];
-    sr *= sc;
-    si *= sc;
-    C[k * kMaxM + j] = make_double2(sr, si);
+    C[k * kMaxM + j] = make_double2(sr * sc, si * sc);
   }
 }
 
@@ -132,30 +196,47 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
     const LzScalars* __restrict__ Spsi, const LzScalars* __restrict__ Slam,
     const double2* __restrict__ C, double dt, int npairs, int p0, double w0, int p1, double w1,
     int p2, double w2, int p3, double w3, double2* __restrict__ dz, DevStats* stats,
-    const GradRec* __restrict__ rec) {
-  __shared__ double2 v[2 * kMaxM], term[2 * kMaxM];
-  __shared__ double2 Cs[kSmallC][kSmallC];  // C when ml, mp <= kSmallC
+    const GradRec* __restrict__ rec, int* cursor) {
+  __shared__ double2 tb[2][2 * kMaxM];
   __shared__ double red[2];
-  __shared__ int again;
   const int ml = Slam->m_eff, mp = Spsi->m_eff;
   const int nm = ml + mp;
   const int r = threadIdx.x;
+  // the record of this exponential was taken by the prologue: step the cursor
+  // to the one before it (also for a zero state)
+  if (cursor && r == 0) *cursor -= 1;
   if (ml == 0 || mp == 0) return;  // a zero state: no contribution
-  const bool lds_c = ml <= kSmallC && mp <= kSmallC;
-  if (lds_c) {
-    for (int t = r; t < ml * mp; t += blockDim.x) Cs[t / mp][t % mp] = C[(t / mp) * kMaxM + t % mp];
-    __syncthreads();
-  }
-  // row r of M: coefficients (times -i dt) and the infinity norm
-  double rowsum = 0.0;
+  // row r of C in registers when mp <= kSmallC (the Taylor loop then reads
+  // only the term vector from LDS)
+  const bool reg_c = mp <= kSmallC;
+  double2 creg[kSmallC];
+#pragma unroll
+  for (int j = 0; j < kSmallC; ++j)
+    creg[j] = (reg_c && r < ml && j < mp) ? C[r * kMaxM + j] : make_double2(0.0, 0.0);
+  // row r of K = [[S, C], [0, T]]: tridiagonal part in registers (read once),
+  // and the infinity norm
+  double ad = 0.0, bl = 0.0, bu = 0.0;
+  bool hasl = false, hasu = false;
   if (r < ml) {
-    rowsum = fabs(Slam->alpha[r]) + (r > 0 ? Slam->beta[r - 1] : 0.0) +
-             (r + 1 < ml ? Slam->beta[r] : 0.0);
-    for (int j = 0; j < mp; ++j) rowsum += hypot(C[r * kMaxM + j].x, C[r * kMaxM + j].y);
+    ad = Slam->alpha[r];
+    hasl = r > 0;
+    hasu = r + 1 < ml;
+    if (hasl) bl = Slam->beta[r - 1];
+    if (hasu) bu = Slam->beta[r];
   } else if (r < nm) {
     const int q = r - ml;
-    rowsum = fabs(Spsi->alpha[q]) + (q > 0 ? Spsi->beta[q - 1] : 0.0) +
-             (q + 1 < mp ? Spsi->beta[q] : 0.0);
+    ad = Spsi->alpha[q];
+    hasl = q > 0;
+    hasu = q + 1 < mp;
+    if (hasl) bl = Spsi->beta[q - 1];
+    if (hasu) bu = Spsi->beta[q];
+  }
+  double rowsum = fabs(ad) + bl + bu;
+  if (r < ml && reg_c) {
+#pragma unroll
+    for (int j = 0; j < kSmallC; ++j) rowsum += hypot(creg[j].x, creg[j].y);  // zero past mp
+  } else if (r < ml) {
+    for (int j = 0; j < mp; ++j) rowsum += hypot(C[r * kMaxM + j].x, C[r * kMaxM + j].y);
   }
   rowsum *= fabs(dt);
   // block maximum of rowsum
@@ -166,54 +247,62 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
   const double nrm = fmax(red[0], red[1]);
   const int nsub = max(1, (int)ceil(2.0 * nrm));
   const double h = dt / nsub;
-  if (r < 2 * kMaxM) v[r] = make_double2(r == ml ? 1.0 : 0.0, 0.0);
-  __syncthreads();
+  // thread r < nm owns entry r of v; the Taylor terms alternate between two
+  // LDS buffers, so one barrier per term both publishes the new term and
+  // decides (any entry still moving) whether to go on
+  double2 vr = make_double2(r == ml ? 1.0 : 0.0, 0.0);
   for (int sub = 0; sub < nsub; ++sub) {
-    if (r < 2 * kMaxM) term[r] = v[r];
+    if (r < nm) tb[0][r] = vr;
     __syncthreads();
+    int cur = 0;
     for (int kk = 1; kk < 60; ++kk) {
-      // nxt = (M/nsub) term / kk, M x = -i h (K x) with K = [[S, C], [0, T]]
-      double2 kx = make_double2(0.0, 0.0);
-      if (r < ml) {
-        double ar = Slam->alpha[r] * term[r].x, ai = Slam->alpha[r] * term[r].y;
-        if (r > 0) { ar += Slam->beta[r - 1] * term[r - 1].x; ai += Slam->beta[r - 1] * term[r - 1].y; }
-        if (r + 1 < ml) { ar += Slam->beta[r] * term[r + 1].x; ai += Slam->beta[r] * term[r + 1].y; }
-        for (int j = 0; j < mp; ++j) {
-          const double2 c = lds_c ? Cs[r][j] : C[r * kMaxM + j], x = term[ml + j];
-          ar += c.x * x.x - c.y * x.y;
-          ai += c.x * x.y + c.y * x.x;
+      // next term = (-i h / kk) K term, K = [[S, C], [0, T]]
+      const double2* __restrict__ t = tb[cur];
+      bool moving = false;
+      if (r < nm) {
+        double ar = ad * t[r].x, ai = ad * t[r].y;
+        if (hasl) { ar += bl * t[r - 1].x; ai += bl * t[r - 1].y; }
+        if (hasu) { ar += bu * t[r + 1].x; ai += bu * t[r + 1].y; }
+        if (r < ml && reg_c) {
+          double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;  // even / odd j
+#pragma unroll
+          for (int j = 0; j < kSmallC; j += 2) {
+            if (j < mp) {
+              const double2 c = creg[j], x = t[ml + j];
+              er += c.x * x.x - c.y * x.y;
+              ei += c.x * x.y + c.y * x.x;
+            }
+            if (j + 1 < mp) {
+              const double2 c = creg[j + 1], x = t[ml + j + 1];
+              orr += c.x * x.x - c.y * x.y;
+              oi += c.x * x.y + c.y * x.x;
+            }
+          }
+          ar += er + orr;
+          ai += ei + oi;
+        } else if (r < ml) {
+          for (int j = 0; j < mp; ++j) {
+            const double2 c = C[r * kMaxM + j], x = t[ml + j];
+            ar += c.x * x.x - c.y * x.y;
+            ai += c.x * x.y + c.y * x.x;
+          }
         }
-        kx = make_double2(ar, ai);
-      } else if (r < nm) {
-        const int q = r - ml;
-        double ar = Spsi->alpha[q] * term[r].x, ai = Spsi->alpha[q] * term[r].y;
-        if (q > 0) { ar += Spsi->beta[q - 1] * term[r - 1].x; ai += Spsi->beta[q - 1] * term[r - 1].y; }
-        if (q + 1 < mp) { ar += Spsi->beta[q] * term[r + 1].x; ai += Spsi->beta[q] * term[r + 1].y; }
-        kx = make_double2(ar, ai);
+        const double hk = h / kk;
+        const double2 nt = make_double2(hk * ai, -hk * ar);
+        vr.x += nt.x;
+        vr.y += nt.y;
+        tb[cur ^ 1][r] = nt;
+        moving = (fabs(nt.x) + fabs(nt.y)) > 1e-18 * (fabs(vr.x) + fabs(vr.y) + 1e-300);
       }
-      // -i h kx / kk
-      const double2 nt = make_double2(h * kx.y / kk, -h * kx.x / kk);
-      __syncthreads();
-      if (r < nm) {
-        v[r].x += nt.x;
-        v[r].y += nt.y;
-      }
-      if (r == 0) again = 0;
-      __syncthreads();
-      if (r < nm) {
-        const double tn = fabs(nt.x) + fabs(nt.y);
-        const double vn = fabs(v[r].x) + fabs(v[r].y);
-        if (tn > 1e-18 * (vn + 1e-300)) again = 1;
-        term[r] = nt;
-      }
-      __syncthreads();
-      if (!again) break;
+      const int any = __syncthreads_or(moving ? 1 : 0);
+      cur ^= 1;
+      if (!any) break;
     }
     __syncthreads();
   }
   if (r == 0) {
     const double bb = Slam->beta0 * Spsi->beta0;
-    const double2 g = make_double2(bb * v[0].x, bb * v[0].y);
+    const double2 g = make_double2(bb * vr.x, bb * vr.y);
     int ps[4] = {p0, p1, p2, p3};
     double ws[4] = {w0, w1, w2, w3};
     if (rec) {  // pairs from device memory (replayed graphs)
@@ -275,19 +364,23 @@ __global__ __launch_bounds__(256) void k_grad_prologue(const GradRec* __restrict
                                                        const double2* __restrict__ before,
                                                        int64_t n, double2* __restrict__ pb,
                                                        const double2* __restrict__ lam,
-                                                       double2* __restrict__ lam_copy) {
-  const int idx = *cursor;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *cur = recs[idx];
-  const double2* __restrict__ src = before + (int64_t)idx * n;
+                                                       double2* __restrict__ lam_copy,
+                                                       unsigned long long* __restrict__ bar,
+                                                       int bar_words, int* __restrict__ fault) {
+  // cursor == nullptr: only the lambda copy and the barrier state
+  const int idx = cursor ? *cursor : 0;
+  if (cursor && blockIdx.x == 0 && threadIdx.x == 0) *cur = recs[idx];
+  // barrier state of the persistent launches that follow (they skip their own reset)
+  if (bar && blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < bar_words; i += blockDim.x) bar[i] = 0ull;
+    if (threadIdx.x == 0) *fault = 0;
+  }
+  const double2* __restrict__ src = cursor ? before + (int64_t)idx * n : nullptr;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    pb[i] = src[i];
+    if (src) pb[i] = src[i];
     if (lam_copy) lam_copy[i] = lam[i];
   }
-}
-
-__global__ void k_grad_epilogue(int* cursor) {
-  if (threadIdx.x == 0) *cursor -= 1;
 }
 
 __global__ void k_zero2(double2* p, int n) {
@@ -302,6 +395,34 @@ int frechet_c_blocks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 128));
 }
 
+static int frechet_dots_blocks(int64_t n) {
+  const int64_t tiles = (n + kDRows - 1) / kDRows;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 256));
+}
+
+int frechet_part_blocks(int64_t n) {
+  return std::max(frechet_c_blocks(n), frechet_dots_blocks(n));
+}
+
+static hipError_t launch_c_reduce(const double2* part, int nb, const LzScalars* Spsi,
+                                  const LzScalars* Slam, double2* C, hipStream_t st) {
+  // one wavefront per pair in use (at most kMaxM^2; the kernel reads m_eff)
+  hipLaunchKernelGGL(k_frechet_c_reduce, dim3((kMaxM * kMaxM + 3) / 4), dim3(256), 0, st, part,
+                     nb, Spsi, Slam, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_frechet_dots(int64_t n, const double2* lam0, const double2* lam_rest,
+                               const double2* Y, const LzScalars* Spsi, const LzScalars* Slam,
+                               double2* part, double2* C, hipStream_t st) {
+  const int nb = frechet_dots_blocks(n);
+  hipLaunchKernelGGL(k_frechet_dots, dim3(nb), dim3(kCBlock), 0, st, n, lam0, lam_rest, Y, Spsi,
+                     Slam, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_c_reduce(part, nb, Spsi, Slam, C, st);
+}
+
 hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
                             const double2* psi_rest, const double2* lam0, const double2* lam_rest,
                             const LzScalars* Spsi, const LzScalars* Slam, double2* part,
@@ -311,9 +432,7 @@ hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
                      term, psi0, psi_rest, lam0, lam_rest, Spsi, Slam, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_frechet_c_reduce, dim3((kMaxM * kMaxM + 255) / 256), dim3(256), 0, st,
-                     part, nb, Spsi, Slam, C);
-  return hipGetLastError();
+  return launch_c_reduce(part, nb, Spsi, Slam, C, st);
 }
 
 hipError_t launch_frechet_small(const LzScalars* Spsi, const LzScalars* Slam, const double2* C,
@@ -321,29 +440,25 @@ hipError_t launch_frechet_small(const LzScalars* Spsi, const LzScalars* Slam, co
                                 double2* dz, DevStats* stats, hipStream_t st) {
   hipLaunchKernelGGL(k_frechet_small, dim3(1), dim3(kSmallThreads), 0, st, Spsi, Slam, C, dt,
                      npairs, p[0], w[0], p[1], w[1], p[2], w[2], p[3], w[3], dz, stats,
-                     (const GradRec*)nullptr);
+                     (const GradRec*)nullptr, (int*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_frechet_small_rec(const LzScalars* Spsi, const LzScalars* Slam,
                                     const double2* C, double dt, const GradRec* cur,
-                                    double2* dz, DevStats* stats, hipStream_t st) {
+                                    double2* dz, DevStats* stats, int* cursor, hipStream_t st) {
   hipLaunchKernelGGL(k_frechet_small, dim3(1), dim3(kSmallThreads), 0, st, Spsi, Slam, C, dt, 0,
-                     0, 0.0, 0, 0.0, 0, 0.0, 0, 0.0, dz, stats, cur);
+                     0, 0.0, 0, 0.0, 0, 0.0, 0, 0.0, dz, stats, cur, cursor);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_prologue(const GradRec* recs, const int* cursor, GradRec* cur,
                                 const double2* before, int64_t n, double2* pb,
-                                const double2* lam, double2* lam_copy, hipStream_t st) {
+                                const double2* lam, double2* lam_copy, unsigned long long* bar,
+                                int bar_words, int* fault, hipStream_t st) {
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
   hipLaunchKernelGGL(k_grad_prologue, dim3(nb), dim3(256), 0, st, recs, cursor, cur, before, n,
-                     pb, lam, lam_copy);
-  return hipGetLastError();
-}
-
-hipError_t launch_grad_epilogue(int* cursor, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad_epilogue, dim3(1), dim3(64), 0, st, cursor);
+                     pb, lam, lam_copy, bar, bar_words, fault);
   return hipGetLastError();
 }
 

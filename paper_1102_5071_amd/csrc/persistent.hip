@@ -420,16 +420,19 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
       double c1 = 0.0, c2 = 0.0, c3 = 0.0;
       double S1 = 0.0, S2 = 0.0;  // block sums of <u, z> and ||u||^2 of the last phase
       double scale = 0.0, alpha_prev = 0.0, inv_prev = 0.0;
+      // index of this exponential in application order within the call
+      const int64_t eidx = step * A.s + (A.s - 1 - i);
+      LzScalars* const XT = (A.export_T && A.export_each) ? A.export_T + eidx : A.export_T;
+      double2* const XY =
+          (A.export_Y && A.export_each) ? A.export_Y + (size_t)eidx * (size_t)m * (size_t)n
+                                        : A.export_Y;
       // u_0 = psi on the own rows (the previous exponential's barrier or the
       // weights' __syncthreads above ended every read of the ring)
 #pragma unroll
       for (int p = 0; p < PMAX; ++p)
         if (lane == 0 && rowp[p] >= 0) {
           lu[0][rowp[p] - r0] = u1[p];
-          if (A.save) {  // the state before this exponential, in application order
-            const int64_t e = step * A.s + (A.s - 1 - i);
-            A.save[e * n + rowp[p]] = u1[p];
-          }
+          if (A.save) A.save[eidx * n + rowp[p]] = u1[p];  // the state before this exponential
         }
       __syncthreads();
       gather(0);
@@ -567,6 +570,16 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
               }
             }
           }
+          if (NT == 1 && XY) {
+            // H_1 u_k on this row (the driven term alone, before weighting)
+            double hr = a1r, hi = a1i;
+#pragma unroll
+            for (int off = G / 2; off >= 1; off >>= 1) {
+              hr += __shfl_xor(hr, off, G);
+              hi += __shfl_xor(hi, off, G);
+            }
+            if (lane == 0 && rowp[p] >= 0) XY[(size_t)k * (size_t)n + rowp[p]] = make_double2(hr, hi);
+          }
           double yr, yi;
           if (NT == 1) {
             yr = w0 * a0r + w1 * a1r;
@@ -628,17 +641,17 @@ __global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
           ls.expo += 1;
           ls.brk += 1;
           ls.minm = 0;
-          if (A.export_T) {
-            A.export_T->beta0 = 0.0;
-            A.export_T->m_eff = 0;
+          if (XT) {
+            XT->beta0 = 0.0;
+            XT->m_eff = 0;
           }
         }
         continue;
       }
       __syncthreads();
-      if (A.export_T && blockIdx.x == 0) {
+      if (XT && blockIdx.x == 0) {
         // the projection of this exponential: u_j = nu_j v_j, so inv_nrm = 1 / nu
-        LzScalars* X = A.export_T;
+        LzScalars* X = XT;
         const int t = threadIdx.x;
         if (t < meff) {
           X->alpha[t] = sh.alpha[t];
@@ -822,12 +835,15 @@ const void* persistent_kernel(int preset, int nterms, bool single) {
 }
 
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,
-                             hipStream_t st) {
+                             hipStream_t st, bool reset) {
   const void* fn = persistent_kernel(preset, args.nterms, single);
   if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_persist_reset, dim3(1), dim3(64), 0, st, args.bar, args.fault);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (reset) {
+    hipLaunchKernelGGL(k_persist_reset, dim3(1), dim3(64), 0, st, args.bar, args.fault);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   PersistArgs a = args;
   void* kargs[] = {&a};
   if (single) {
