@@ -124,11 +124,12 @@ typedef struct {
  * (n > 2^22, where only the multi-kernel path runs) default to
  * CFET_LAYOUT_SELL_UNIFORM below; this flag alone selects plain SELL-64. */
 #define CFET_LAYOUT_SELL 0x100u
-/* SELL-64 as above, plus per slice a uniform part: the entries that all 64
- * rows of a slice hold with the same column offset (column = row XOR offset),
- * term and value (e.g. a site operator's flip with one coupling) are stored
- * once per slice instead of once per row.  Same results up to the order of
- * summation; detection runs on the host at cfet_create.  Implies
+/* SELL-64 as above, plus per slice a shared part: an entry that at least 8
+ * rows of a slice (all of them, in a slice of fewer rows) hold with the same
+ * column offset (column = row XOR offset), term and value -- e.g. a site
+ * operator's flip with one coupling -- is stored once per slice with a mask of
+ * the rows holding it, instead of once per row.  Same results up to the order
+ * of summation; detection runs on the host at cfet_create.  Implies
  * CFET_LAYOUT_SELL. */
 #define CFET_LAYOUT_SELL_UNIFORM 0x200u
 
@@ -152,11 +153,11 @@ typedef struct {
                                 SpMV phases, reductions/barriers, small exponentials,
                                 recombinations (microseconds, cumulative) */
   int32_t layout;            /* operator storage of the multi-kernel path: 0 merged CSR,
-                                1 SELL-64, 2 SELL-64 with uniform parts */
+                                1 SELL-64, 2 SELL-64 with shared parts */
   int32_t reserved;
   int64_t matrix_bytes;      /* stored operator bytes one application of that layout
-                                reads (values, columns, row and slice data; padding
-                                excluded) */
+                                reads (values, columns, masks, row and slice data;
+                                padding excluded) */
 } cfet_stats_t;
 
 /* Build a context for H(t) = H0 + sum_k f_k(t) Hk[k], k < nterms

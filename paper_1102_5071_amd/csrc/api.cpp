@@ -160,6 +160,7 @@ void free_ctx(cfet_ctx* c) {
   if (c->sell.uptr) (void)hipFree(c->sell.uptr);
   if (c->sell.ucolt) (void)hipFree(c->sell.ucolt);
   if (c->sell.uval) (void)hipFree(c->sell.uval);
+  if (c->sell.umask) (void)hipFree(c->sell.umask);
   if (c->basis) (void)hipFree(c->basis);
   if (c->partA) (void)hipFree(c->partA);
   if (c->partB) (void)hipFree(c->partB);
@@ -399,19 +400,24 @@ struct GradBuffers {
 };
 
 // Host staging of the SELL-64 layout.  Row r lists the driven terms' entries
-// (H1, H2, ... each in the caller's order) and then H0's.  With `uniform`, the
-// entries that every row of a slice holds with the same (row XOR column,
-// term, value) go to the slice's uniform part, in the slice's first row's
-// order, and are left out of the per-row slots.
+// (H1, H2, ... each in the caller's order) and then H0's.  With `uniform`,
+// every (row XOR column, term, value) that at least kSharedMinRows rows of a
+// slice hold (all of them, in a slice of fewer rows) becomes one shared entry
+// of the slice with a 64-bit mask of those rows, in order of first
+// appearance (rows in order); the per-row slots keep the rest.
+constexpr int kSharedMinRows = 8;
+
 struct SellStage {
   std::vector<int64_t> sptr;
   std::vector<int32_t> swid;
+  std::vector<int32_t> rlen;   // per-row slots in use
   std::vector<uint32_t> scol;
   std::vector<double> sval;
   std::vector<int32_t> nuni;
   std::vector<int64_t> uptr;
   std::vector<uint32_t> ucol;
   std::vector<double> uval;
+  std::vector<uint64_t> umask;
 };
 
 template <class F>
@@ -423,83 +429,91 @@ void for_sell_row(const std::vector<HostCSR>& mats, int nterms, int64_t r, F f) 
   }
 }
 
-// Entries shared by all rows of one slice: candidates are the first row's
-// entries keyed by (row XOR column, term); a candidate is kept if every row
-// holds it exactly once with bit-identical value.
-struct SliceUniform {
-  std::vector<uint32_t> key;
-  std::vector<double> val;
-  std::vector<int32_t> cnt;
-  std::vector<int64_t> last;
+// Shared entries of one slice: (row XOR column | term << kTermShift, value
+// bits) keys in a small open-addressing table, with the mask of rows holding
+// each (a row holds a key at most once: columns of one term are distinct).
+struct SliceShared {
+  struct Cand {
+    uint32_t key;
+    uint64_t re, im;
+    uint64_t mask;
+    int count;
+  };
+  std::vector<Cand> cand;
   std::vector<char> keep;
-  std::vector<int32_t> table;  // open addressing: candidate index + 1, 0 = empty
-  uint32_t mask = 0;
-  int bits = 0;
-
-  int find(uint32_t k) const {
-    if (table.empty()) return -1;
-    uint32_t h = (k * 0x9E3779B1u) >> (32 - bits);
-    while (table[h]) {
-      const int i = table[h] - 1;
-      if (key[i] == k) return i;
-      h = (h + 1) & mask;
-    }
-    return -1;
-  }
+  std::vector<int32_t> table;  // candidate index + 1, 0 = empty
+  uint32_t tmask = 0;
 
   static uint32_t make_key(int64_t r, int32_t col, int term) {
     return uint32_t(int64_t(col) ^ r) | (uint32_t(term) << cfet::kTermShift);
   }
-
-  // Returns the number of kept entries of rows [r0, r1).
-  int run(const std::vector<HostCSR>& mats, int nterms, int64_t r0, int64_t r1) {
-    key.clear();
-    val.clear();
-    for_sell_row(mats, nterms, r0, [&](int term, int32_t col, const double* v) {
-      key.push_back(make_key(r0, col, term));
-      val.push_back(v[0]);
-      val.push_back(v[1]);
-    });
-    const int nc = int(key.size());
-    table.clear();
-    if (nc == 0) return 0;
-    bits = 1;
-    while ((1 << bits) < 2 * nc) ++bits;
-    mask = (1u << bits) - 1u;
-    table.assign(size_t(1) << bits, 0);
-    cnt.assign(nc, 0);
-    last.assign(nc, -1);
-    keep.assign(nc, 1);
-    for (int i = 0; i < nc; ++i) {
-      const int j = find(key[i]);
-      if (j >= 0) {  // repeated in the first row: neither copy is uniform
-        keep[j] = keep[i] = 0;
-        continue;
-      }
-      uint32_t h = (key[i] * 0x9E3779B1u) >> (32 - bits);
-      while (table[h]) h = (h + 1) & mask;
-      table[h] = i + 1;
+  static uint64_t bits(double v) {
+    uint64_t u;
+    std::memcpy(&u, &v, sizeof(u));
+    return u;
+  }
+  uint32_t slot(uint32_t key, uint64_t re, uint64_t im) const {
+    uint64_t h = uint64_t(key) * 0x9E3779B97F4A7C15ull;
+    h ^= (re + 0x632BE59BD9B4E019ull) * 0xC2B2AE3D27D4EB4Full;
+    h ^= (im + 0x94D049BB133111EBull) * 0x165667B19E3779F9ull;
+    return uint32_t(h >> 32) & tmask;
+  }
+  int find(uint32_t key, uint64_t re, uint64_t im) const {
+    if (table.empty()) return -1;
+    for (uint32_t h = slot(key, re, im);; h = (h + 1) & tmask) {
+      const int i = table[h] - 1;
+      if (i < 0) return -1;
+      if (cand[i].key == key && cand[i].re == re && cand[i].im == im) return i;
     }
-    for (int64_t r = r0; r < r1; ++r) {
-      for_sell_row(mats, nterms, r, [&](int term, int32_t col, const double* v) {
-        const int j = find(make_key(r, col, term));
-        if (j < 0) return;
-        if (last[j] == r || std::memcmp(v, &val[2 * j], 2 * sizeof(double)) != 0) keep[j] = 0;
-        last[j] = r;
-        ++cnt[j];
-      });
-    }
-    int nu = 0;
-    for (int i = 0; i < nc; ++i) {
-      if (cnt[i] != r1 - r0) keep[i] = 0;
-      nu += keep[i];
-    }
-    return nu;
   }
 
-  bool kept(int64_t r, int32_t col, int term) const {
-    const int j = find(make_key(r, col, term));
-    return j >= 0 && keep[j];
+  // Returns the number of shared entries of rows [r0, r1) (at most 64 rows).
+  int run(const std::vector<HostCSR>& mats, int nterms, int64_t r0, int64_t r1,
+          const std::vector<int32_t>& rowlen) {
+    cand.clear();
+    int64_t total = 0;
+    for (int64_t r = r0; r < r1; ++r) total += rowlen[r];
+    table.clear();
+    if (total == 0) return 0;
+    uint32_t size = 2;
+    while (size < 2 * uint64_t(total)) size <<= 1;
+    tmask = size - 1;
+    table.assign(size, 0);
+    for (int64_t r = r0; r < r1; ++r) {
+      const uint64_t bit = uint64_t(1) << (r - r0);
+      for_sell_row(mats, nterms, r, [&](int term, int32_t col, const double* v) {
+        const uint32_t key = make_key(r, col, term);
+        const uint64_t re = bits(v[0]), im = bits(v[1]);
+        uint32_t h = slot(key, re, im);
+        for (;; h = (h + 1) & tmask) {
+          const int i = table[h] - 1;
+          if (i < 0) {
+            table[h] = int32_t(cand.size()) + 1;
+            cand.push_back({key, re, im, bit, 1});
+            break;
+          }
+          if (cand[i].key == key && cand[i].re == re && cand[i].im == im) {
+            cand[i].mask |= bit;
+            cand[i].count += 1;
+            break;
+          }
+        }
+      });
+    }
+    const int need = int(std::min<int64_t>(kSharedMinRows, r1 - r0));
+    keep.assign(cand.size(), 0);
+    int ns = 0;
+    for (size_t i = 0; i < cand.size(); ++i)
+      if (cand[i].count >= need) {
+        keep[i] = 1;
+        ++ns;
+      }
+    return ns;
+  }
+
+  bool shared(int64_t r, int32_t col, int term, const double* v) const {
+    const int i = find(make_key(r, col, term), bits(v[0]), bits(v[1]));
+    return i >= 0 && keep[i];
   }
 };
 
@@ -510,6 +524,7 @@ bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
   try {
     S->sptr.assign(nsl + 1, 0);
     S->swid.assign(nsl, 0);
+    S->rlen = rowlen;
     if (uniform) {
       S->nuni.assign(nsl, 0);
       S->uptr.assign(nsl + 1, 0);
@@ -524,19 +539,26 @@ bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
     for (auto& th : pool) th.join();
   };
   if (uniform) {
+    // shared entries per slice, and each row's count of the rest
     run_threads([&](int64_t s0, int64_t s1) {
-      SliceUniform U;
-      for (int64_t sl = s0; sl < s1; ++sl)
-        S->nuni[sl] = U.run(mats, nterms, sl * 64, std::min<int64_t>(n, sl * 64 + 64));
+      SliceShared U;
+      for (int64_t sl = s0; sl < s1; ++sl) {
+        const int64_t r0 = sl * 64, r1 = std::min<int64_t>(n, sl * 64 + 64);
+        S->nuni[sl] = U.run(mats, nterms, r0, r1, rowlen);
+        for (size_t i = 0; i < U.cand.size(); ++i) {
+          if (!U.keep[i]) continue;
+          for (int64_t r = r0; r < r1; ++r)
+            if ((U.cand[i].mask >> (r - r0)) & 1u) S->rlen[r] -= 1;
+        }
+      }
     });
   }
   for (int64_t sl = 0; sl < nsl; ++sl) {
     int w = 0;
-    for (int64_t r = sl * 64; r < std::min<int64_t>(n, sl * 64 + 64); ++r) w = std::max(w, rowlen[r]);
-    const int nu = uniform ? S->nuni[sl] : 0;
-    S->swid[sl] = w - nu;
-    S->sptr[sl + 1] = S->sptr[sl] + 64 * int64_t(w - nu);
-    if (uniform) S->uptr[sl + 1] = S->uptr[sl] + nu;
+    for (int64_t r = sl * 64; r < std::min<int64_t>(n, sl * 64 + 64); ++r) w = std::max(w, S->rlen[r]);
+    S->swid[sl] = w;
+    S->sptr[sl + 1] = S->sptr[sl] + 64 * int64_t(w);
+    if (uniform) S->uptr[sl + 1] = S->uptr[sl] + S->nuni[sl];
   }
   const int64_t slots = S->sptr[nsl];
   const int64_t uslots = uniform ? S->uptr[nsl] : 0;
@@ -545,22 +567,25 @@ bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
     S->sval.assign(2 * slots, 0.0);
     S->ucol.assign(uslots, 0u);
     S->uval.assign(2 * uslots, 0.0);
+    S->umask.assign(uslots, 0ull);
   } catch (const std::bad_alloc&) {
     return false;
   }
   run_threads([&](int64_t s0, int64_t s1) {
-    SliceUniform U;
+    SliceShared U;
     for (int64_t sl = s0; sl < s1; ++sl) {
       const int64_t r0 = sl * 64, r1 = std::min<int64_t>(n, sl * 64 + 64);
       const bool uni = uniform && S->nuni[sl] > 0;
       if (uni) {
-        U.run(mats, nterms, r0, r1);
+        U.run(mats, nterms, r0, r1, rowlen);
         int64_t u = S->uptr[sl];
-        for (size_t i = 0; i < U.key.size(); ++i) {
+        for (size_t i = 0; i < U.cand.size(); ++i) {
           if (!U.keep[i]) continue;
-          S->ucol[u] = U.key[i];
-          S->uval[2 * u] = U.val[2 * i];
-          S->uval[2 * u + 1] = U.val[2 * i + 1];
+          const SliceShared::Cand& cd = U.cand[i];
+          S->ucol[u] = cd.key;
+          std::memcpy(&S->uval[2 * u], &cd.re, sizeof(double));
+          std::memcpy(&S->uval[2 * u + 1], &cd.im, sizeof(double));
+          S->umask[u] = cd.mask;
           ++u;
         }
       }
@@ -568,7 +593,7 @@ bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
         const int64_t lane = r - r0;
         int64_t k = 0;
         for_sell_row(mats, nterms, r, [&](int term, int32_t col, const double* v) {
-          if (uni && U.kept(r, col, term)) return;
+          if (uni && U.shared(r, col, term, v)) return;
           const int64_t pos = S->sptr[sl] + 64 * k + lane;
           S->scol[pos] = uint32_t(col) | (uint32_t(term) << cfet::kTermShift);
           S->sval[2 * pos] = v[0];
@@ -745,15 +770,13 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     if (e == hipSuccess)
       e = hipMemcpy(c->sell.slice_width, S.swid.data(), nsl * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-      e = hipMemcpy(c->sell.rowlen, rowlen.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+      e = hipMemcpy(c->sell.rowlen, S.rlen.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && slots)
       e = hipMemcpy(c->sell.colt, S.scol.data(), slots * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && slots)
       e = hipMemcpy(c->sell.val, S.sval.data(), slots * sizeof(double2), hipMemcpyHostToDevice);
-    int64_t stored = nnz;  // per-row entries actually present (padding excluded)
-    if (uniform)
-      for (int64_t sl = 0; sl < nsl; ++sl)
-        stored -= int64_t(S.nuni[sl]) * (std::min<int64_t>(n, sl * 64 + 64) - sl * 64);
+    int64_t stored = 0;  // per-row entries actually present (padding excluded)
+    for (int64_t r = 0; r < n; ++r) stored += S.rlen[r];
     c->sell_bytes = 20 * stored + 4 * n + 12 * nsl;
     if (uniform) {
       const int64_t us = S.uptr[nsl];
@@ -762,6 +785,7 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       if (e == hipSuccess) e = hipMalloc(&c->sell.uptr, (nsl + 1) * sizeof(int64_t));
       if (e == hipSuccess) e = hipMalloc(&c->sell.ucolt, std::max<int64_t>(us, 1) * sizeof(uint32_t));
       if (e == hipSuccess) e = hipMalloc(&c->sell.uval, std::max<int64_t>(us, 1) * sizeof(double2));
+      if (e == hipSuccess) e = hipMalloc(&c->sell.umask, std::max<int64_t>(us, 1) * sizeof(uint64_t));
       if (e == hipSuccess)
         e = hipMemcpy(c->sell.nuni, S.nuni.data(), nsl * sizeof(int32_t), hipMemcpyHostToDevice);
       if (e == hipSuccess)
@@ -770,7 +794,9 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
         e = hipMemcpy(c->sell.ucolt, S.ucol.data(), us * sizeof(uint32_t), hipMemcpyHostToDevice);
       if (e == hipSuccess && us)
         e = hipMemcpy(c->sell.uval, S.uval.data(), us * sizeof(double2), hipMemcpyHostToDevice);
-      c->sell_bytes += 20 * us + 12 * nsl;
+      if (e == hipSuccess && us)
+        e = hipMemcpy(c->sell.umask, S.umask.data(), us * sizeof(uint64_t), hipMemcpyHostToDevice);
+      c->sell_bytes += 28 * us + 12 * nsl;
     }
     c->use_sell = true;
   }

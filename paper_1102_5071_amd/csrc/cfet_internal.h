@@ -82,18 +82,19 @@ struct DevSELL {
   int64_t n = 0;
   int64_t* slice_ptr = nullptr;  // first slot of each slice
   int32_t* slice_width = nullptr;
-  int32_t* rowlen = nullptr;     // entries of each row
+  int32_t* rowlen = nullptr;     // per-row entries of each row (slots in use)
   uint32_t* colt = nullptr;      // column | term << kTermShift (padding: 0)
   double2* val = nullptr;        // padding: 0
   int64_t slots = 0;
-  // Optional uniform part (null nuni: none).  nuni[s] entries that every row
-  // of slice s holds with the same column offset (column = row XOR offset),
-  // term and value are stored once, at uptr[s]; rowlen counts them too, and
-  // slice_width / slice_ptr cover only the remaining per-row entries.
+  // Optional shared part (null nuni: none).  nuni[s] entries of slice s, each
+  // a column offset (column = row XOR offset), term and value that the rows
+  // of umask (bit l: row 64 s + l) hold, are stored once at uptr[s]; rowlen
+  // and the slots above count only the remaining per-row entries.
   int32_t* nuni = nullptr;
   int64_t* uptr = nullptr;
   uint32_t* ucolt = nullptr;     // offset | term << kTermShift
   double2* uval = nullptr;
+  uint64_t* umask = nullptr;
   int64_t uslots = 0;
 };
 

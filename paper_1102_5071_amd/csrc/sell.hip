@@ -10,10 +10,11 @@
 // every row) entry k of 64 consecutive rows then gathers 64 consecutive x
 // values.  Matrix streams are read non-temporally so they do not evict x from
 // the caches; padded slots are skipped (row lengths are stored per row).
-// Optionally the entries that every row of a slice holds with the same column
+// Optionally the entries that many rows of a slice hold with the same column
 // offset (column = row XOR offset), term and value, such as a site term's
-// flip with a uniform coupling, are stored once per slice ahead of the
-// per-row slots, so their values and columns are not streamed per row.
+// flip with a uniform coupling, are stored once per slice with a 64-bit mask
+// of the rows holding them, ahead of the per-row slots, so their values and
+// columns are not streamed per row.
 #include <hip/hip_runtime.h>
 
 #include "cfet_internal.h"
@@ -23,7 +24,11 @@ namespace cfet {
 namespace {
 
 constexpr int kSellBlock = 256;  // 4 slices per block
-constexpr int kSellMaxBlocks = 4096;
+// The row kernels are held to 80 VGPRs (6 wavefronts per SIMD): the gathers of
+// x are latency-bound and more resident wavefronts keep more of them in
+// flight (8 per SIMD spills and runs slower).
+#define CFET_SELL_OCCUPANCY __attribute__((amdgpu_waves_per_eu(6, 6)))
+constexpr int kSellMaxBlocks = 3072;
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
@@ -80,35 +85,42 @@ __device__ __forceinline__ double2 sell_row(const DevSELL& S, int64_t slice_in, 
   const bool valid = row < S.n;
   int len = valid ? (int)S.rowlen[row] : 0;
   double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
-  // uniform prefix: one (offset, term, value) per slot for the whole slice,
-  // column = row ^ offset; every row of the slice holds these entries
+  // shared entries: one (offset, term, value) for the rows in its mask,
+  // column = row ^ offset; the other rows gather x[row] and drop the product
   const int nu = S.nuni ? S.nuni[slice] : 0;
   if (nu > 0) {
     const int64_t ub = S.uptr[slice];
     const uint32_t* __restrict__ uc = S.ucolt + ub;
     const dvec2* __restrict__ uv = reinterpret_cast<const dvec2*>(S.uval) + ub;
+    const uint64_t* __restrict__ um = S.umask + ub;
+    const int64_t xr = valid ? row : 0;
     int k = 0;
     for (; k + 4 <= nu; k += 4) {
       uint32_t ct[4];
       dvec2 v[4];
+      bool on[4];
       double2 xv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         ct[u] = uc[k + u];
         v[u] = uv[k + u];
+        on[u] = (um[k + u] >> lane) & 1ull;
       }
-      // rows past n (last slice only) gather x[0] and are never stored
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xv[u] = x[valid ? row ^ (int64_t)(ct[u] & kColMask) : 0];
+      for (int u = 0; u < 4; ++u) xv[u] = x[on[u] ? row ^ (int64_t)(ct[u] & kColMask) : xr];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) sell_acc<NT>(ct[u], v[u], xv[u], wl, a0r, a0i, a1r, a1i);
+      for (int u = 0; u < 4; ++u) {
+        if (!on[u]) v[u] = dvec2{0.0, 0.0};
+        sell_acc<NT>(ct[u], v[u], xv[u], wl, a0r, a0i, a1r, a1i);
+      }
     }
     for (; k < nu; ++k) {
       const uint32_t ct = uc[k];
-      const double2 xv = x[valid ? row ^ (int64_t)(ct & kColMask) : 0];
-      sell_acc<NT>(ct, uv[k], xv, wl, a0r, a0i, a1r, a1i);
+      const bool on = (um[k] >> lane) & 1ull;
+      const double2 xv = x[on ? row ^ (int64_t)(ct & kColMask) : xr];
+      const dvec2 v = on ? uv[k] : dvec2{0.0, 0.0};
+      sell_acc<NT>(ct, v, xv, wl, a0r, a0i, a1r, a1i);
     }
-    len = valid ? len - nu : 0;  // entries of this row in the per-row slots
   }
   const uint32_t* __restrict__ cp = S.colt + base + lane;
   const dvec2* __restrict__ vp = reinterpret_cast<const dvec2*>(S.val) + base + lane;
@@ -168,7 +180,7 @@ __device__ __forceinline__ SliceRange slice_range(int64_t nslices) {
 }
 
 template <int NT>
-__global__ __launch_bounds__(kSellBlock) void k_sell_apply(DevSELL S, TermWeights tw,
+__global__ __launch_bounds__(kSellBlock) CFET_SELL_OCCUPANCY void k_sell_apply(DevSELL S, TermWeights tw,
                                                            const double2* __restrict__ x,
                                                            double2* __restrict__ y) {
   __shared__ double wl[kMaxTerms + 1];
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(kSellBlock) void k_sell_apply(DevSELL S, TermWeight
 // the pending norm reduction, applies the early-stop rule, y = H_w v_j and
 // partials of Re<v_j, y>.
 template <int NT>
-__global__ __launch_bounds__(kSellBlock) void k_sell_lz_spmv(
+__global__ __launch_bounds__(kSellBlock) CFET_SELL_OCCUPANCY void k_sell_lz_spmv(
     DevSELL S, TermWeights tw, const double2* __restrict__ x, double2* __restrict__ y,
     const double* __restrict__ part_in, int np_in, double* __restrict__ part_out, LzScalars* L,
     int j) {
