@@ -132,6 +132,14 @@ typedef struct {
  * of summation; detection runs on the host at cfet_create.  Implies
  * CFET_LAYOUT_SELL. */
 #define CFET_LAYOUT_SELL_UNIFORM 0x200u
+/* Above 4096 rows, and when the operator is stored as CSR only, cfet_create
+ * may give the CSR paths a row order of their own (reverse Cuthill-McKee)
+ * when that leaves at least a quarter fewer entries whose column lies in
+ * another row block of the cooperative kernel; cfet_propagate, cfet_apply and
+ * cfet_gradient then permute the caller's vectors in and out on the stream
+ * (results equal up to the order of summation).  cfet_stats_t.reordered tells.
+ * This flag keeps the caller's order. */
+#define CFET_NO_REORDER 0x400u
 
 typedef struct cfet_ctx cfet_ctx;
 
@@ -154,7 +162,8 @@ typedef struct {
                                 recombinations (microseconds, cumulative) */
   int32_t layout;            /* operator storage of the multi-kernel path: 0 merged CSR,
                                 1 SELL-64, 2 SELL-64 with shared parts */
-  int32_t reserved;
+  int32_t reordered;         /* 1: the CSR paths run on their own row order (see
+                                CFET_NO_REORDER) */
   int64_t matrix_bytes;      /* stored operator bytes one application of that layout
                                 reads (values, columns, masks, row and slice data;
                                 padding excluded) */

@@ -26,6 +26,7 @@ VALIDATE_HERMITIAN = 0x1
 PATH_FLAGS = {None: 0, "auto": 0, "multi": 0x10, "single": 0x20, "coop": 0x40,
               "sell": 0x10 | 0x100, "sell_uniform": 0x10 | 0x200}
 LAYOUT_FLAGS = {None: 0, "auto": 0, "sell": 0x100, "sell_uniform": 0x200}
+NO_REORDER = 0x400
 PATH_NAMES = {0: "none", 1: "multi", 2: "single", 3: "coop"}
 MAX_KRYLOV = 64
 
@@ -52,7 +53,7 @@ class _Stats(ctypes.Structure):
                 ("matvecs", c_int64), ("min_m_eff", c_int32), ("breakdowns", c_int32),
                 ("path", c_int32), ("status", c_int32), ("last_norm", c_double),
                 ("timed_launches", c_int64), ("timed_ms", c_double),
-                ("segment_us", c_double * 4), ("layout", c_int32), ("reserved", c_int32),
+                ("segment_us", c_double * 4), ("layout", c_int32), ("reordered", c_int32),
                 ("matrix_bytes", c_int64)]
 
 
@@ -193,7 +194,7 @@ class Propagator:
     """Owns a cfet context for H(t) = H0 + sum_k f_k(t) Hk[k]."""
 
     def __init__(self, H0, Hk, drives, validate_hermitian: bool = False, path=None,
-                 layout=None):
+                 layout=None, reorder: bool = True):
         lib = load()
         keep = []
         self.nterms = len(Hk)
@@ -204,7 +205,7 @@ class Propagator:
         dv = (_Drive * self.nterms)(*[_drive_struct(d, keep) for d in drives])
         ctx = c_void_p()
         flags = ((VALIDATE_HERMITIAN if validate_hermitian else 0) | PATH_FLAGS[path]
-                 | LAYOUT_FLAGS[layout])
+                 | LAYOUT_FLAGS[layout] | (0 if reorder else NO_REORDER))
         code = lib.cfet_create(ctypes.byref(h0), self.nterms, hk, dv, flags, ctypes.byref(ctx))
         if code != 0:
             raise CfetError(code, lib.cfet_last_error(None).decode(errors="replace"))

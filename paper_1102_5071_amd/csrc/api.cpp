@@ -29,6 +29,13 @@ struct cfet_ctx {
   cfet::DevSELL sell;
   bool use_sell = false;
   int64_t sell_bytes = 0;   // stored SELL data one application reads
+  // row order of the CSR paths (null: the caller's): row i of the stored
+  // operator is the caller's row perm[i], caller row j is row iperm[j];
+  // pv, pv2 hold vectors in that order
+  int32_t* perm = nullptr;
+  int32_t* iperm = nullptr;
+  double2* pv = nullptr;
+  double2* pv2 = nullptr;
   cfet::LaunchPlan plan{};
   std::vector<DriveSpec> drives;
   // Krylov workspace (grown on demand)
@@ -76,6 +83,12 @@ thread_local std::string g_err;
 // automatic path choice by dimension
 constexpr int64_t kAutoSingleMaxN = 4096;
 constexpr int64_t kAutoCoopMaxN = int64_t(1) << 22;
+// Grid of the cooperative kernel: one block per CU, but at least ~128 rows per
+// block; each block owns ceil(n / blocks) consecutive rows.
+int64_t coop_grid_blocks(int64_t n, int cus) {
+  return std::max<int64_t>(1, std::min<int64_t>(cus, (n + 127) / 128));
+}
+
 // device bytes the gradient may spend on keeping the recomputed projections
 constexpr size_t kGradStoreMax = size_t(16) << 30;
 static_assert(sizeof(cfet_stats_t) == 120 && offsetof(cfet_stats_t, matrix_bytes) == 112,
@@ -151,6 +164,10 @@ void free_ctx(cfet_ctx* c) {
   if (c->A.rowptr) (void)hipFree(c->A.rowptr);
   if (c->A.colt) (void)hipFree(c->A.colt);
   if (c->A.val) (void)hipFree(c->A.val);
+  if (c->perm) (void)hipFree(c->perm);
+  if (c->iperm) (void)hipFree(c->iperm);
+  if (c->pv) (void)hipFree(c->pv);
+  if (c->pv2) (void)hipFree(c->pv2);
   if (c->sell.slice_ptr) (void)hipFree(c->sell.slice_ptr);
   if (c->sell.slice_width) (void)hipFree(c->sell.slice_width);
   if (c->sell.rowlen) (void)hipFree(c->sell.rowlen);
@@ -701,6 +718,35 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
   c->A.n = n;
   c->A.nnz = nnz;
   const unsigned nth_all = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  // Row order of the CSR paths: reverse Cuthill-McKee when it leaves at least
+  // a quarter fewer entries whose column lies in another block of the
+  // cooperative kernel (those are the values a block gathers from other
+  // blocks each Lanczos step).  Only above the single-workgroup size, and not
+  // when the multi-kernel path runs on SELL.
+  std::vector<int32_t> perm, iperm;
+  if (need_csr && !use_sell && n > kAutoSingleMaxN && !(flags & CFET_NO_REORDER)) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) ==
+            hipSuccess && cus > 0) {
+      const int64_t nbw = coop_grid_blocks(n, cus);
+      const int64_t per = (n + nbw - 1) / nbw;
+      try {
+        std::vector<int32_t> ord = cfet::rcm_order(mats, n);
+        std::vector<int32_t> inv(n);
+        for (int64_t i = 0; i < n; ++i) inv[ord[i]] = int32_t(i);
+        const int64_t nat = cfet::cross_block_entries(mats, n, per, nullptr);
+        const int64_t rcm = cfet::cross_block_entries(mats, n, per, inv.data());
+        if (4 * rcm <= 3 * nat) {
+          perm.swap(ord);
+          iperm.swap(inv);
+        }
+      } catch (const std::bad_alloc&) {
+        perm.clear();  // keep the caller's order
+        iperm.clear();
+      }
+    }
+  }
+  const bool reorder = !perm.empty();
   if (need_csr) {
     std::vector<int64_t> rp;
     std::vector<uint32_t> colt;
@@ -714,19 +760,23 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       free_ctx(c);
       return rc;
     }
+    // stored row i is the caller's row perm[i] (i itself without reordering),
+    // columns relabelled by iperm; entries keep the caller's order
     rp[0] = 0;
-    for (int64_t r = 0; r < n; ++r) rp[r + 1] = rp[r] + rowlen[r];
+    for (int64_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + rowlen[reorder ? perm[i] : i];
     const unsigned nth = (n < 65536) ? 1u : nth_all;
     std::vector<std::thread> pool;
     for (unsigned t = 0; t < nth; ++t) {
       pool.emplace_back([&, t]() {
-        const int64_t r0 = n * t / nth, r1 = n * (t + 1) / nth;
-        for (int64_t r = r0; r < r1; ++r) {
-          int64_t pos = rp[r];
+        const int64_t i0 = n * t / nth, i1 = n * (t + 1) / nth;
+        for (int64_t i = i0; i < i1; ++i) {
+          const int64_t r = reorder ? perm[i] : i;
+          int64_t pos = rp[i];
           for (int k = 0; k <= nterms; ++k) {
             const HostCSR& h = mats[k];
             for (int64_t q = h.rp[r]; q < h.rp[r + 1]; ++q, ++pos) {
-              colt[pos] = uint32_t(h.col[q]) | (uint32_t(k) << cfet::kTermShift);
+              const uint32_t col = uint32_t(reorder ? iperm[h.col[q]] : h.col[q]);
+              colt[pos] = col | (uint32_t(k) << cfet::kTermShift);
               val[2 * pos] = h.val[2 * q];
               val[2 * pos + 1] = h.val[2 * q + 1];
             }
@@ -744,6 +794,16 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       e = hipMemcpy(c->A.colt, colt.data(), nnz * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && nnz)
       e = hipMemcpy(c->A.val, val.data(), nnz * sizeof(double2), hipMemcpyHostToDevice);
+    if (e == hipSuccess && reorder) {
+      e = hipMalloc(&c->perm, n * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc(&c->iperm, n * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc(&c->pv, n * sizeof(double2));
+      if (e == hipSuccess) e = hipMalloc(&c->pv2, n * sizeof(double2));
+      if (e == hipSuccess)
+        e = hipMemcpy(c->perm, perm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(c->iperm, iperm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+    }
   }
   if (e == hipSuccess && use_sell) {
     const int64_t nsl = (n + 63) / 64;
@@ -822,8 +882,7 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
   }
   c->preset_single = need_csr ? cfet::persistent_choose_preset(c->max_row, n, true) : -1;
   if (e == hipSuccess && c->num_cus > 0 && need_csr) {
-    // cooperative grid: one block per CU, but at least ~128 rows per block
-    const int64_t nbw = std::max<int64_t>(1, std::min<int64_t>(c->num_cus, (n + 127) / 128));
+    const int64_t nbw = coop_grid_blocks(n, c->num_cus);
     const int64_t rows = (n + nbw - 1) / nbw;
     c->preset_coop = cfet::persistent_choose_preset(c->max_row, rows, false);
     if (c->preset_coop >= 0) {
@@ -903,21 +962,34 @@ int cfet_apply(cfet_ctx* c, const void* x_dev, void* y_dev, double a, const doub
   tw.w[0] = a;
   for (int k = 0; k < c->nterms; ++k) tw.w[k + 1] = b[k];
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const hipError_t e =
-      c->use_sell ? cfet::launch_sell_apply(c->sell, c->nterms, tw,
-                                            static_cast<const double2*>(x_dev),
-                                            static_cast<double2*>(y_dev), st)
-                  : cfet::launch_apply(c->A, c->nterms, c->plan, tw,
-                                       static_cast<const double2*>(x_dev),
-                                       static_cast<double2*>(y_dev), st);
+  hipError_t e;
+  if (c->use_sell) {
+    e = cfet::launch_sell_apply(c->sell, c->nterms, tw, static_cast<const double2*>(x_dev),
+                                static_cast<double2*>(y_dev), st);
+  } else if (c->perm) {  // the stored row order: permute x in and y out
+    e = cfet::launch_permute(c->pv, static_cast<const double2*>(x_dev), c->perm, c->n, st);
+    if (e == hipSuccess) e = cfet::launch_apply(c->A, c->nterms, c->plan, tw, c->pv, c->pv2, st);
+    if (e == hipSuccess)
+      e = cfet::launch_permute(static_cast<double2*>(y_dev), c->pv2, c->iperm, c->n, st);
+  } else {
+    e = cfet::launch_apply(c->A, c->nterms, c->plan, tw, static_cast<const double2*>(x_dev),
+                           static_cast<double2*>(y_dev), st);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "cfet_apply launch");
   c->last_stream = st;
   c->have_work = true;
   return CFET_OK;
 }
 
-int cfet_propagate(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
-                   int32_t scheme, int32_t krylov_m, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// cfet_propagate on psi_dev in the stored row order (user_order false: the
+// gradient's own buffers) or in the caller's order (permuted in and out when
+// the CSR paths run on a row order of their own).
+int propagate_impl(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
+                   int32_t scheme, int32_t krylov_m, void* hip_stream, bool user_order) {
   if (!c) return fail(nullptr, CFET_EINVAL, "null context");
   if (!psi_dev) return fail(c, CFET_EINVAL, "null psi");
   if (nsteps < 0) return fail(c, CFET_EINVAL, "nsteps < 0");
@@ -941,7 +1013,24 @@ int cfet_propagate(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nst
   if (rc != CFET_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int path = choose_path(c);
-  if (path != 1) return propagate_persistent(c, psi_dev, t0, dt, nsteps, sc, m, path, st);
+  void* const user_psi = psi_dev;
+  const bool permute = user_order && c->perm;
+  if (permute) {
+    const hipError_t ep = cfet::launch_permute(c->pv, static_cast<const double2*>(user_psi),
+                                               c->perm, c->n, st);
+    if (ep != hipSuccess) return hip_fail(c, ep, "permute psi in");
+    psi_dev = c->pv;
+  }
+  auto permute_out = [&]() -> int {
+    if (!permute) return CFET_OK;
+    const hipError_t ep =
+        cfet::launch_permute(static_cast<double2*>(user_psi), c->pv, c->iperm, c->n, st);
+    return ep == hipSuccess ? CFET_OK : hip_fail(c, ep, "permute psi out");
+  };
+  if (path != 1) {
+    const int rp = propagate_persistent(c, psi_dev, t0, dt, nsteps, sc, m, path, st);
+    return rp == CFET_OK ? permute_out() : rp;
+  }
   c->h_W[0] = static_cast<double2*>(psi_dev);
   hipError_t e;
   cfet::ExpWork wk;
@@ -982,7 +1071,16 @@ int cfet_propagate(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nst
   c->last_stream = st;
   c->have_work = true;
   c->last_path = 1;
-  return CFET_OK;
+  return permute_out();
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfet_propagate(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
+                   int32_t scheme, int32_t krylov_m, void* hip_stream) {
+  return propagate_impl(c, psi_dev, t0, dt, nsteps, scheme, krylov_m, hip_stream, true);
 }
 
 int cfet_profile(cfet_ctx* c, int32_t enable, int32_t max_launches) {
@@ -1103,17 +1201,20 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
   if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: workspace");
   const size_t vb = nn * sizeof(double2);
   // ---- forward pass, keeping psi at the start of every segment
-  e = hipMemcpyAsync(psi, psi0_dev, vb, hipMemcpyDeviceToDevice, st);
+  // psi and lambda live in the stored row order
+  e = c->perm ? cfet::launch_permute(psi, static_cast<const double2*>(psi0_dev), c->perm, n, st)
+              : hipMemcpyAsync(psi, psi0_dev, vb, hipMemcpyDeviceToDevice, st);
   for (int64_t sg = 0; sg < nseg && e == hipSuccess; ++sg) {
     e = hipMemcpyAsync(ckpt + size_t(sg) * nn, psi, vb, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) break;
     const int64_t s0 = sg * seg, len = std::min(seg, N - s0);
-    rc = cfet_propagate(c, psi, t0 + double(s0) * dt, dt, len, scheme, m, st);
+    rc = propagate_impl(c, psi, t0 + double(s0) * dt, dt, len, scheme, m, st, false);
     if (rc != CFET_OK) return rc;
   }
-  if (e == hipSuccess) e = cfet::launch_zdot(static_cast<const double2*>(target_dev), psi, n,
-                                             zpart, zval, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(lam, target_dev, vb, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = c->perm ? cfet::launch_permute(lam, static_cast<const double2*>(target_dev), c->perm, n, st)
+                : hipMemcpyAsync(lam, target_dev, vb, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = cfet::launch_zdot(lam, psi, n, zpart, zval, st);
   if (e == hipSuccess) e = cfet::launch_zero2(dz, K, st);
   if (e != hipSuccess) return hip_fail(c, e, "cfet_gradient: forward pass");
 
@@ -1335,6 +1436,7 @@ int cfet_stats(cfet_ctx* c, cfet_stats_t* s) {
   s->breakdowns = d.breakdowns;
   s->path = c->last_path;
   s->layout = !c->use_sell ? 0 : (c->sell.nuni ? 2 : 1);
+  s->reordered = c->perm ? 1 : 0;
   s->matrix_bytes = c->use_sell ? c->sell_bytes : 20 * c->A.nnz + 8 * (c->n + 1);
   s->status = d.status;
   s->last_norm = std::sqrt(d.last_norm2);

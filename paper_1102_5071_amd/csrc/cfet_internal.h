@@ -136,6 +136,9 @@ struct ExpWork {
   const TermWeights* twp = nullptr;  // if set, the SpMV reads the weights here (device)
 };
 
+// out[i] = in[idx[i]] for i < n (idx a permutation of 0..n-1; out and in distinct)
+hipError_t launch_permute(double2* out, const double2* in, const int32_t* idx, int64_t n,
+                          hipStream_t st);
 hipError_t launch_norm_start(const double2* psi, int64_t n, const LaunchPlan& plan, double* part,
                              hipStream_t st);
 hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& plan,

@@ -19,6 +19,8 @@
 // array, and every consumer block re-reduces the partials in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 
 #include "cfet_internal.h"
@@ -61,6 +63,15 @@ __device__ double sum_partials(const double* __restrict__ part, int np, double* 
 }
 
 __device__ __forceinline__ bool block0_thread0() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// out[i] = in[idx[i]] (a row permutation of a vector; out and in distinct)
+__global__ __launch_bounds__(kBlock) void k_permute(double2* __restrict__ out,
+                                                    const double2* __restrict__ in,
+                                                    const int32_t* __restrict__ idx, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = in[idx[i]];
+}
 
 __global__ __launch_bounds__(kBlock) void k_norm_start(const double2* __restrict__ psi, int64_t n,
                                                        double* __restrict__ part) {
@@ -408,6 +419,14 @@ hipError_t launch_apply(const DevCSR& A, int nterms, const LaunchPlan& plan, con
                         const double2* x, double2* y, hipStream_t st) {
   if (nterms == 1) return dispatch_apply<1>(plan.G, A, plan.nb_spmv, tw, x, y, st);
   return dispatch_apply<0>(plan.G, A, plan.nb_spmv, tw, x, y, st);
+}
+
+hipError_t launch_permute(double2* out, const double2* in, const int32_t* idx, int64_t n,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int nb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+  hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, st, out, in, idx, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_norm_start(const double2* psi, int64_t n, const LaunchPlan& plan, double* part,

@@ -190,4 +190,93 @@ int copy_drive(std::string& err, const cfet_drive& d, DriveSpec* out) {
   return CFET_OK;
 }
 
+std::vector<int32_t> rcm_order(const std::vector<HostCSR>& mats, int64_t n) {
+  std::vector<int32_t> deg(n, 0);
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t d = 0;
+    for (const HostCSR& h : mats) d += h.rp[r + 1] - h.rp[r];
+    deg[r] = int32_t(std::min<int64_t>(d, INT32_MAX));
+  }
+  auto for_nb = [&](int32_t u, auto f) {
+    for (const HostCSR& h : mats)
+      for (int64_t q = h.rp[u]; q < h.rp[u + 1]; ++q) f(h.col[q]);
+  };
+  std::vector<char> done(n, 0);           // placed in the order
+  std::vector<int32_t> lvl(n, -1), q;     // level scratch of one search
+  // breadth-first search over rows not yet placed; returns the last level's
+  // row of smallest degree and sets ecc to its level
+  auto bfs = [&](int32_t s, int& ecc) -> int32_t {
+    q.clear();
+    q.push_back(s);
+    lvl[s] = 0;
+    for (size_t h = 0; h < q.size(); ++h) {
+      const int32_t u = q[h];
+      for_nb(u, [&](int32_t v) {
+        if (!done[v] && lvl[v] < 0) {
+          lvl[v] = lvl[u] + 1;
+          q.push_back(v);
+        }
+      });
+    }
+    ecc = lvl[q.back()];
+    int32_t best = q.back();
+    for (size_t h = q.size(); h-- > 0 && lvl[q[h]] == ecc;)
+      if (deg[q[h]] < deg[best]) best = q[h];
+    for (int32_t u : q) lvl[u] = -1;
+    return best;
+  };
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<int32_t> nbrs;
+  for (int64_t s0 = 0; s0 < n; ++s0) {
+    if (done[s0]) continue;
+    // pseudo-peripheral root: repeat the search from the far end while the
+    // eccentricity grows (at most a few rounds)
+    int32_t root = int32_t(s0);
+    int ecc = 0;
+    int32_t far = bfs(root, ecc);
+    for (int it = 0; it < 4; ++it) {
+      int e2 = 0;
+      const int32_t far2 = bfs(far, e2);
+      if (e2 <= ecc) break;
+      root = far;
+      ecc = e2;
+      far = far2;
+    }
+    // Cuthill-McKee from the root
+    const size_t first = order.size();
+    order.push_back(root);
+    done[root] = 1;
+    for (size_t h = first; h < order.size(); ++h) {
+      const int32_t u = order[h];
+      nbrs.clear();
+      for_nb(u, [&](int32_t v) {
+        if (!done[v]) {
+          done[v] = 1;
+          nbrs.push_back(v);
+        }
+      });
+      std::stable_sort(nbrs.begin(), nbrs.end(),
+                       [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+      order.insert(order.end(), nbrs.begin(), nbrs.end());
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+int64_t cross_block_entries(const std::vector<HostCSR>& mats, int64_t n, int64_t per,
+                            const int32_t* inv) {
+  int64_t cross = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    const int64_t br = (inv ? inv[r] : r) / per;
+    for (const HostCSR& h : mats)
+      for (int64_t q = h.rp[r]; q < h.rp[r + 1]; ++q) {
+        const int64_t c = h.col[q];
+        cross += ((inv ? inv[c] : c) / per) != br;
+      }
+  }
+  return cross;
+}
+
 }  // namespace cfet

@@ -31,4 +31,17 @@ int validate_csr(std::string& err, const HostCSR& h, const char* name);
 int check_hermitian(std::string& err, const HostCSR& h, const char* name);
 int copy_drive(std::string& err, const cfet_drive& d, DriveSpec* out);
 
+// Reverse Cuthill-McKee order of the union of the matrices' patterns (row
+// adjacency; the operators are Hermitian, so rows and columns carry the same
+// pattern): breadth-first levels from a pseudo-peripheral row of each
+// connected part, neighbours taken by increasing degree, the whole sequence
+// reversed.  Returns order[new] = old.
+std::vector<int32_t> rcm_order(const std::vector<HostCSR>& mats, int64_t n);
+
+// Entries (over all matrices) whose row and column fall in different blocks
+// of `per` consecutive rows, with rows relabelled old -> inv[old] (null: as
+// given).
+int64_t cross_block_entries(const std::vector<HostCSR>& mats, int64_t n, int64_t per,
+                            const int32_t* inv);
+
 }  // namespace cfet

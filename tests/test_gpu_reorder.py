@@ -1,0 +1,104 @@
+"""GPU parity with the CSR paths' own row order (reverse Cuthill-McKee).
+
+An operator whose couplings run far from the diagonal in the caller's order
+(the hydrogen grid: l +- 1 at the same radius is Nr rows away) is stored in a
+banded order and the caller's vectors are permuted in and out.  Bar: the
+oracle's results to the usual tolerances (propagation 1e-10 relative, apply
+1e-14, gradient 1e-10), and the same call on a context that keeps the
+caller's order to rounding (1e-12).  Spin chains keep the caller's order
+(reordering would put more entries across blocks).
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as A
+from oracle import cfet as O
+from paper_1102_5071_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1102_5071_amd.binding")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    B.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.complex128)).to("cuda")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def grid_problem():
+    # 16 partial waves x 400 radial points: 6400 rows (cooperative path);
+    # spectral radius ~3e3, so dt ||H|| stays near 1 and the Krylov spaces
+    # converge (results then depend on rounding only weakly)
+    H0, H1 = I.hydrogen_fd(400, 0.2, 15)
+    rng = np.random.default_rng(4)
+    return H0, [H1], I.random_state(H0.n, rng)
+
+
+@pytest.mark.parametrize("path", [None, "multi", "coop"])
+def test_propagation_in_own_row_order(path):
+    H0, Hk, psi0 = grid_problem()
+    drives = [{"kind": "cos", "A": 0.3, "omega": 0.7, "phi": 0.1}]
+    t0, dt, N, scheme, m = 0.5, 0.0005, 6, "CF4:2", 20
+    out = {}
+    for reorder in (True, False):
+        with B.Propagator(H0, Hk, drives, path=path, reorder=reorder) as P:
+            psi = dev(psi0)
+            P.propagate(psi, t0, dt, N, scheme, m)
+            st = P.stats()
+            out[reorder] = psi.cpu().numpy()
+        assert st["status"] == 0
+        assert st["reordered"] == (1 if reorder else 0)
+    ref = O.propagate(H0, Hk, drives, psi0, t0, dt, N, scheme, m=m)
+    assert rel(out[True], ref) <= 1e-10
+    assert rel(out[True], out[False]) <= 1e-12
+
+
+def test_apply_in_own_row_order():
+    H0, Hk, x = grid_problem()
+    drives = [{"kind": "cos", "A": 1.0, "omega": 1.0}]
+    with B.Propagator(H0, Hk, drives) as P:
+        assert P.stats()["reordered"] == 1
+        y = P.apply(dev(x), -0.4, [1.7]).cpu().numpy()
+    ref = -0.4 * (H0.to_scipy() @ x) + 1.7 * (Hk[0].to_scipy() @ x)
+    assert rel(y, ref) < 1e-14
+
+
+def test_gradient_in_own_row_order():
+    H0, Hk, psi0 = grid_problem()
+    rng = np.random.default_rng(9)
+    target = I.random_state(H0.n, rng)
+    K = 4
+    drives = [{"kind": "pwc", "t_edges": np.linspace(0.0, 0.004, K + 1),
+               "u": rng.uniform(-1, 1, K)}]
+    t0, dt, N, scheme, m = 0.0, 0.0005, 8, "CF4:2", 12
+    res = {}
+    for reorder in (True, False):
+        with B.Propagator(H0, Hk, drives, reorder=reorder) as P:
+            assert P.stats()["reordered"] == (1 if reorder else 0)
+            res[reorder] = P.gradient(dev(psi0), dev(target), t0, dt, N, scheme, m)
+            assert P.stats()["status"] == 0
+    F_ref, g_ref = A.fidelity_gradient(H0, Hk, drives, psi0, target, t0, dt, N, scheme, m)
+    F, g = res[True]
+    assert abs(F - F_ref) <= 1e-12
+    assert rel(np.asarray(g), g_ref) <= 1e-10
+    assert rel(np.asarray(g), np.asarray(res[False][1])) <= 1e-12
+
+
+def test_spin_chain_keeps_caller_order():
+    p = I.config_ising(L=13)
+    with B.Propagator(p.H0, p.Hk, p.drives) as P:
+        assert P.stats()["reordered"] == 0
