@@ -189,7 +189,6 @@ hipError_t launch_zdot(const double2* a, const double2* b, int64_t n, double2* p
                        double2* out, hipStream_t st);
 hipError_t launch_zero2(double2* p, int n, hipStream_t st);
 // Persistent propagation (persistent.hip): one launch for a whole call.
-constexpr int kPersistBlock = 512;  // threads per block of the persistent kernels
 
 struct PersistArgs {
   const int64_t* rowptr;
@@ -227,6 +226,7 @@ hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, i
                              hipStream_t st, bool reset = true);
 hipError_t persistent_max_blocks(int preset, int nterms, int* out);
 int persistent_rows_per_block(int preset, bool single);
+int persistent_block_threads(int preset, bool single);
 int persistent_barrier_words();
 int persistent_choose_preset(int max_row, int64_t min_rows_per_block, bool single);
 

@@ -41,19 +41,26 @@ namespace cfet {
 namespace {
 
 // Register-holding presets (G lanes per row, P rows per lane group, Q
-// entries per lane and row).  A block of kPersistBlock threads holds
-// P * kPersistBlock / G rows; rows longer than G*Q read their tail from memory.
+// entries per lane and row, B threads per block).  A block holds P * B / G
+// rows; rows longer than G*Q read their tail from memory.
 struct Preset {
-  int G, P, Q;
+  int G, P, Q, B;
 };
-// cooperative kernel (gathers prefetched into registers)
-constexpr Preset kCoopPresets[] = {{1, 1, 5}, {1, 1, 8}, {2, 1, 8}, {4, 1, 8}};
+// cooperative kernel (gathers prefetched into registers).  With eight entries
+// per lane a 512-thread block needs more than the 256 registers a wavefront
+// gets at two wavefronts per SIMD and spills to scratch; at 256 threads (one
+// wavefront per SIMD) the overflow goes to accumulation registers instead,
+// so those presets come first and the 512-thread ones serve only larger
+// blocks.  (The single-workgroup kernel is faster with 512 threads in spite
+// of its spills: it needs the wavefronts to spread its rows.)
+constexpr Preset kCoopPresets[] = {{1, 1, 5, 512}, {1, 1, 8, 256}, {2, 1, 8, 256}, {4, 1, 8, 256},
+                                   {1, 1, 8, 512}, {2, 1, 8, 512}, {4, 1, 8, 512}};
 // single-workgroup kernel (working vectors in LDS, n <= kSingleMaxRows)
-constexpr Preset kSinglePresets[] = {{1, 2, 12}, {2, 2, 8}, {4, 2, 8}};
+constexpr Preset kSinglePresets[] = {{1, 2, 12, 512}, {2, 2, 8, 512}, {4, 2, 8, 512}};
 constexpr int kNumCoopPresets = sizeof(kCoopPresets) / sizeof(kCoopPresets[0]);
 constexpr int kNumSinglePresets = sizeof(kSinglePresets) / sizeof(kSinglePresets[0]);
 constexpr int kSingleMaxRows = 1024;
-constexpr int kCoopMaxRows = kPersistBlock;  // rows of one cooperative block (G = 1, P = 1)
+constexpr int kCoopMaxRows = 512;  // rows of one cooperative block, at most (P * B / G)
 
 // One DPP step of the wavefront sum: v + (v moved by the DPP pattern), rows
 // outside row_mask add 0.
@@ -308,9 +315,10 @@ struct LaunchStats {
   }
 };
 
-template <int G, int PMAX, int QMAX, int NT, bool SINGLE>
-__global__ __launch_bounds__(kPersistBlock) void k_propagate(PersistArgs A) {
-  constexpr int BLOCK = kPersistBlock;
+template <int G, int PMAX, int QMAX, int NT, bool SINGLE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
+  static_assert(BLOCK % 64 == 0 && BLOCK <= 512, "block of whole wavefronts, at most 8");
+  static_assert(SINGLE || PMAX * BLOCK / G <= kCoopMaxRows, "rows of a block exceed the ring");
   __shared__ Shared sh;
   // u_k ring (k mod 3) of this block's own rows in LDS, indexed by row - r0:
   // the single workgroup reads every gathered value from here, the cooperative
@@ -765,28 +773,38 @@ __global__ void k_persist_reset(unsigned long long* bar, int* fault) {
   if (threadIdx.x == 0) *fault = 0;
 }
 
-template <int G, int P, int Q, bool SINGLE>
+template <int G, int P, int Q, bool SINGLE, int B>
 const void* pick_nt(int NT) {
-  return NT == 1 ? (const void*)&k_propagate<G, P, Q, 1, SINGLE>
-                 : (const void*)&k_propagate<G, P, Q, 0, SINGLE>;
+  return NT == 1 ? (const void*)&k_propagate<G, P, Q, 1, SINGLE, B>
+                 : (const void*)&k_propagate<G, P, Q, 0, SINGLE, B>;
 }
 
+static_assert(kNumCoopPresets == 7 && kNumSinglePresets == 3,
+              "pick_coop and pick_single list every preset");
+
 const void* pick_coop(int preset, int NT) {
-#define CFET_CP(I) \
-  case I: return pick_nt<kCoopPresets[I].G, kCoopPresets[I].P, kCoopPresets[I].Q, false>(NT);
+#define CFET_CP(I)                                                                        \
+  case I:                                                                                 \
+    return pick_nt<kCoopPresets[I].G, kCoopPresets[I].P, kCoopPresets[I].Q, false,        \
+                   kCoopPresets[I].B>(NT);
   switch (preset) {
     CFET_CP(0)
     CFET_CP(1)
     CFET_CP(2)
     CFET_CP(3)
+    CFET_CP(4)
+    CFET_CP(5)
+    CFET_CP(6)
     default: return nullptr;
   }
 #undef CFET_CP
 }
 
 const void* pick_single(int preset, int NT) {
-#define CFET_SP(I) \
-  case I: return pick_nt<kSinglePresets[I].G, kSinglePresets[I].P, kSinglePresets[I].Q, true>(NT);
+#define CFET_SP(I)                                                                        \
+  case I:                                                                                 \
+    return pick_nt<kSinglePresets[I].G, kSinglePresets[I].P, kSinglePresets[I].Q, true,   \
+                   kSinglePresets[I].B>(NT);
   switch (preset) {
     CFET_SP(0)
     CFET_SP(1)
@@ -798,11 +816,17 @@ const void* pick_single(int preset, int NT) {
 
 }  // namespace
 
+int persistent_block_threads(int preset, bool single) {
+  const Preset* t = single ? kSinglePresets : kCoopPresets;
+  const int np = single ? kNumSinglePresets : kNumCoopPresets;
+  return (preset < 0 || preset >= np) ? 0 : t[preset].B;
+}
+
 int persistent_rows_per_block(int preset, bool single) {
   const Preset* t = single ? kSinglePresets : kCoopPresets;
   const int np = single ? kNumSinglePresets : kNumCoopPresets;
   if (preset < 0 || preset >= np) return 0;
-  const int rows = t[preset].P * (kPersistBlock / t[preset].G);
+  const int rows = t[preset].P * (t[preset].B / t[preset].G);
   return single ? std::min(rows, kSingleMaxRows) : rows;
 }
 
@@ -846,10 +870,11 @@ hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, i
   }
   PersistArgs a = args;
   void* kargs[] = {&a};
+  const int block = persistent_block_threads(preset, single);
   if (single) {
-    e = hipLaunchKernel(fn, dim3(1), dim3(kPersistBlock), kargs, 0, st);
+    e = hipLaunchKernel(fn, dim3(1), dim3(block), kargs, 0, st);
   } else {
-    e = hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kPersistBlock), kargs, 0, st);
+    e = hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(block), kargs, 0, st);
   }
   return e;
 }
@@ -860,7 +885,9 @@ hipError_t persistent_max_blocks(int preset, int nterms, int* out) {
   int dev = 0, cus = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kPersistBlock, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn,
+                                                     persistent_block_threads(preset, false), 0);
   if (e != hipSuccess) return e;
   *out = cus * per;
   return hipSuccess;
