@@ -84,23 +84,6 @@ __device__ __forceinline__ double p_wave_sum(double v) {
   return lane_read(v, 63);
 }
 
-// Block sum; every thread receives the value thread 0 formed.
-__device__ double p_block_sum(double v, double* red) {
-  v = p_wave_sum(v);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
-  __syncthreads();
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < nw; ++i) t += red[i];
-    red[16] = t;
-  }
-  __syncthreads();
-  return red[16];
-}
-
 // Device-scope accesses of cross-block vectors: one 16-byte buffer load or
 // store carrying the device-coherence cache policy, addressed as (base,
 // element index) so the buffer descriptor stays uniform.  The descriptor's
@@ -202,9 +185,14 @@ __device__ bool grid_barrier(unsigned long long* bar, int* fault, unsigned long 
   return *s_ok != 0;
 }
 
+constexpr int kRedB = 16;      // offset of the second sum's per-wavefront values
+constexpr int kRedA = 2 * kRedB;  // the two results
+
 struct Shared {
   double cheb[kChebMaxTerms];
-  double red[18];
+  // block reductions: per-wavefront values of the first sum at red[w], of the
+  // second at red[kRedB + w] (up to 16 wavefronts), results at red[2 kRedB + 0/1]
+  double red[2 * kRedB + 2];
   double alpha[kMaxM];
   double beta[kMaxM];
   double inv[kMaxM];
@@ -235,21 +223,21 @@ __device__ void p_block_sum2(double& a, double& b, double* red) {
   __syncthreads();
   if (l == 0) {
     red[w] = a;
-    red[8 + w] = b;
+    red[kRedB + w] = b;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double ta = 0.0, tb = 0.0;
     for (int i = 0; i < nw; ++i) {
       ta += red[i];
-      tb += red[8 + i];
+      tb += red[kRedB + i];
     }
-    red[16] = ta;
-    red[17] = tb;
+    red[kRedA] = ta;
+    red[kRedA + 1] = tb;
   }
   __syncthreads();
-  a = red[16];
-  b = red[17];
+  a = red[kRedA];
+  b = red[kRedA + 1];
 }
 
 // Global sums of (a, b) over all threads of all blocks.  Returns false on a fault.
@@ -317,7 +305,7 @@ struct LaunchStats {
 
 template <int G, int PMAX, int QMAX, int NT, bool SINGLE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
-  static_assert(BLOCK % 64 == 0 && BLOCK <= 512, "block of whole wavefronts, at most 8");
+  static_assert(BLOCK % 64 == 0 && BLOCK <= 64 * kRedB, "block of whole wavefronts, at most 16");
   static_assert(SINGLE || PMAX * BLOCK / G <= kCoopMaxRows, "rows of a block exceed the ring");
   __shared__ Shared sh;
   // u_k ring (k mod 3) of this block's own rows in LDS, indexed by row - r0:
@@ -465,13 +453,13 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
               sa = p_wave_sum(sa);
               sb = p_wave_sum(sb);
               if (threadIdx.x == 0) {
-                sh.red[16] = sa;
-                sh.red[17] = sb;
+                sh.red[kRedA] = sa;
+                sh.red[kRedA + 1] = sb;
               }
             }
             __syncthreads();
-            S1 = sh.red[16];
-            S2 = sh.red[17];
+            S1 = sh.red[kRedA];
+            S2 = sh.red[kRedA + 1];
           }
           const double nu = sqrt(S2);
           if (k == 1) {
@@ -623,7 +611,7 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
           s_uu = p_wave_sum(s_uu);
           if ((threadIdx.x & 63) == 0) {
             sh.red[threadIdx.x >> 6] = s_uz;
-            sh.red[8 + (threadIdx.x >> 6)] = s_uu;
+            sh.red[kRedB + (threadIdx.x >> 6)] = s_uu;
           }
           __syncthreads();
           double* P = A.part + (size_t)(pc & 1) * 2 * gridDim.x;
@@ -631,7 +619,7 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
             double ta = 0.0, tb = 0.0;
             for (int wv = 0; wv < BLOCK / 64; ++wv) {
               ta += sh.red[wv];
-              tb += sh.red[8 + wv];
+              tb += sh.red[kRedB + wv];
             }
             dstore(P + 2 * blockIdx.x, ta);
             dstore(P + 2 * blockIdx.x + 1, tb);
