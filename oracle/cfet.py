@@ -42,7 +42,7 @@ from .schemes import Scheme, gl_weights, scheme as get_scheme
 
 BREAKDOWN_REL_TOL = 1e-12
 
-__all__ = ["drive_value", "step_weights", "lanczos", "tridiag_expm_e1", "expv",
+__all__ = ["apply_rows", "drive_value", "step_weights", "lanczos", "tridiag_expm_e1", "expv",
            "expv_adaptive", "expv_dense", "propagate", "propagate_batch", "LanczosInfo",
            "BREAKDOWN_REL_TOL"]
 
@@ -260,6 +260,21 @@ def expv_dense(H, psi: np.ndarray, dt: float) -> np.ndarray:
 # --------------------------------------------------------------------------
 # CFET time stepping (Secs. 4, 6.1, 7)
 # --------------------------------------------------------------------------
+def apply_rows(H0, Hk, a: float, b, x: np.ndarray, rows) -> np.ndarray:
+    """Entries ``rows`` of y = (a H0 + sum_k b_k H_k) x, one row at a time from
+    the CSR rows (for spot checks of operators too large to apply whole).
+    The matrices are CSR containers with row_ptr / col / val arrays."""
+    out = np.zeros(len(rows), dtype=np.complex128)
+    mats = [(a, H0)] + [(bk, h) for bk, h in zip(b, Hk)]
+    for i, r in enumerate(rows):
+        acc = 0.0 + 0.0j
+        for w, h in mats:
+            lo, hi = int(h.row_ptr[r]), int(h.row_ptr[r + 1])
+            acc += w * np.dot(h.val[lo:hi], x[h.col[lo:hi]])
+        out[i] = acc
+    return out
+
+
 def _as_matrix(H, dense: bool):
     """Accept a scipy sparse matrix, a dense array, or any object with a
     ``to_scipy()`` method (the CSR container of the input generators)."""

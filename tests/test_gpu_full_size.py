@@ -1,0 +1,98 @@
+"""GPU checks at the benchmark's full sizes, in the launch configurations that
+bench.py times (default paths and layouts).
+
+* Heisenberg chain L = 24 (dim 2^24, 612 M stored entries): too large for
+  the oracle to propagate, so the weighted apply is checked on sampled rows
+  computed one by one by the oracle (oracle.cfet.apply_rows), and the
+  propagation by properties that hold at any size: a step of dt followed by a
+  step of -dt returns the state (the schemes are time-symmetric and the
+  Krylov spaces converge at dt ||H|| ~ 1), and the norm is conserved.
+* The batch of 256 driven chains (L = 12..18): every trajectory is
+  independent, so sampled trajectories are propagated by the oracle one at a
+  time and compared (1e-10 relative, same number of H applications).
+"""
+import numpy as np
+import pytest
+
+from oracle import cfet as O
+from paper_1102_5071_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1102_5071_amd.binding")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    B.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.complex128)).to("cuda")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def test_heisenberg_L24_sampled_rows_reversibility_and_norm():
+    p = I.config_heisenberg(L=24)
+    n = p.dim
+    rng = np.random.default_rng(24)
+    with B.Propagator(p.H0, p.Hk, p.drives) as P:
+        st = P.stats()
+        assert st["layout"] == 2          # SELL-64 with shared parts, the default here
+        x = I.random_state(n, rng)
+        a, b = 0.83, [-1.7]
+        y = P.apply(dev(x), a, b).cpu().numpy()
+        # rows at slice edges, the ends, and a random sample
+        rows = np.unique(np.concatenate([
+            [0, 1, 63, 64, n - 64, n - 1],
+            np.arange(0, n, n // 64) + 63,
+            rng.choice(n, 3000, replace=False)]))
+        ref = O.apply_rows(p.H0, p.Hk, a, b, x, rows)
+        err = np.abs(y[rows] - ref)
+        assert np.all(err <= 1e-13 * (1.0 + np.abs(ref))), float(err.max())
+        del x, y
+        # one step forward and one back, on the benchmark's path and scheme
+        psi = dev(p.psi0)
+        P.propagate(psi, 0.0, p.dt, 1, p.scheme, p.m)
+        mid = torch.linalg.vector_norm(psi).item()
+        P.propagate(psi, p.dt, -p.dt, 1, p.scheme, p.m)
+        st = P.stats()
+        assert st["status"] == 0
+        assert B.PATH_NAMES[st["path"]] == "multi"
+        assert st["matvecs"] == 2 * 5 * p.m
+        back = psi.cpu().numpy()
+    assert abs(mid - 1.0) < 1e-12
+    assert rel(back, p.psi0) < 1e-10
+
+
+def test_batched_256_chains_sampled_trajectories():
+    Bt = I.config_batched()
+    insts = Bt.instances
+    nsteps = 3
+    with B.BatchPropagator(Bt.ops, insts) as P:
+        psi = torch.from_numpy(np.concatenate([i["psi0"] for i in insts])).to("cuda")
+        P.propagate(psi, 0.0, Bt.dt, nsteps, Bt.scheme, Bt.m, Bt.tol)
+        st = P.stats()
+        mv = P.instance_matvecs()
+        out = [v.cpu().numpy() for v in P.split(psi)]
+    assert st["status"] == 0 and st["graph"] == 1 and st["ninst"] == 256
+    dims = np.array([len(i["psi0"]) for i in insts])
+    rng = np.random.default_rng(5)
+    pick = sorted(set([int(np.argmin(dims)), int(np.argmax(dims))]
+                      + list(rng.choice(len(insts), 4, replace=False))))
+    resolved = [{"H0": Bt.ops[insts[j]["h0"]], "Hk": [Bt.ops[k] for k in insts[j]["hk"]],
+                 "drives": insts[j]["drives"], "psi0": insts[j]["psi0"]} for j in pick]
+    stats = []
+    ref = O.propagate_batch(resolved, 0.0, Bt.dt, nsteps, Bt.scheme, Bt.m, Bt.tol, stats=stats)
+    for j, r, s in zip(pick, ref, stats):
+        assert rel(out[j], r) <= 1e-10, (j, rel(out[j], r))
+        assert mv[j] == s["n_matvec"], j

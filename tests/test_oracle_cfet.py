@@ -223,3 +223,24 @@ def test_piecewise_constant_drive_step_aligned():
     Hb = H0.toarray() - 0.9 * Hk[0].toarray()
     ref = sla.expm(-0.5j * Hb) @ (sla.expm(-0.5j * Ha) @ psi0)
     assert np.linalg.norm(out - ref) < 1e-13
+
+
+def test_apply_rows_matches_sparse_product():
+    # spot rows of y = a H0 x + b1 H1 x + b2 H2 x against scipy's whole product,
+    # on a ragged random operator (empty rows included) and a spin chain
+    rng = np.random.default_rng(21)
+    H0 = I.random_hermitian(90, rng, density=0.05)
+    H1 = I.random_hermitian(90, rng, density=0.1)
+    H2 = I.diagonal(rng.standard_normal(90))
+    x = I.random_state(90, rng)
+    a, b = -0.7, [1.3, 0.25]
+    full = a * (H0.to_scipy() @ x) + b[0] * (H1.to_scipy() @ x) + b[1] * (H2.to_scipy() @ x)
+    rows = [0, 5, 44, 89] + list(rng.choice(90, 10, replace=False))
+    got = O.apply_rows(H0, [H1, H2], a, b, x, rows)
+    assert np.allclose(got, full[rows], rtol=1e-14, atol=1e-14)
+    p = I.config_heisenberg(L=8)
+    x = I.random_state(p.dim, rng)
+    full = 0.4 * (p.H0.to_scipy() @ x) - 2.0 * (p.Hk[0].to_scipy() @ x)
+    rows = list(range(0, p.dim, 17))
+    assert np.allclose(O.apply_rows(p.H0, p.Hk, 0.4, [-2.0], x, rows), full[rows],
+                       rtol=1e-14, atol=1e-14)
