@@ -10,6 +10,9 @@ bench.py times (default paths and layouts).
 * The batch of 256 driven chains (L = 12..18): every trajectory is
   independent, so sampled trajectories are propagated by the oracle one at a
   time and compared (1e-10 relative, same number of H applications).
+* The control problem (L = 14, K = 200, 2000 steps): the fidelity equals the
+  plain propagation's, and central differences of the forward map agree with
+  the gradient on sampled pieces.
 """
 import numpy as np
 import pytest
@@ -96,3 +99,35 @@ def test_batched_256_chains_sampled_trajectories():
     for j, r, s in zip(pick, ref, stats):
         assert rel(out[j], r) <= 1e-10, (j, rel(out[j], r))
         assert mv[j] == s["n_matvec"], j
+
+
+def test_control_problem_full_size_gradient_properties():
+    # L = 14, K = 200 pieces, 2000 steps of CF6:5Opt, m = 20 (the gradient
+    # benchmark): F equals |<target|psi_N>|^2 of the plain propagation, and
+    # central differences of the forward map (h = 1e-4) agree with dF/du on
+    # sampled pieces (the oracle needs minutes for the whole gradient here;
+    # it is compared with the GPU gradient at reduced sizes)
+    p = I.config_adjoint()
+    N = p.nsteps
+    target = p.meta["target"]
+    u = p.drives[0]["u"]
+
+    def forward_F(uu):
+        with B.Propagator(p.H0, p.Hk, [dict(p.drives[0], u=uu)]) as Q:
+            psi = dev(p.psi0)
+            Q.propagate(psi, 0.0, p.dt, N, p.scheme, p.m)
+            return abs(np.vdot(target, psi.cpu().numpy())) ** 2
+
+    with B.Propagator(p.H0, p.Hk, p.drives) as P:
+        F, g = P.gradient(dev(p.psi0), dev(target), 0.0, p.dt, N, p.scheme, p.m)
+        assert P.stats()["status"] == 0
+    g = np.asarray(g)
+    assert abs(F - forward_F(u)) <= 1e-12
+    h = 1e-4
+    scale = np.max(np.abs(g))
+    for q in (3, 117):
+        up, um = u.copy(), u.copy()
+        up[q] += h
+        um[q] -= h
+        fd = (forward_F(up) - forward_F(um)) / (2 * h)
+        assert abs(fd - g[q]) <= 2e-8 * scale, (q, fd, g[q])
