@@ -491,7 +491,8 @@ struct SliceShared {
     int64_t total = 0;
     for (int64_t r = r0; r < r1; ++r) total += rowlen[r];
     table.clear();
-    if (total == 0) return 0;
+    // (a slice of very long rows keeps everything per row)
+    if (total == 0 || total > (int64_t(1) << 29)) return 0;
     uint32_t size = 2;
     while (size < 2 * uint64_t(total)) size <<= 1;
     tmask = size - 1;
