@@ -29,6 +29,9 @@
  *     eigen-solver non-convergence) are latched and reported by the next call
  *     on the context or by cfet_stats().
  *   - A context is not thread-safe: calls on one context must not overlap.
+ *     Its workspace (Krylov basis, internal vectors, barrier state) is shared
+ *     by all its calls, so work it enqueues on different streams must not run
+ *     concurrently either: use one stream per context, or order the streams.
  */
 #ifndef CFET_H
 #define CFET_H
