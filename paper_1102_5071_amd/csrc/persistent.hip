@@ -373,28 +373,32 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
 
   // own-row state (lane 0 of each group): u_{k-1}, u_{k-2}, z_{k-1}
   double2 u1[PMAX], u2[PMAX], zp[PMAX];
-  // raw values gathered for the register-held entries of the current phase
+  // other blocks' columns of the register-held entries: running copies of
+  // u_{k-1} (g1), u_{k-2} (g2), and z_{k-1} gathered for the current phase
   double2 g1[PMAX][QMAX], g2[PMAX][QMAX], gz[PMAX][QMAX];
 #pragma unroll
   for (int p = 0; p < PMAX; ++p) {
     u1[p] = u2[p] = zp[p] = make_double2(0.0, 0.0);
     if (lane == 0 && rowp[p] >= 0) u1[p] = vld<SINGLE>(psi, rowp[p], n);  // becomes u_0
   }
-  // issue the gathers of phase k: u_{k-1}, z_{k-1}, u_{k-2} (phase 0: psi only)
+  // issue the gathers of phase k at the register-held entries whose column is
+  // another block's row: phase 0 takes u_0 = psi, phase k >= 1 only z_{k-1}.
+  // u_{k-1} and u_{k-2} of such a column are the running copies g1, g2 that
+  // this lane formed itself in the two phases before, with the same fused
+  // multiply-adds as the column's owner, so they equal the owner's values bit
+  // for bit (by induction from u_0).
   auto gather = [&](int k) {
     if (SINGLE) return;
-    const double2* __restrict__ a1 = U(k - 1);
+    const double2* __restrict__ a0 = psi;
     const double2* __restrict__ az = Zb(k - 1);
-    const double2* __restrict__ a2 = U(k - 2);
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
 #pragma unroll
       for (int q = 0; q < QMAX; ++q) {
         if (rowp[p] >= 0 && q < cnt[p] && !((lmask[p] >> q) & 1u)) {
           const int64_t c = ccol[p][q] & kColMask;
-          g1[p][q] = vld<SINGLE>(a1, c, n);
-          if (k >= 1) gz[p][q] = vld<SINGLE>(az, c, n);
-          if (k >= 2) g2[p][q] = vld<SINGLE>(a2, c, n);
+          if (k == 0) g1[p][q] = vld<SINGLE>(a0, c, n);
+          else gz[p][q] = vld<SINGLE>(az, c, n);
         }
       }
     }
@@ -528,6 +532,10 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
                 } else {
                   const double2 xg2 = (k >= 2) ? g2[p][q] : make_double2(0.0, 0.0);
                   xv = (k >= 1) ? form_u(gz[p][q], g1[p][q], xg2, c1, c2, c3) : g1[p][q];
+                  if (k >= 1) {  // the running copies move on: u_{k-1}, u_k
+                    g2[p][q] = g1[p][q];
+                    g1[p][q] = xv;
+                  }
                 }
                 const double pr = v.x * xv.x - v.y * xv.y;
                 const double pi = v.x * xv.y + v.y * xv.x;
