@@ -499,7 +499,7 @@ def main():
         log(f"oracle: {cps:.3f} steps/s")
 
     out = {
-        "metric": "CFET steps/s at 1e-8 state error",
+        "metric": "CFET steps/s at 1e-8 state error (batched/adjoint vs plain); SpMV HBM GB/s",
         "value": round(steps_per_s, 3),
         "unit": "steps/s",
         "n_gpus": 1,
