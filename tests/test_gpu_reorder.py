@@ -77,7 +77,8 @@ def test_apply_in_own_row_order():
     assert rel(y, ref) < 1e-14
 
 
-def test_gradient_in_own_row_order():
+@pytest.mark.parametrize("path", [None, "multi"])
+def test_gradient_in_own_row_order(path):
     H0, Hk, psi0 = grid_problem()
     rng = np.random.default_rng(9)
     target = I.random_state(H0.n, rng)
@@ -87,7 +88,7 @@ def test_gradient_in_own_row_order():
     t0, dt, N, scheme, m = 0.0, 0.0005, 8, "CF4:2", 12
     res = {}
     for reorder in (True, False):
-        with B.Propagator(H0, Hk, drives, reorder=reorder) as P:
+        with B.Propagator(H0, Hk, drives, path=path, reorder=reorder) as P:
             assert P.stats()["reordered"] == (1 if reorder else 0)
             res[reorder] = P.gradient(dev(psi0), dev(target), t0, dt, N, scheme, m)
             assert P.stats()["status"] == 0
