@@ -193,6 +193,9 @@ struct Shared {
   // block reductions: per-wavefront values of the first sum at red[w], of the
   // second at red[kRedB + w] (up to 16 wavefronts), results at red[2 kRedB + 0/1]
   double red[2 * kRedB + 2];
+  // the single workgroup's per-iteration sums: two alternating sets of
+  // per-wavefront values (first sum at [w], second at [kRedB + w])
+  double red2[2][2 * kRedB];
   double alpha[kMaxM];
   double beta[kMaxM];
   double inv[kMaxM];
@@ -238,6 +241,33 @@ __device__ void p_block_sum2(double& a, double& b, double* red) {
   __syncthreads();
   a = red[kRedA];
   b = red[kRedA + 1];
+}
+
+// The same two block sums with one block barrier: the per-wavefront values go
+// to the set `parity` of red2 and every thread adds them in the order thread
+// 0 uses above (so the results are the same bit for bit).  Two calls in a row
+// use different sets; a set is rewritten only two calls later, after a block
+// barrier that every thread passes once it has read the set.
+__device__ __forceinline__ void p_block_sum2_1b(double& a, double& b, double (*red2)[2 * kRedB],
+                                                int& parity) {
+  a = p_wave_sum(a);
+  b = p_wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  double* R = red2[parity];
+  if (l == 0) {
+    R[w] = a;
+    R[kRedB + w] = b;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    ta += R[i];
+    tb += R[kRedB + i];
+  }
+  a = ta;
+  b = tb;
+  parity ^= 1;
 }
 
 // Global sums of (a, b) over all threads of all blocks.  Returns false on a fault.
@@ -324,6 +354,7 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
   constexpr int NGRP = BLOCK / G;
   unsigned long long epoch = 0;
   int pc = 0;
+  int rpar = 0;  // set of sh.red2 the next single-workgroup sum uses
   bool ok = true;
   double2* __restrict__ psi = A.psi;
   // u_0 = psi, u_k (k >= 1) in the basis storage; z_k alternates between two buffers
@@ -609,7 +640,7 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
         }
         tm.lap(A.stats, 0);
         if (SINGLE) {
-          p_block_sum2(s_uz, s_uu, sh.red);
+          p_block_sum2_1b(s_uz, s_uu, sh.red2, rpar);
           S1 = s_uz;
           S2 = s_uu;
         } else {
