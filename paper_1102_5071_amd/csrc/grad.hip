@@ -245,7 +245,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
   if ((r & 63) == 0) red[r >> 6] = mx;
   __syncthreads();
   const double nrm = fmax(red[0], red[1]);
-  const int nsub = max(1, (int)ceil(2.0 * nrm));
+  // substeps of infinity norm <= 1: the terms then shrink at least like 1/k!
+  // and no term exceeds the sum by much (no cancellation)
+  const int nsub = max(1, (int)ceil(nrm));
   const double h = dt / nsub;
   // thread r < nm owns entry r of v; the Taylor terms alternate between two
   // LDS buffers, so one barrier per term both publishes the new term and
