@@ -14,6 +14,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace cfet {
 
 __device__ __forceinline__ void wave_sync() {
@@ -169,16 +171,130 @@ __device__ inline int sturm_count(double a, double b, int k, double x) {
   return cnt;
 }
 
-constexpr int kChebMaxTerms = 8192;      // LDS doubles reserved for the Bessel values
+// Miller's backward recurrence for the Bessel values fused with Clenshaw's
+// for the Chebyshev sum (used by tridiag_exp_e1_cheb).  Miller: f_{Nm+1} = 0,
+// f_{Nm} = tiny, f_{j-1} = (2j/theta) f_j - f_{j+1}, with Nm >= N + 16 (J_Nm is
+// then below J_N by orders of magnitude, so the start leaves no trace in
+// f_0 .. f_N); f_j = J_j(theta) / S with S = f_0 + 2 sum_{k >= 1} f_2k (the
+// Bessel sum J_0 + 2 sum J_2k = 1).  The sum sum_{j <= N} w_j f_j T_j(X) e_1,
+// w_0 = 1 and w_j = 2 (sgn i)^j, is taken by Clenshaw's recurrence
+// y_j = w_j f_j e_1 + 2 X y_{j+1} - y_{j+2} (sum = y_0 - X y_1), which runs
+// downwards in j like Miller's, so both advance in one loop as independent
+// chains whose latencies overlap.  X is real: the even j feed the real part,
+// the odd j the imaginary part.  PACKED: both parts in one vector (real rows
+// in lanes 0..31, imaginary rows in lanes 32..63; wre, wim are nonzero in
+// lane 0 and lane 32), else in two (yr, yi; wre, wim nonzero in lane 0).
+// On return f0 = f_0, S without its f_0 term, and y1, y2 (yi1, yi2) = y_1, y_2.
+template <bool PACKED>
+__device__ __forceinline__ void miller_clenshaw(int N, int Nm, double theta, double ax, double blo,
+                                                double bhi, double wre, double wim, double& f0,
+                                                double& S, double& yr1, double& yr2, double& yi1,
+                                                double& yi2) {
+  const double it2 = 2.0 / theta;
+  const double a2 = 2.0 * ax, b2lo = 2.0 * blo, b2hi = 2.0 * bhi;
+  double f1 = 0.0;
+  f0 = 1e-30;
+  S = 0.0;
+  yr1 = yr2 = yi1 = yi2 = 0.0;
+  // f0 <- f_{j-1}, f1 <- f_j
+  auto miller = [&](int j) {
+    const double fm = ((double)j * it2) * f0 - f1;
+    f1 = f0;
+    f0 = fm;
+  };
+  // Clenshaw step j (phase PH = j mod 4) with f0 = f_j
+  auto clenshaw = [&](auto ph) {
+    constexpr int PH = decltype(ph)::value;
+    if (PH == 0 || PH == 2) S += 2.0 * f0;
+    if constexpr (PACKED) {
+      const double lo = from_lane_below(yr1), hi = from_lane_above(yr1);
+      double r = a2 * yr1 - yr2;
+      if (PH == 0) r = wre * f0 + r;
+      if (PH == 2) r = r - wre * f0;
+      if (PH == 1) r = wim * f0 + r;
+      if (PH == 3) r = r - wim * f0;
+      r = b2lo * lo + r;
+      yr2 = yr1;
+      yr1 = b2hi * hi + r;
+    } else {
+      const double lr = from_lane_below(yr1), hr = from_lane_above(yr1);
+      const double li = from_lane_below(yi1), hi = from_lane_above(yi1);
+      double r = a2 * yr1 - yr2;
+      double q = a2 * yi1 - yi2;
+      if (PH == 0) r = wre * f0 + r;
+      if (PH == 2) r = r - wre * f0;
+      if (PH == 1) q = wim * f0 + q;
+      if (PH == 3) q = q - wim * f0;
+      r = b2lo * lr + r;
+      q = b2lo * li + q;
+      yr2 = yr1;
+      yi2 = yi1;
+      yr1 = b2hi * hr + r;
+      yi1 = b2hi * hi + q;
+    }
+  };
+  using P0 = std::integral_constant<int, 0>;
+  using P1 = std::integral_constant<int, 1>;
+  using P2 = std::integral_constant<int, 2>;
+  using P3 = std::integral_constant<int, 3>;
+  auto clenshaw_any = [&](int j) {
+    switch (j & 3) {
+      case 0: clenshaw(P0{}); break;
+      case 1: clenshaw(P1{}); break;
+      case 2: clenshaw(P2{}); break;
+      default: clenshaw(P3{}); break;
+    }
+  };
+  // |f| grows by at most 2 Nm/theta + 1 <= 1e8 per step (theta >= 1e-6 here),
+  // so tests every 4 steps (and once after the first 16..31) at 1e150 keep
+  // every value far below the overflow threshold; everything is scaled alike
+  auto rescale = [&]() {
+    if (__builtin_amdgcn_readfirstlane(fabs(f0) > 1e150 ? 1 : 0)) {
+      f0 *= 1e-200;
+      f1 *= 1e-200;
+      S *= 1e-200;
+      yr1 *= 1e-200;
+      yr2 *= 1e-200;
+      yi1 *= 1e-200;
+      yi2 *= 1e-200;
+    }
+  };
+  int j = Nm;
+  for (; j > N; --j) miller(j);  // f_N, f_{N+1}
+  rescale();
+  for (; j >= 1 && (j & 3) != 3; --j) {
+    clenshaw_any(j);
+    miller(j);
+  }
+  // j = 3 mod 4 at the top: phases 3, 2, 1, 0
+  for (; j >= 4; j -= 4) {
+    clenshaw(P3{});
+    miller(j);
+    clenshaw(P2{});
+    miller(j - 1);
+    clenshaw(P1{});
+    miller(j - 2);
+    clenshaw(P0{});
+    miller(j - 3);
+    rescale();
+  }
+  for (; j >= 1; --j) {
+    clenshaw_any(j);
+    miller(j);
+  }
+}
+
+constexpr int kChebMaxTerms = 8192;      // LDS doubles a caller reserves (the QR path's Z and phi)
 constexpr double kChebMaxTheta = 7000.0; // beyond this the QR path is cheaper
 
 // c = exp(-i dt T) e_1 by the Chebyshev expansion of exp(-i theta x) on the
 // spectral interval of T (Jacobi-Anger: exp(-i theta x) = J_0(theta)
-// + 2 sum_k (-i)^k J_k(theta) T_k(x)).  With X = (T - sigma)/h the vectors
-// T_k(X) e_1 are real and follow t_{k+1} = 2 X t_k - t_{k-1}; the Bessel values
-// J_k(theta) come from Miller's backward recurrence normalised by
-// J_0 + 2 sum J_2k = 1.  lds: kChebMaxTerms doubles.  Returns 0, or 1 if theta
-// is too large for this path (the caller then diagonalises).
+// + 2 sum_k (-i)^k J_k(theta) T_k(x)), with X = (T - sigma)/h.  The Bessel
+// values J_k(theta) come from Miller's backward recurrence normalised by
+// J_0 + 2 sum J_2k = 1, and the series is summed by Clenshaw's backward
+// recurrence in the same loop.  lds is not used here (the QR path uses it).
+// Returns 0, or 1 if theta is too large for this path (the caller then
+// diagonalises).
 __device__ inline int tridiag_exp_e1_cheb(double a, double b, int k, double dt, double* lds,
                                           double2& c) {
   const int lane = threadIdx.x & 63;
@@ -194,7 +310,12 @@ __device__ inline int tridiag_exp_e1_cheb(double a, double b, int k, double dt, 
   lo = wave_min(lo);
   hi = wave_max(hi);
   double theta = fabs(dt) * 0.5 * (hi - lo);
-  if (theta > 32.0 && k > 1) {
+  // A multisection round (one Sturm recurrence of length k per lane) costs
+  // about as much as 60 terms of the expansion below, and a tighter interval
+  // saves (theta_Gershgorin - theta) terms: worth it only for large theta
+  // (Gershgorin overestimates the half-width of Lanczos matrices by some tens
+  // of per cent).
+  if (theta > 256.0 && k > 1) {
     // Two rounds of 64-point multisection on the Sturm count tighten both
     // ends: round 0 spans the Gershgorin interval, round 1 spends 32 points
     // on each end within one round-0 spacing.  Every update keeps a valid
@@ -239,96 +360,34 @@ __device__ inline int tridiag_exp_e1_cheb(double a, double b, int k, double dt, 
     c = (lane < k) ? make_double2(cs * cr + sn * ci, cs * ci - sn * cr) : make_double2(0.0, 0.0);
     return 0;
   }
-  const int N = __builtin_amdgcn_readfirstlane((int)ceil(theta + 12.0 * cbrt(theta) + 20.0));
-  // Miller: f_{Nm+1} = 0, f_{Nm} = tiny, f_{j-1} = (2j/theta) f_j - f_{j+1}, with
-  // Nm >= N + 30 a multiple of 16.  Every lane runs the same scalar recurrence;
-  // lane (j mod 64) keeps f_j and each completed run of 64 values is stored with
-  // one LDS write per lane.  The recurrence runs in unrolled chunks of 16 steps
-  // without branches on its critical path (|f| grows by at most 2 Nm/theta + 1
-  // <= 1e8 per step here, so a rescale test after each chunk at 1e150 cannot be
-  // overtaken by an overflow); the coefficient j (2/theta) of the next step is
-  // formed one step ahead.
-  const int Nm = (N + 30 + 15) & ~15;
-  double f1 = 0.0, f0 = 1e-30, S = 0.0;
-  const double it2 = 2.0 / theta;
-  double mine = 0.0;
-  double jt = (double)Nm * it2;
-  for (int j0 = Nm; j0 >= 16; j0 -= 16) {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int j = j0 - u;
-      const double jn = (double)(j - 1) * it2;
-      const int pick = (j <= N) ? (j & 63) : 64;     // lane that keeps f_j (64: none)
-      mine = (lane == pick) ? f0 : mine;
-      // the run j .. j + 63 is complete (j0 is a multiple of 16: only u = 0 can
-      // be a multiple of 64)
-      if (u == 0 && j <= N && (j & 63) == 0) lds[j + lane] = mine;
-      const double fm = jt * f0 - f1;
-      f1 = f0;
-      f0 = fm;
-      jt = jn;
-    }
-    if (__builtin_amdgcn_readfirstlane(fabs(f0) > 1e150 ? 1 : 0)) {  // rescale all so far (rare)
-      f0 *= 1e-200;
-      f1 *= 1e-200;
-      mine *= 1e-200;
-      for (int q = (j0 - 15 + 63) & ~63; q <= N; q += 64) lds[q + lane] *= 1e-200;
-    }
-  }
-  // the lowest run 0 .. 63 (f_0 now in f0)
-  mine = (lane == 0) ? f0 : mine;
-  lds[lane] = mine;
-  wave_sync();
-  // normalisation J_0 + 2 sum_{k >= 1} J_2k = 1, summed from the stored values
-  // (each lane over its column, then across lanes in a fixed order)
-  for (int q = 0; q <= N; q += 64) {
-    const int jj = q + lane;
-    if (jj <= N && ((jj & 1) == 0)) S += (jj == 0 ? 1.0 : 2.0) * lds[jj];
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) S += __shfl_xor(S, off, 64);
-  // forward Chebyshev recurrence on the real vectors t_k = T_k(X) e_1:
-  // t_{k+1} = 2 X t_k - t_{k-1}, with the diagonal term first so that the
-  // neighbour exchange overlaps it
-  const double a2 = 2.0 * ax, b2lo = 2.0 * blo, b2hi = 2.0 * bhi;
-  const double sgn = (dt >= 0.0) ? -1.0 : 1.0;   // phase (sgn i)^k
-  double tp = (lane == 0) ? 1.0 : 0.0;           // t_0
-  double cr = lds[0] * tp, ci = 0.0;
-  double t = ax * tp + blo * from_lane_below(tp) + bhi * from_lane_above(tp);  // t_1
-  ci += 2.0 * sgn * lds[1] * t;
-  auto next = [&](double cur, double prev) {
-    const double lo = from_lane_below(cur), hi = from_lane_above(cur);
-    double r = a2 * cur - prev;
-    r = b2lo * lo + r;
-    return b2hi * hi + r;
-  };
-  // four terms per iteration: j = 2 mod 4 at the top, so the phases (sgn i)^j
-  // are -1, -sgn i, +1, +sgn i; the four Bessel values are read together
-  int j = 2;
-  for (; j + 3 <= N; j += 4) {
-    const double J0 = lds[j], J1 = lds[j + 1], J2 = lds[j + 2], J3 = lds[j + 3];
-    const double tn = next(t, tp);
-    cr -= 2.0 * J0 * tn;
-    tp = next(tn, t);
-    ci -= sgn * 2.0 * J1 * tp;
-    t = next(tp, tn);
-    cr += 2.0 * J2 * t;
-    const double t4 = next(t, tp);
-    ci += sgn * 2.0 * J3 * t4;
-    tp = t;
-    t = t4;
-  }
-  for (; j <= N; ++j) {
-    const double tn = next(t, tp);
-    tp = t;
-    t = tn;
-    const double w = 2.0 * lds[j];
-    switch (j & 3) {
-      case 0: cr += w * t; break;
-      case 1: ci += sgn * w * t; break;
-      case 2: cr -= w * t; break;
-      default: ci -= sgn * w * t; break;
-    }
+  // truncation after N terms: 2 sum_{j > N} |J_j(theta)| stays below 4e-19
+  // for 0.04 <= theta <= 7000 and below 3e-16 for smaller theta
+  const int N = __builtin_amdgcn_readfirstlane((int)ceil(theta + 12.0 * cbrt(theta) + 2.0));
+  const int Nm = (N + 16 + 15) & ~15;
+  const double sgn = (dt >= 0.0) ? -1.0 : 1.0;   // phase (sgn i)^j
+  double cr, ci, S;
+  if (k <= 32) {
+    // real part in lanes 0..31, imaginary part in lanes 32..63 (row = lane & 31);
+    // the rows past k have zero coefficients, so nothing crosses between halves
+    const int src = lane & 31;
+    const double pax = __shfl(ax, src, 64), pblo = __shfl(blo, src, 64), pbhi = __shfl(bhi, src, 64);
+    double y1, y2, unused1 = 0.0, unused2 = 0.0, f0;
+    miller_clenshaw<true>(N, Nm, theta, pax, pblo, pbhi, (lane == 0) ? 2.0 : 0.0,
+                          (lane == 32) ? 2.0 * sgn : 0.0, f0, S, y1, y2, unused1, unused2);
+    S += f0;
+    double sum = pax * y1 + pblo * from_lane_below(y1) + pbhi * from_lane_above(y1) - y2;
+    sum = ((lane == 0) ? f0 : 0.0) + sum;
+    cr = sum;
+    ci = __shfl(sum, src + 32, 64);
+  } else {
+    const double e1 = (lane == 0) ? 1.0 : 0.0;
+    double yr1, yr2, yi1, yi2, f0;
+    miller_clenshaw<false>(N, Nm, theta, ax, blo, bhi, 2.0 * e1, 2.0 * sgn * e1, f0, S, yr1, yr2,
+                           yi1, yi2);
+    S += f0;
+    cr = ax * yr1 + blo * from_lane_below(yr1) + bhi * from_lane_above(yr1) - yr2;
+    ci = ax * yi1 + blo * from_lane_below(yi1) + bhi * from_lane_above(yi1) - yi2;
+    cr = e1 * f0 + cr;
   }
   const double invS = 1.0 / S;
   cr *= invS;

@@ -157,7 +157,7 @@ def test_sell_uniform_stores_shared_flips_once():
 def _tridiag_cases():
     rng = np.random.default_rng(11)
     cases = []
-    for k in (1, 2, 3, 7, 16, 24, 30, 31, 33, 47, 63, 64):
+    for k in (1, 2, 3, 7, 16, 24, 30, 31, 32, 33, 47, 63, 64):
         a = rng.standard_normal(k) * 3.0
         b = np.abs(rng.standard_normal(k - 1)) + 0.05
         for dt in (0.01, 1.0, 40.0):
