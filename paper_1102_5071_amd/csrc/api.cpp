@@ -1307,7 +1307,7 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
         x = cfet::launch_frechet_dots(n, lam0, vlam, Yall + ix * size_t(m) * nn, Tx, Slam, cpart,
                                       cmat, s_);
       if (x == hipSuccess)
-        x = cfet::launch_frechet_small_rec(Tx, Slam, cmat, dt, rx, dz, c->stats, nullptr, s_);
+        x = cfet::launch_frechet_small_rec(Tx, Slam, cmat, dt, rx, dz, c->stats, nullptr, m, s_);
       return x;
     }
     hipError_t x = cfet::launch_grad_prologue(d_recs, d_cursor, d_cur, before, n, pb, lam,
@@ -1333,7 +1333,8 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
       x = cfet::launch_frechet_c(c->A, kstar + 1, pb, vpsi, rpath != 1 ? lam0 : lam, vlam, Spsi,
                                  Slam, cpart, cmat, s_);
     if (x == hipSuccess)
-      x = cfet::launch_frechet_small_rec(Spsi, Slam, cmat, dt, d_cur, dz, c->stats, d_cursor, s_);
+      x = cfet::launch_frechet_small_rec(Spsi, Slam, cmat, dt, d_cur, dz, c->stats, d_cursor, m,
+                                          s_);
     if (x == hipSuccess && rpath == 1) x = cfet::launch_combine(n, c->plan, wl, s_);
     return x;
   };

@@ -167,9 +167,11 @@ hipError_t launch_grad_prologue(const GradRec* recs, const int* cursor, GradRec*
                                 const double2* before, int64_t n, double2* pb,
                                 const double2* lam, double2* lam_copy, unsigned long long* bar,
                                 int bar_words, int* fault, hipStream_t st);
+// mmax: bound on both Krylov dimensions (one wavefront serves m <= 32)
 hipError_t launch_frechet_small_rec(const LzScalars* Spsi, const LzScalars* Slam,
                                     const double2* C, double dt, const GradRec* cur,
-                                    double2* dz, DevStats* stats, int* cursor, hipStream_t st);
+                                    double2* dz, DevStats* stats, int* cursor, int mmax,
+                                    hipStream_t st);
 int frechet_c_blocks(int64_t n);
 int frechet_part_blocks(int64_t n);  // blocks of partials either C kernel writes, at most
 // C from the stored lambda basis and Y_j = H_k* w_psi,j (exported by the

@@ -323,6 +323,120 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
   }
 }
 
+// The same on one wavefront, for m_lam + m_psi <= 64 and m_psi <= kSmallC:
+// entry r of the term in lane r, neighbours by DPP lane shifts, the term
+// published in LDS for the C product after a wavefront barrier.  The number
+// of terms per substep is fixed in advance by the norm bound: with
+// nu = ||h K||_inf <= 1 (|Re| + |Im| bounds each modulus), term k has
+// infinity norm <= nu^k / k! times that of the substep's start, so the
+// series stops after the K-th term with nu^(K+1) / (K+1)! <= 1e-18 (the
+// entry-wise test of k_frechet_small waits for entries far from the start,
+// which only begin to move after as many terms as their distance).
+__device__ __forceinline__ double lane_below(double v) {  // lane r receives lane r-1 (0 in lane 0)
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_above(double v) {  // lane r receives lane r+1 (0 in lane 63)
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(64) void k_frechet_small_wave(
+    const LzScalars* __restrict__ Spsi, const LzScalars* __restrict__ Slam,
+    const double2* __restrict__ C, double dt, double2* __restrict__ dz, DevStats* stats,
+    const GradRec* __restrict__ rec, int* cursor) {
+  __shared__ double2 tw[64];
+  const int ml = Slam->m_eff, mp = Spsi->m_eff;
+  const int nm = ml + mp;
+  const int r = threadIdx.x;
+  if (cursor && r == 0) *cursor -= 1;
+  if (ml == 0 || mp == 0) return;  // a zero state: no contribution
+  double2 creg[kSmallC];
+#pragma unroll
+  for (int j = 0; j < kSmallC; ++j)
+    creg[j] = (r < ml && j < mp) ? C[r * kMaxM + j] : make_double2(0.0, 0.0);
+  double ad = 0.0, bl = 0.0, bu = 0.0;
+  if (r < ml) {
+    ad = Slam->alpha[r];
+    if (r > 0) bl = Slam->beta[r - 1];
+    if (r + 1 < ml) bu = Slam->beta[r];
+  } else if (r < nm) {
+    const int q = r - ml;
+    ad = Spsi->alpha[q];
+    if (q > 0) bl = Spsi->beta[q - 1];
+    if (q + 1 < mp) bu = Spsi->beta[q];
+  }
+  double rowsum = fabs(ad) + bl + bu;
+  if (r < ml) {
+#pragma unroll
+    for (int j = 0; j < kSmallC; ++j) rowsum += fabs(creg[j].x) + fabs(creg[j].y);  // zero past mp
+  }
+  rowsum *= fabs(dt);
+  double nrm = rowsum;
+  for (int off = 32; off >= 1; off >>= 1) nrm = fmax(nrm, __shfl_xor(nrm, off, 64));
+  const int nsub = __builtin_amdgcn_readfirstlane(max(1, (int)ceil(nrm)));
+  const double h = dt / nsub;
+  const double nu = nrm / nsub;
+  int nterms = 1;
+  for (double nxt = 0.5 * nu * nu; nterms < 59 && nxt > 1e-18; nxt *= nu / (nterms + 1)) ++nterms;
+  nterms = __builtin_amdgcn_readfirstlane(nterms);
+  double2 vr = make_double2(r == ml ? 1.0 : 0.0, 0.0);
+  for (int sub = 0; sub < nsub; ++sub) {
+    double2 t = vr;
+    for (int kk = 1; kk <= nterms; ++kk) {
+      // publish the term for the C product (the previous term's reads are
+      // complete: their values fed the term written here)
+      tw[r] = t;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double tlx = lane_below(t.x), tly = lane_below(t.y);
+      const double tux = lane_above(t.x), tuy = lane_above(t.y);
+      double ar = ad * t.x, ai = ad * t.y;
+      ar += bl * tlx;
+      ai += bl * tly;
+      ar += bu * tux;
+      ai += bu * tuy;
+      if (r < ml) {
+        double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;  // even / odd j
+#pragma unroll
+        for (int j = 0; j < kSmallC; j += 2) {
+          if (j < mp) {
+            const double2 c = creg[j], x = tw[ml + j];
+            er += c.x * x.x - c.y * x.y;
+            ei += c.x * x.y + c.y * x.x;
+          }
+          if (j + 1 < mp) {
+            const double2 c = creg[j + 1], x = tw[ml + j + 1];
+            orr += c.x * x.x - c.y * x.y;
+            oi += c.x * x.y + c.y * x.x;
+          }
+        }
+        ar += er + orr;
+        ai += ei + oi;
+      }
+      const double hk = h / kk;
+      const double2 nt = (r < nm) ? make_double2(hk * ai, -hk * ar) : make_double2(0.0, 0.0);
+      vr.x += nt.x;
+      vr.y += nt.y;
+      t = nt;
+    }
+  }
+  if (r == 0) {
+    const double bb = Slam->beta0 * Spsi->beta0;
+    const double2 g = make_double2(bb * vr.x, bb * vr.y);
+    const int npairs = rec->np;
+    for (int q = 0; q < npairs; ++q) {
+      dz[rec->p[q]].x += rec->w[q] * g.x;
+      dz[rec->p[q]].y += rec->w[q] * g.y;
+    }
+    if (!(isfinite(g.x) && isfinite(g.y)) && stats->status == CFET_OK)
+      stats->status = CFET_ENONFINITE;
+  }
+}
+
 // conj(a) . b partial sums per block (complex).
 __global__ __launch_bounds__(256) void k_zdot(const double2* __restrict__ a,
                                               const double2* __restrict__ b, int64_t n,
@@ -448,9 +562,15 @@ hipError_t launch_frechet_small(const LzScalars* Spsi, const LzScalars* Slam, co
 
 hipError_t launch_frechet_small_rec(const LzScalars* Spsi, const LzScalars* Slam,
                                     const double2* C, double dt, const GradRec* cur,
-                                    double2* dz, DevStats* stats, int* cursor, hipStream_t st) {
-  hipLaunchKernelGGL(k_frechet_small, dim3(1), dim3(kSmallThreads), 0, st, Spsi, Slam, C, dt, 0,
-                     0, 0.0, 0, 0.0, 0, 0.0, 0, 0.0, dz, stats, cur, cursor);
+                                    double2* dz, DevStats* stats, int* cursor, int mmax,
+                                    hipStream_t st) {
+  if (cur && mmax >= 1 && mmax <= kSmallC && 2 * mmax <= 64) {
+    hipLaunchKernelGGL(k_frechet_small_wave, dim3(1), dim3(64), 0, st, Spsi, Slam, C, dt, dz,
+                       stats, cur, cursor);
+  } else {
+    hipLaunchKernelGGL(k_frechet_small, dim3(1), dim3(kSmallThreads), 0, st, Spsi, Slam, C, dt,
+                       0, 0, 0.0, 0, 0.0, 0, 0.0, 0, 0.0, dz, stats, cur, cursor);
+  }
   return hipGetLastError();
 }
 

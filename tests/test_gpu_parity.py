@@ -155,13 +155,21 @@ def test_sell_uniform_stores_shared_flips_once():
 # small exponential exp(-i dt T) e_1
 # --------------------------------------------------------------------------
 def _tridiag_cases():
+    # theta = |dt| h spans the tiny-theta series (< 1e-6), the expansion on the
+    # Gershgorin interval (up to 256), the tightened interval above it, and
+    # negative dt; m = 32 and 33 straddle the packed (two halves of one
+    # wavefront) and the two-vector forms
     rng = np.random.default_rng(11)
     cases = []
     for k in (1, 2, 3, 7, 16, 24, 30, 31, 32, 33, 47, 63, 64):
         a = rng.standard_normal(k) * 3.0
         b = np.abs(rng.standard_normal(k - 1)) + 0.05
-        for dt in (0.01, 1.0, 40.0):
+        for dt in (0.01, 1.0, 12.0, 40.0, -12.0):
             cases.append((f"rand{k}_dt{dt}", a, b, dt))
+    for k in (2, 30, 33):
+        a = rng.standard_normal(k)
+        b = np.abs(rng.standard_normal(k - 1)) + 0.05
+        cases.append((f"tiny_theta{k}", a, b, 1e-8))
     # Lanczos-like: huge spread, tiny tail couplings, near-degenerate pairs
     k = 30
     a = np.concatenate([np.linspace(-0.5, 2.0e5, k - 4), [1.0, 1.0 + 1e-12, 3.0, 3.0]])
@@ -184,7 +192,7 @@ def test_tridiag_exponential(name, a, b, dt):
     c, status = B.tridiag_expm(ta, tb, dt)
     assert status == 0
     ref = O.tridiag_expm_e1(a, b, dt)
-    scale = 1.0 + dt * (np.abs(a).max() + (np.abs(b).max() if len(b) else 0.0))
+    scale = 1.0 + abs(dt) * (np.abs(a).max() + (np.abs(b).max() if len(b) else 0.0))
     assert np.linalg.norm(host(c) - ref) < 1e-13 * scale
 
 
