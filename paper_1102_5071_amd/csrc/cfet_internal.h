@@ -183,9 +183,6 @@ hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
                             const double2* psi_rest, const double2* lam0, const double2* lam_rest,
                             const LzScalars* Spsi, const LzScalars* Slam, double2* part,
                             double2* C, hipStream_t st);
-hipError_t launch_frechet_small(const LzScalars* Spsi, const LzScalars* Slam, const double2* C,
-                                double dt, int npairs, const int* p, const double* w,
-                                double2* dz, DevStats* stats, hipStream_t st);
 int zdot_blocks(int64_t n);
 hipError_t launch_zdot(const double2* a, const double2* b, int64_t n, double2* part,
                        double2* out, hipStream_t st);

@@ -10,9 +10,9 @@
 //     M = -i dt [[S, C], [0, T]],   C_kj = <v_lam,k | H_k* | v_psi,j>.
 // k_frechet_c forms C from the operator (partials per block, fixed-order
 // reduction after); k_frechet_dots forms it from Y_j = H_k* w_psi,j when the
-// recurrence from psi has stored those; k_frechet_small exponentiates M
-// against one unit vector by a Taylor series with substeps and accumulates g
-// into dz/du.
+// recurrence from psi has stored those; k_frechet_small (one wavefront:
+// k_frechet_small_wave, for m <= 32) exponentiates M against one unit vector
+// by a Taylor series with substeps and accumulates g into dz/du.
 #include <hip/hip_runtime.h>
 
 #include "cfet_internal.h"
@@ -194,8 +194,7 @@ __global__ __launch_bounds__(256) void k_frechet_c_reduce(const double2* __restr
 // the (piece, weight) pairs of this exponential.
 __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
     const LzScalars* __restrict__ Spsi, const LzScalars* __restrict__ Slam,
-    const double2* __restrict__ C, double dt, int npairs, int p0, double w0, int p1, double w1,
-    int p2, double w2, int p3, double w3, double2* __restrict__ dz, DevStats* stats,
+    const double2* __restrict__ C, double dt, double2* __restrict__ dz, DevStats* stats,
     const GradRec* __restrict__ rec, int* cursor) {
   __shared__ double2 tb[2][2 * kMaxM];
   __shared__ double red[2];
@@ -245,22 +244,24 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
   if ((r & 63) == 0) red[r >> 6] = mx;
   __syncthreads();
   const double nrm = fmax(red[0], red[1]);
-  // substeps of infinity norm <= 1: the terms then shrink at least like 1/k!
-  // and no term exceeds the sum by much (no cancellation)
+  // substeps of infinity norm nu <= 1: term k is then bounded by nu^k / k!
+  // times the substep's start (no cancellation), and the series stops after
+  // the K-th term with nu^(K+1) / (K+1)! <= 1e-18
   const int nsub = max(1, (int)ceil(nrm));
   const double h = dt / nsub;
+  const double nu = nrm / nsub;
+  int nterms = 1;
+  for (double nxt = 0.5 * nu * nu; nterms < 59 && nxt > 1e-18; nxt *= nu / (nterms + 1)) ++nterms;
   // thread r < nm owns entry r of v; the Taylor terms alternate between two
-  // LDS buffers, so one barrier per term both publishes the new term and
-  // decides (any entry still moving) whether to go on
+  // LDS buffers, so one barrier per term publishes the new term
   double2 vr = make_double2(r == ml ? 1.0 : 0.0, 0.0);
   for (int sub = 0; sub < nsub; ++sub) {
     if (r < nm) tb[0][r] = vr;
     __syncthreads();
     int cur = 0;
-    for (int kk = 1; kk < 60; ++kk) {
+    for (int kk = 1; kk <= nterms; ++kk) {
       // next term = (-i h / kk) K term, K = [[S, C], [0, T]]
       const double2* __restrict__ t = tb[cur];
-      bool moving = false;
       if (r < nm) {
         double ar = ad * t[r].x, ai = ad * t[r].y;
         if (hasl) { ar += bl * t[r - 1].x; ai += bl * t[r - 1].y; }
@@ -294,29 +295,20 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
         vr.x += nt.x;
         vr.y += nt.y;
         tb[cur ^ 1][r] = nt;
-        moving = (fabs(nt.x) + fabs(nt.y)) > 1e-18 * (fabs(vr.x) + fabs(vr.y) + 1e-300);
       }
-      const int any = __syncthreads_or(moving ? 1 : 0);
+      __syncthreads();
       cur ^= 1;
-      if (!any) break;
     }
     __syncthreads();
   }
   if (r == 0) {
     const double bb = Slam->beta0 * Spsi->beta0;
     const double2 g = make_double2(bb * vr.x, bb * vr.y);
-    int ps[4] = {p0, p1, p2, p3};
-    double ws[4] = {w0, w1, w2, w3};
-    if (rec) {  // pairs from device memory (replayed graphs)
-      npairs = rec->np;
-      for (int q = 0; q < 4; ++q) {
-        ps[q] = rec->p[q];
-        ws[q] = rec->w[q];
-      }
-    }
+    // (piece, weight) pairs of this exponential from its record
+    const int npairs = rec->np;
     for (int q = 0; q < npairs; ++q) {
-      dz[ps[q]].x += ws[q] * g.x;
-      dz[ps[q]].y += ws[q] * g.y;
+      dz[rec->p[q]].x += rec->w[q] * g.x;
+      dz[rec->p[q]].y += rec->w[q] * g.y;
     }
     if (!(isfinite(g.x) && isfinite(g.y)) && stats->status == CFET_OK)
       stats->status = CFET_ENONFINITE;
@@ -325,13 +317,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_frechet_small(
 
 // The same on one wavefront, for m_lam + m_psi <= 64 and m_psi <= kSmallC:
 // entry r of the term in lane r, neighbours by DPP lane shifts, the term
-// published in LDS for the C product after a wavefront barrier.  The number
-// of terms per substep is fixed in advance by the norm bound: with
-// nu = ||h K||_inf <= 1 (|Re| + |Im| bounds each modulus), term k has
-// infinity norm <= nu^k / k! times that of the substep's start, so the
-// series stops after the K-th term with nu^(K+1) / (K+1)! <= 1e-18 (the
-// entry-wise test of k_frechet_small waits for entries far from the start,
-// which only begin to move after as many terms as their distance).
+// published in LDS for the C product after a wavefront barrier, and the
+// same term count from the norm bound (|Re| + |Im| bounds each modulus in
+// the norm here).  A count fixed in advance, rather than a test of each
+// entry's last term, matters: entries far down the tridiagonal blocks only
+// begin to move after as many terms as their distance from the start.
 __device__ __forceinline__ double lane_below(double v) {  // lane r receives lane r-1 (0 in lane 0)
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, true);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, true);
@@ -551,25 +541,17 @@ hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
   return launch_c_reduce(part, nb, Spsi, Slam, C, st);
 }
 
-hipError_t launch_frechet_small(const LzScalars* Spsi, const LzScalars* Slam, const double2* C,
-                                double dt, int npairs, const int* p, const double* w,
-                                double2* dz, DevStats* stats, hipStream_t st) {
-  hipLaunchKernelGGL(k_frechet_small, dim3(1), dim3(kSmallThreads), 0, st, Spsi, Slam, C, dt,
-                     npairs, p[0], w[0], p[1], w[1], p[2], w[2], p[3], w[3], dz, stats,
-                     (const GradRec*)nullptr, (int*)nullptr);
-  return hipGetLastError();
-}
-
 hipError_t launch_frechet_small_rec(const LzScalars* Spsi, const LzScalars* Slam,
                                     const double2* C, double dt, const GradRec* cur,
                                     double2* dz, DevStats* stats, int* cursor, int mmax,
                                     hipStream_t st) {
-  if (cur && mmax >= 1 && mmax <= kSmallC && 2 * mmax <= 64) {
+  if (!cur) return hipErrorInvalidValue;
+  if (mmax >= 1 && mmax <= kSmallC && 2 * mmax <= 64) {
     hipLaunchKernelGGL(k_frechet_small_wave, dim3(1), dim3(64), 0, st, Spsi, Slam, C, dt, dz,
                        stats, cur, cursor);
   } else {
     hipLaunchKernelGGL(k_frechet_small, dim3(1), dim3(kSmallThreads), 0, st, Spsi, Slam, C, dt,
-                       0, 0, 0.0, 0, 0.0, 0, 0.0, 0, 0.0, dz, stats, cur, cursor);
+                       dz, stats, cur, cursor);
   }
   return hipGetLastError();
 }

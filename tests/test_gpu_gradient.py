@@ -65,6 +65,19 @@ def test_gradient_matches_oracle(scheme, m, path):
     assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)
 
 
+@pytest.mark.parametrize("L,m", [(6, 16), (7, 40)])
+def test_gradient_block_exponential_forms(L, m):
+    # the small block exponential exp(M), M = -i dt [[S, C], [0, T]]: one
+    # wavefront for m <= 32, the 128-thread form for m = 40 (m_lam + m_psi up
+    # to 80); dt = 0.15 makes ||M||_inf 2 .. 4, so both take substeps
+    H0, Hk, drives, psi0, target = control_problem(L, 6, 0.6, 21 + L)
+    dt, N = 0.15, 4
+    F, g = gpu_grad(H0, Hk, drives, psi0, target, 0.0, dt, N, "CF4:2", m)
+    Fo, go = A.fidelity_gradient(H0, Hk, drives, psi0, target, 0.0, dt, N, "CF4:2", m)
+    assert abs(F - Fo) < 1e-12
+    assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)
+
+
 def test_pieces_cutting_steps_and_ragged_segments():
     # 23 steps (segments of 5: the last one short), edges inside steps
     edges = [0.0, 0.0137, 0.05, 0.0731, 0.1, 0.2, 0.33, 0.47]
