@@ -487,7 +487,7 @@ def main():
     cpu = None
     n_cpu = args.cpu_steps
     if n_cpu < 0:
-        n_cpu = {"hydrogen": 10, "ising": 200, "heisenberg": 1}[args.workload]
+        n_cpu = {"hydrogen": 15, "ising": 200, "heisenberg": 1}[args.workload]
         if args.workload == "heisenberg" and p.dim > (1 << 20):
             n_cpu = 0
     if n_cpu > 0:
