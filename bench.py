@@ -377,7 +377,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+        print("bench.py: the library runs on one GPU (it has no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -54,7 +54,7 @@ enum {
   CFET_ENOMEM = 2,        /* device or host allocation failed */
   CFET_EDEVICE = 3,       /* HIP runtime error */
   CFET_ENONFINITE = 4,    /* NaN/Inf in input data or produced on the device */
-  CFET_EUNSUPPORTED = 5,  /* valid request this build does not implement */
+  CFET_EUNSUPPORTED = 5,  /* valid request the library does not implement */
   CFET_ENOCONV = 6        /* small eigen-solver did not converge */
 };
 
