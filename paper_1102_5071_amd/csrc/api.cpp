@@ -70,6 +70,7 @@ struct cfet_ctx {
   long long spin_limit = 0;
   int num_cus = 0;
   int max_row = 0;                  // longest row of the merged operator
+  bool real_vals = false;           // every stored value has imaginary part 0
   int preset_single = -1;           // register preset of the one-workgroup kernel (-1: none)
   int preset_coop = -1;             // register preset of the cooperative kernel (-1: none)
   int coop_blocks = 0;              // grid of the cooperative kernel
@@ -323,6 +324,7 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
   pa.rowptr = c->A.rowptr;
   pa.colt = c->A.colt;
   pa.val = c->A.val;
+  pa.real_vals = c->real_vals ? 1 : 0;
   pa.n = c->n;
   pa.nterms = c->nterms;
   pa.wts = c->d_wts;
@@ -373,6 +375,7 @@ hipError_t persistent_exponential(cfet_ctx* c, int path, double2* psi, double2* 
   pa.rowptr = c->A.rowptr;
   pa.colt = c->A.colt;
   pa.val = c->A.val;
+  pa.real_vals = c->real_vals ? 1 : 0;
   pa.n = c->n;
   pa.nterms = c->nterms;
   pa.wts = wts_dev;
@@ -786,6 +789,8 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       });
     }
     for (auto& th : pool) th.join();
+    c->real_vals = true;
+    for (int64_t q = 0; q < nnz && c->real_vals; ++q) c->real_vals = (val[2 * q + 1] == 0.0);
     e = hipMalloc(&c->A.rowptr, (n + 1) * sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc(&c->A.colt, std::max<int64_t>(nnz, 1) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&c->A.val, std::max<int64_t>(nnz, 1) * sizeof(double2));

@@ -218,6 +218,7 @@ struct PersistArgs {
   int export_each;          // 1: export_T / export_Y hold one record per exponential of
                             // the call (application order e: export_T + e,
                             // export_Y + e*m*n) instead of the last one only
+  int real_vals;            // 1: every imaginary part of val is 0 (real-valued kernels)
 };
 
 // reset = false: the caller has cleared args.bar and args.fault on the stream

@@ -36,6 +36,8 @@
 #include "cfet_internal.h"
 #include "tridiag.hpp"
 
+#include <type_traits>
+
 namespace cfet {
 
 namespace {
@@ -333,7 +335,11 @@ struct LaunchStats {
   }
 };
 
-template <int G, int PMAX, int QMAX, int NT, bool SINGLE, int BLOCK>
+// RV: every stored value is real (imaginary parts exactly 0), so the
+// register-held entries keep only their real parts (half the registers; the
+// products are the same numbers, a zero imaginary part contributing exact
+// zeros).
+template <int G, int PMAX, int QMAX, int NT, bool SINGLE, int BLOCK, bool RV = false>
 __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
   static_assert(BLOCK % 64 == 0 && BLOCK <= 64 * kRedB, "block of whole wavefronts, at most 16");
   static_assert(SINGLE || PMAX * BLOCK / G <= kCoopMaxRows, "rows of a block exceed the ring");
@@ -368,7 +374,7 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
   int64_t tail_beg[PMAX], tail_end[PMAX];
   int cnt[PMAX];
   uint32_t ccol[PMAX][QMAX];
-  double2 cval[PMAX][QMAX];
+  std::conditional_t<RV, double, double2> cval[PMAX][QMAX];
   uint32_t lmask[PMAX];  // bit q: entry q's column is a row of this block (read from LDS)
 #pragma unroll
   for (int p = 0; p < PMAX; ++p) {
@@ -384,10 +390,12 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
       const int64_t e = beg + lane + (int64_t)q * G;
       if (e < end) {
         ccol[p][q] = A.colt[e] ;
-        cval[p][q] = A.val[e];
+        if constexpr (RV) cval[p][q] = A.val[e].x;
+        else cval[p][q] = A.val[e];
       } else {
         ccol[p][q] = 0u;
-        cval[p][q] = make_double2(0.0, 0.0);
+        if constexpr (RV) cval[p][q] = 0.0;
+        else cval[p][q] = make_double2(0.0, 0.0);
       }
     }
     tail_beg[p] = beg + (int64_t)QMAX * G + lane;
@@ -556,7 +564,7 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
             for (int q = 0; q < QMAX; ++q) {
               if (q < cnt[p]) {
                 const uint32_t ct = ccol[p][q];
-                const double2 v = cval[p][q];
+                const auto v = cval[p][q];
                 double2 xv;
                 if ((lmask[p] >> q) & 1u) {
                   xv = lu[k % 3][(int)((int64_t)(ct & kColMask) - r0)];  // u_k, own block
@@ -568,8 +576,14 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
                     g1[p][q] = xv;
                   }
                 }
-                const double pr = v.x * xv.x - v.y * xv.y;
-                const double pi = v.x * xv.y + v.y * xv.x;
+                double pr, pi;
+                if constexpr (RV) {
+                  pr = v * xv.x;
+                  pi = v * xv.y;
+                } else {
+                  pr = v.x * xv.x - v.y * xv.y;
+                  pi = v.x * xv.y + v.y * xv.x;
+                }
                 if (NT == 1) {
                   if (ct >> kTermShift) { a1r += pr; a1i += pi; } else { a0r += pr; a0i += pi; }
                 } else {
@@ -800,10 +814,10 @@ __global__ void k_persist_reset(unsigned long long* bar, int* fault) {
   if (threadIdx.x == 0) *fault = 0;
 }
 
-template <int G, int P, int Q, bool SINGLE, int B>
+template <int G, int P, int Q, bool SINGLE, int B, bool RV = false>
 const void* pick_nt(int NT) {
-  return NT == 1 ? (const void*)&k_propagate<G, P, Q, 1, SINGLE, B>
-                 : (const void*)&k_propagate<G, P, Q, 0, SINGLE, B>;
+  return NT == 1 ? (const void*)&k_propagate<G, P, Q, 1, SINGLE, B, RV>
+                 : (const void*)&k_propagate<G, P, Q, 0, SINGLE, B, RV>;
 }
 
 static_assert(kNumCoopPresets == 7 && kNumSinglePresets == 3,
@@ -827,11 +841,15 @@ const void* pick_coop(int preset, int NT) {
 #undef CFET_CP
 }
 
-const void* pick_single(int preset, int NT) {
+// real: the single-workgroup kernels also come in the real-valued form (their
+// register-held entries are what spills there)
+const void* pick_single(int preset, int NT, bool real) {
 #define CFET_SP(I)                                                                        \
   case I:                                                                                 \
-    return pick_nt<kSinglePresets[I].G, kSinglePresets[I].P, kSinglePresets[I].Q, true,   \
-                   kSinglePresets[I].B>(NT);
+    return real ? pick_nt<kSinglePresets[I].G, kSinglePresets[I].P, kSinglePresets[I].Q,  \
+                          true, kSinglePresets[I].B, true>(NT)                            \
+                : pick_nt<kSinglePresets[I].G, kSinglePresets[I].P, kSinglePresets[I].Q,  \
+                          true, kSinglePresets[I].B>(NT);
   switch (preset) {
     CFET_SP(0)
     CFET_SP(1)
@@ -880,14 +898,14 @@ int persistent_choose_preset(int max_row, int64_t min_rows_per_block, bool singl
   return best;
 }
 
-const void* persistent_kernel(int preset, int nterms, bool single) {
+const void* persistent_kernel(int preset, int nterms, bool single, bool real = false) {
   const int NT = (nterms == 1) ? 1 : 0;
-  return single ? pick_single(preset, NT) : pick_coop(preset, NT);
+  return single ? pick_single(preset, NT, real) : pick_coop(preset, NT);
 }
 
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,
                              hipStream_t st, bool reset) {
-  const void* fn = persistent_kernel(preset, args.nterms, single);
+  const void* fn = persistent_kernel(preset, args.nterms, single, args.real_vals != 0);
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
   if (reset) {
