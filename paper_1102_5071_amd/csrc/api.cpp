@@ -893,7 +893,7 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     c->preset_coop = cfet::persistent_choose_preset(c->max_row, rows, false);
     if (c->preset_coop >= 0) {
       int maxb = 0;
-      e = cfet::persistent_max_blocks(c->preset_coop, nterms, &maxb);
+      e = cfet::persistent_max_blocks(c->preset_coop, nterms, c->real_vals, &maxb);
       c->coop_blocks = (maxb >= nbw) ? int(nbw) : 0;
       if (c->coop_blocks == 0) c->preset_coop = -1;
     }

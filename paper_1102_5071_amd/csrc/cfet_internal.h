@@ -224,7 +224,8 @@ struct PersistArgs {
 // reset = false: the caller has cleared args.bar and args.fault on the stream
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,
                              hipStream_t st, bool reset = true);
-hipError_t persistent_max_blocks(int preset, int nterms, int* out);
+// real: occupancy of the real-valued form (the one launched for real operators)
+hipError_t persistent_max_blocks(int preset, int nterms, bool real, int* out);
 int persistent_rows_per_block(int preset, bool single);
 int persistent_block_threads(int preset, bool single);
 int persistent_barrier_words();

@@ -823,11 +823,13 @@ const void* pick_nt(int NT) {
 static_assert(kNumCoopPresets == 7 && kNumSinglePresets == 3,
               "pick_coop and pick_single list every preset");
 
-const void* pick_coop(int preset, int NT) {
+const void* pick_coop(int preset, int NT, bool real) {
 #define CFET_CP(I)                                                                        \
   case I:                                                                                 \
-    return pick_nt<kCoopPresets[I].G, kCoopPresets[I].P, kCoopPresets[I].Q, false,        \
-                   kCoopPresets[I].B>(NT);
+    return real ? pick_nt<kCoopPresets[I].G, kCoopPresets[I].P, kCoopPresets[I].Q, false, \
+                          kCoopPresets[I].B, true>(NT)                                    \
+                : pick_nt<kCoopPresets[I].G, kCoopPresets[I].P, kCoopPresets[I].Q, false, \
+                          kCoopPresets[I].B>(NT);
   switch (preset) {
     CFET_CP(0)
     CFET_CP(1)
@@ -841,8 +843,6 @@ const void* pick_coop(int preset, int NT) {
 #undef CFET_CP
 }
 
-// real: the single-workgroup kernels also come in the real-valued form (their
-// register-held entries are what spills there)
 const void* pick_single(int preset, int NT, bool real) {
 #define CFET_SP(I)                                                                        \
   case I:                                                                                 \
@@ -898,9 +898,10 @@ int persistent_choose_preset(int max_row, int64_t min_rows_per_block, bool singl
   return best;
 }
 
-const void* persistent_kernel(int preset, int nterms, bool single, bool real = false) {
+// real: the real-valued form (every stored value has imaginary part 0)
+const void* persistent_kernel(int preset, int nterms, bool single, bool real) {
   const int NT = (nterms == 1) ? 1 : 0;
-  return single ? pick_single(preset, NT, real) : pick_coop(preset, NT);
+  return single ? pick_single(preset, NT, real) : pick_coop(preset, NT, real);
 }
 
 hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, int nblocks,
@@ -924,8 +925,8 @@ hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, i
   return e;
 }
 
-hipError_t persistent_max_blocks(int preset, int nterms, int* out) {
-  const void* fn = persistent_kernel(preset, nterms, false);
+hipError_t persistent_max_blocks(int preset, int nterms, bool real, int* out) {
+  const void* fn = persistent_kernel(preset, nterms, false, real);
   if (!fn) return hipErrorInvalidValue;
   int dev = 0, cus = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
