@@ -443,7 +443,7 @@ def main():
     # launch of the dominant kernel (the SpMV on the multi-kernel path, the
     # whole-call kernel on the persistent paths)
     psi.copy_(psi_start)
-    P.profile(True, max_launches=min(K * s * p.m, 1 << 18))
+    P.profile(True, max_launches=min(K * s * p.m, 1 << 18), segments=False)
     run(psi, t_start, p.dt, K, p.m)
     torch.cuda.synchronize()
     stp = P.stats()
@@ -464,8 +464,17 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     log(f"path {path}: {kernel} {stp['timed_launches']} launches, avg {avg_ms * 1e3:.2f} us, "
         f"{bytes_per_launch / 1e6:.2f} MB algorithmic -> {achieved:.0f} GB/s")
-    seg = [a - b for a, b in zip(stp["segment_us"], st1["segment_us"])]
     if path != "multi":
+        # where block 0's time goes: a third pass with the segment timers on
+        # (they lengthen the kernel slightly, so the pass above runs without)
+        psi.copy_(psi_start)
+        st2 = P.stats()
+        P.profile(True, max_launches=16, segments=True)
+        run(psi, t_start, p.dt, K, p.m)
+        torch.cuda.synchronize()
+        st3 = P.stats()
+        P.profile(False)
+        seg = [a - b for a, b in zip(st3["segment_us"], st2["segment_us"])]
         log("persistent segments (block 0, us per step): spmv %.1f, reduce/barrier %.1f, "
             "small exp %.1f, recombination %.1f" % tuple(x / K for x in seg))
 

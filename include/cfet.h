@@ -160,7 +160,7 @@ typedef struct {
   double last_norm;          /* ||psi|| after the last exponential */
   int64_t timed_launches;    /* launches timed with events (cfet_profile) */
   double timed_ms;           /* their summed event-measured duration */
-  double segment_us[4];      /* persistent paths with cfet_profile on: time of block 0 in
+  double segment_us[4];      /* persistent paths with the segment timers of cfet_profile: time of block 0 in
                                 SpMV phases, reductions/barriers, small exponentials,
                                 recombinations (microseconds, cumulative) */
   int32_t layout;            /* operator storage of the multi-kernel path: 0 merged CSR,
@@ -241,9 +241,12 @@ CFET_API const char *cfet_last_error(const cfet_ctx *c);
  * kernel -- the Lanczos SpMV on the multi-kernel path, the whole persistent
  * kernel on the single-workgroup and cooperative paths -- (up to max_launches
  * pairs; later launches run untimed), and cfet_stats reports the count and
- * summed duration.  The
- * events add a little launch overhead, so throughput is measured with timing
- * off.  enable == 0 releases the events. */
+ * summed duration.  enable == 2 records the events only; any other nonzero
+ * value also runs the persistent kernels' segment timers (cfet_stats
+ * segment_us), which read a clock in block 0 several times per Lanczos
+ * iteration and so lengthen the kernel slightly.  The events add a little
+ * launch overhead, so throughput is measured with timing off.  enable == 0
+ * releases the events. */
 CFET_API int cfet_profile(cfet_ctx *c, int32_t enable, int32_t max_launches);
 
 /* Host-side view of the library's own scheme data: s (exponentials), M

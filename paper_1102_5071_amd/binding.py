@@ -261,8 +261,11 @@ class Propagator:
         """True when the multi-kernel path runs on a SELL-64 layout."""
         return self.stats()["layout"] in (1, 2)
 
-    def profile(self, enable: bool, max_launches: int = 65536):
-        _check(load().cfet_profile(self._ctx, 1 if enable else 0, int(max_launches)), self._ctx)
+    def profile(self, enable: bool, max_launches: int = 65536, segments: bool = True):
+        """Event timing of the dominant kernel; segments: also the persistent
+        kernels' segment timers (they lengthen those kernels slightly)."""
+        mode = 0 if not enable else (1 if segments else 2)
+        _check(load().cfet_profile(self._ctx, mode, int(max_launches)), self._ctx)
 
     def gradient(self, psi0, target, t0: float, dt: float, nsteps: int, scheme, m: int,
                  u=None, stream=None):

@@ -50,6 +50,7 @@ struct cfet_ctx {
   hipStream_t last_stream = nullptr;
   cfet::EventPool events;
   bool profiling = false;
+  bool seg_timers = false;          // profiling also runs the persistent segment timers
   int64_t timed_launches = 0;
   double timed_ms = 0.0;
   bool have_work = false;
@@ -340,7 +341,7 @@ int propagate_persistent(cfet_ctx* c, void* psi_dev, double t0, double dt, int64
   pa.fault = c->d_fault;
   pa.stats = c->stats;
   pa.spin_limit = c->spin_limit;
-  pa.timing = c->profiling ? 1 : 0;
+  pa.timing = (c->profiling && c->seg_timers) ? 1 : 0;
   pa.save = save;
   pa.export_T = export_T;  // one record per exponential of the call
   pa.no_combine = 0;
@@ -1096,6 +1097,7 @@ int cfet_profile(cfet_ctx* c, int32_t enable, int32_t max_launches) {
   harvest_events(c);
   free_events(c);
   c->profiling = false;
+  c->seg_timers = false;
   c->timed_launches = 0;
   c->timed_ms = 0.0;
   if (!enable) return CFET_OK;
@@ -1117,6 +1119,7 @@ int cfet_profile(cfet_ctx* c, int32_t enable, int32_t max_launches) {
     }
   }
   c->profiling = true;
+  c->seg_timers = (enable != 2);
   return CFET_OK;
 }
 

@@ -344,6 +344,27 @@ def test_piecewise_constant_drive(path):
     assert rel(out, ref) < PROP_TOL
 
 
+@pytest.mark.parametrize("path", ["single", "coop"])
+def test_profile_modes(path):
+    # events only: launches timed, segment timers untouched; with segments:
+    # block 0's segment times accumulate; the state is the same either way
+    p = I.config_ising(L=10)
+    with B.Propagator(p.H0, p.Hk, p.drives, path=path) as P:
+        out = []
+        for segments in (False, True):
+            psi = dev(p.psi0)
+            s0 = P.stats()
+            P.profile(True, 64, segments=segments)
+            P.propagate(psi, 0.0, p.dt, 20, p.scheme, p.m)
+            s1 = P.stats()
+            P.profile(False)
+            assert s1["status"] == 0 and s1["timed_launches"] >= 1 and s1["timed_ms"] > 0
+            grew = [a - b for a, b in zip(s1["segment_us"], s0["segment_us"])]
+            assert (min(grew) > 0) if segments else (max(grew) == 0), grew
+            out.append(host(psi))
+    assert np.array_equal(out[0], out[1])
+
+
 # --------------------------------------------------------------------------
 # error handling through the ABI
 # --------------------------------------------------------------------------
