@@ -398,7 +398,7 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the state-error run")
     ap.add_argument("--path", default=None, choices=["multi", "single", "coop"],
                     help="force an execution path (default: chosen by dimension)")
-    ap.add_argument("--layout", default=None, choices=["sell", "sell_uniform"],
+    ap.add_argument("--layout", default=None, choices=["sell", "sell_uniform", "sell_split"],
                     help="operator layout of the multi-kernel path (default: by dimension)")
     ap.add_argument("--chunk", type=int, default=0,
                     help="steps per propagate call (default per workload); every launch "

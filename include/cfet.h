@@ -125,7 +125,8 @@ typedef struct {
 /* Store the operator in sliced-ELL form (64-row slices, column-major, driven
  * terms first in each row) for the multi-kernel path.  Large dimensions
  * (n > 2^22, where only the multi-kernel path runs) default to
- * CFET_LAYOUT_SELL_UNIFORM below; this flag alone selects plain SELL-64. */
+ * CFET_LAYOUT_SELL_SPLIT below, or CFET_LAYOUT_SELL_UNIFORM where the split
+ * does not apply; this flag alone selects plain SELL-64. */
 #define CFET_LAYOUT_SELL 0x100u
 /* SELL-64 as above, plus per slice a shared part: an entry that at least 8
  * rows of a slice (all of them, in a slice of fewer rows) hold with the same
@@ -135,6 +136,19 @@ typedef struct {
  * of summation; detection runs on the host at cfet_create.  Implies
  * CFET_LAYOUT_SELL. */
 #define CFET_LAYOUT_SELL_UNIFORM 0x200u
+/* SELL-64 with shared parts, split into two passes per application, for
+ * operators on n = 2^b rows (b >= 8) whose shared entries connect rows that
+ * differ in a few bits (site operators of spin systems: column = row XOR
+ * offset).  Shared entries whose offset has a bit at or above
+ * min(16, b - 2) leave the first pass, so its gathers stay within 2^16 rows
+ * of the row; a second pass visits the rows in a bit-permuted order in which
+ * the rows such an entry connects lie in the same small block of the order,
+ * and adds their contribution.  Each pass reads x once from memory instead of
+ * re-reading far columns.  Same results up to the order of summation.  Kept
+ * only when the second pass's entries are shared by at least 8 rows on
+ * average (otherwise CFET_LAYOUT_SELL_UNIFORM); the default for n > 2^22.
+ * Implies CFET_LAYOUT_SELL_UNIFORM. */
+#define CFET_LAYOUT_SELL_SPLIT 0x800u
 /* Above 4096 rows, and when the operator is stored as CSR only, cfet_create
  * may give the CSR paths a row order of their own (reverse Cuthill-McKee)
  * when that leaves at least a quarter fewer entries whose column lies in
@@ -164,7 +178,8 @@ typedef struct {
                                 SpMV phases, reductions/barriers, small exponentials,
                                 recombinations (microseconds, cumulative) */
   int32_t layout;            /* operator storage of the multi-kernel path: 0 merged CSR,
-                                1 SELL-64, 2 SELL-64 with shared parts */
+                                1 SELL-64, 2 SELL-64 with shared parts, 3 the same split
+                                into two passes (CFET_LAYOUT_SELL_SPLIT) */
   int32_t reordered;         /* 1: the CSR paths run on their own row order (see
                                 CFET_NO_REORDER) */
   int64_t matrix_bytes;      /* stored operator bytes one application of that layout
@@ -238,8 +253,9 @@ CFET_API const char *cfet_last_error(const cfet_ctx *c);
 
 /* Kernel timing for measurement: with enable != 0, cfet_propagate records a
  * HIP event pair on the caller's stream around every launch of its dominant
- * kernel -- the Lanczos SpMV on the multi-kernel path, the whole persistent
- * kernel on the single-workgroup and cooperative paths -- (up to max_launches
+ * kernel -- the Lanczos SpMV on the multi-kernel path (both launches of a
+ * split layout between one event pair), the whole persistent kernel on the
+ * single-workgroup and cooperative paths -- (up to max_launches
  * pairs; later launches run untimed), and cfet_stats reports the count and
  * summed duration.  enable == 2 records the events only; any other nonzero
  * value also runs the persistent kernels' segment timers (cfet_stats

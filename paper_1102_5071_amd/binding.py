@@ -24,8 +24,8 @@ ERRORS = {0: "CFET_OK", 1: "CFET_EINVAL", 2: "CFET_ENOMEM", 3: "CFET_EDEVICE",
           4: "CFET_ENONFINITE", 5: "CFET_EUNSUPPORTED", 6: "CFET_ENOCONV"}
 VALIDATE_HERMITIAN = 0x1
 PATH_FLAGS = {None: 0, "auto": 0, "multi": 0x10, "single": 0x20, "coop": 0x40,
-              "sell": 0x10 | 0x100, "sell_uniform": 0x10 | 0x200}
-LAYOUT_FLAGS = {None: 0, "auto": 0, "sell": 0x100, "sell_uniform": 0x200}
+              "sell": 0x10 | 0x100, "sell_uniform": 0x10 | 0x200, "sell_split": 0x10 | 0x800}
+LAYOUT_FLAGS = {None: 0, "auto": 0, "sell": 0x100, "sell_uniform": 0x200, "sell_split": 0x800}
 NO_REORDER = 0x400
 PATH_NAMES = {0: "none", 1: "multi", 2: "single", 3: "coop"}
 LAYOUT_NAMES = {0: "csr", 1: "sell", 2: "sell_uniform", 3: "sell_split"}

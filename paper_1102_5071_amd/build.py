@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcfet.so")
 
-SOURCES = ["device.hip", "persistent.hip", "sell.hip", "batch.hip", "grad.hip", "api.cpp", "schemes.cpp",
+SOURCES = ["device.hip", "persistent.hip", "sell.hip", "tile.hip", "batch.hip", "grad.hip", "api.cpp", "schemes.cpp",
            "host_common.cpp", "batch_api.cpp"]
 
 FLAGS = [

@@ -10,6 +10,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "cfet_internal.h"
@@ -27,6 +28,10 @@ struct cfet_ctx {
   int nterms = 0;
   DevCSR A;
   cfet::DevSELL sell;
+  cfet::DevSELLHi hi;       // second pass of the split layout (hi.nuni null: none)
+  int tbits = 0;            // tile size of its LDS-tiled kernels (2^tbits rows)
+  int nb_tile = 0;          // and their grid
+  bool tile_real = false;   // every value stored in the split layout is real
   bool use_sell = false;
   int64_t sell_bytes = 0;   // stored SELL data one application reads
   // row order of the CSR paths (null: the caller's): row i of the stored
@@ -180,6 +185,11 @@ void free_ctx(cfet_ctx* c) {
   if (c->sell.ucolt) (void)hipFree(c->sell.ucolt);
   if (c->sell.uval) (void)hipFree(c->sell.uval);
   if (c->sell.umask) (void)hipFree(c->sell.umask);
+  if (c->hi.nuni) (void)hipFree(c->hi.nuni);
+  if (c->hi.uptr) (void)hipFree(c->hi.uptr);
+  if (c->hi.ucolt) (void)hipFree(c->hi.ucolt);
+  if (c->hi.uval) (void)hipFree(c->hi.uval);
+  if (c->hi.umask) (void)hipFree(c->hi.umask);
   if (c->basis) (void)hipFree(c->basis);
   if (c->partA) (void)hipFree(c->partA);
   if (c->partB) (void)hipFree(c->partB);
@@ -488,12 +498,17 @@ struct SliceShared {
     }
   }
 
-  // Returns the number of shared entries of rows [r0, r1) (at most 64 rows).
-  int run(const std::vector<HostCSR>& mats, int nterms, int64_t r0, int64_t r1,
-          const std::vector<int32_t>& rowlen) {
+  // Shared entries of the rows rows[0 .. nr) (at most 64; bit l of a mask is
+  // rows[l]), over the entries that keep(row, col) accepts.  A candidate is
+  // kept when at least min(need, nr) of the rows hold it.  Returns the number
+  // kept.
+  template <class Keep>
+  int run(const std::vector<HostCSR>& mats, int nterms, const int64_t* rows, int nr, int need,
+          Keep keep_entry) {
     cand.clear();
     int64_t total = 0;
-    for (int64_t r = r0; r < r1; ++r) total += rowlen[r];
+    for (int l = 0; l < nr; ++l)
+      for (int k = 0; k <= nterms; ++k) total += mats[k].rp[rows[l] + 1] - mats[k].rp[rows[l]];
     table.clear();
     // (a slice of very long rows keeps everything per row)
     if (total == 0 || total > (int64_t(1) << 29)) return 0;
@@ -501,9 +516,11 @@ struct SliceShared {
     while (size < 2 * uint64_t(total)) size <<= 1;
     tmask = size - 1;
     table.assign(size, 0);
-    for (int64_t r = r0; r < r1; ++r) {
-      const uint64_t bit = uint64_t(1) << (r - r0);
+    for (int l = 0; l < nr; ++l) {
+      const int64_t r = rows[l];
+      const uint64_t bit = uint64_t(1) << l;
       for_sell_row(mats, nterms, r, [&](int term, int32_t col, const double* v) {
+        if (!keep_entry(r, col)) return;
         const uint32_t key = make_key(r, col, term);
         const uint64_t re = bits(v[0]), im = bits(v[1]);
         uint32_t h = slot(key, re, im);
@@ -522,11 +539,11 @@ struct SliceShared {
         }
       });
     }
-    const int need = int(std::min<int64_t>(kSharedMinRows, r1 - r0));
+    const int need_rows = std::min(need, nr);
     keep.assign(cand.size(), 0);
     int ns = 0;
     for (size_t i = 0; i < cand.size(); ++i)
-      if (cand[i].count >= need) {
+      if (cand[i].count >= need_rows) {
         keep[i] = 1;
         ++ns;
       }
@@ -539,14 +556,36 @@ struct SliceShared {
   }
 };
 
-// Returns false when the host buffers cannot be allocated.
+// An entry (row, col) belongs to the first pass unless the split bit is set
+// (split_bit > 0) and its offset row ^ col has a bit at or above it.
+inline bool low_entry(int64_t r, int32_t col, int split_bit) {
+  return split_bit <= 0 || ((r ^ int64_t(col)) >> split_bit) == 0;
+}
+
+template <class Body>
+void run_threads(int64_t count, unsigned nth, Body body) {
+  if (nth <= 1) {
+    body(int64_t(0), count);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nth; ++t)
+    pool.emplace_back([&, t]() { body(count * t / nth, count * (t + 1) / nth); });
+  for (auto& th : pool) th.join();
+}
+
+// Stage the SELL-64 layout of the first pass: all entries, or with split_bit
+// > 0 only the low-offset ones (the others go to the second pass).  Returns
+// false when the host buffers cannot be allocated.
 bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
-                const std::vector<int32_t>& rowlen, bool uniform, unsigned nth, SellStage* S) {
+                const std::vector<int32_t>& rowlen_all, bool uniform, int split_bit,
+                int tbits, unsigned nth, SellStage* S) {
   const int64_t nsl = (n + 63) / 64;
+  auto keep = [split_bit](int64_t r, int32_t col) { return low_entry(r, col, split_bit); };
   try {
     S->sptr.assign(nsl + 1, 0);
     S->swid.assign(nsl, 0);
-    S->rlen = rowlen;
+    S->rlen = rowlen_all;
     if (uniform) {
       S->nuni.assign(nsl, 0);
       S->uptr.assign(nsl + 1, 0);
@@ -554,19 +593,27 @@ bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
   } catch (const std::bad_alloc&) {
     return false;
   }
-  auto run_threads = [&](auto body) {
-    std::vector<std::thread> pool;
-    for (unsigned t = 0; t < nth; ++t)
-      pool.emplace_back([&, t]() { body(nsl * t / nth, nsl * (t + 1) / nth); });
-    for (auto& th : pool) th.join();
-  };
+  if (split_bit > 0) {
+    // per-row counts of the first pass's entries
+    run_threads(n, nth, [&](int64_t r0, int64_t r1) {
+      for (int64_t r = r0; r < r1; ++r) {
+        int32_t len = 0;
+        for_sell_row(mats, nterms, r, [&](int, int32_t col, const double*) {
+          if (keep(r, col)) ++len;
+        });
+        S->rlen[r] = len;
+      }
+    });
+  }
   if (uniform) {
     // shared entries per slice, and each row's count of the rest
-    run_threads([&](int64_t s0, int64_t s1) {
+    run_threads(nsl, nth, [&](int64_t s0, int64_t s1) {
       SliceShared U;
+      int64_t rows[64];
       for (int64_t sl = s0; sl < s1; ++sl) {
         const int64_t r0 = sl * 64, r1 = std::min<int64_t>(n, sl * 64 + 64);
-        S->nuni[sl] = U.run(mats, nterms, r0, r1, rowlen);
+        for (int64_t r = r0; r < r1; ++r) rows[r - r0] = r;
+        S->nuni[sl] = U.run(mats, nterms, rows, int(r1 - r0), kSharedMinRows, keep);
         for (size_t i = 0; i < U.cand.size(); ++i) {
           if (!U.keep[i]) continue;
           for (int64_t r = r0; r < r1; ++r)
@@ -593,28 +640,37 @@ bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
   } catch (const std::bad_alloc&) {
     return false;
   }
-  run_threads([&](int64_t s0, int64_t s1) {
+  run_threads(nsl, nth, [&](int64_t s0, int64_t s1) {
     SliceShared U;
+    int64_t rows[64];
     for (int64_t sl = s0; sl < s1; ++sl) {
       const int64_t r0 = sl * 64, r1 = std::min<int64_t>(n, sl * 64 + 64);
       const bool uni = uniform && S->nuni[sl] > 0;
       if (uni) {
-        U.run(mats, nterms, r0, r1, rowlen);
+        for (int64_t r = r0; r < r1; ++r) rows[r - r0] = r;
+        U.run(mats, nterms, rows, int(r1 - r0), kSharedMinRows, keep);
         int64_t u = S->uptr[sl];
-        for (size_t i = 0; i < U.cand.size(); ++i) {
-          if (!U.keep[i]) continue;
-          const SliceShared::Cand& cd = U.cand[i];
-          S->ucol[u] = cd.key;
-          std::memcpy(&S->uval[2 * u], &cd.re, sizeof(double));
-          std::memcpy(&S->uval[2 * u + 1], &cd.im, sizeof(double));
-          S->umask[u] = cd.mask;
-          ++u;
+        // with tiles (tbits > 0) the entries reaching outside the tile first
+        for (int round = (tbits > 0 ? 0 : 1); round < 2; ++round) {
+          for (size_t i = 0; i < U.cand.size(); ++i) {
+            if (!U.keep[i]) continue;
+            const SliceShared::Cand& cd = U.cand[i];
+            const bool outside = tbits > 0 && (cd.key & cfet::kColMask) >> tbits;
+            if (round == 0 && !outside) continue;
+            if (round == 1 && tbits > 0 && outside) continue;
+            S->ucol[u] = cd.key;
+            std::memcpy(&S->uval[2 * u], &cd.re, sizeof(double));
+            std::memcpy(&S->uval[2 * u + 1], &cd.im, sizeof(double));
+            S->umask[u] = cd.mask;
+            ++u;
+          }
         }
       }
       for (int64_t r = r0; r < r1; ++r) {
         const int64_t lane = r - r0;
         int64_t k = 0;
         for_sell_row(mats, nterms, r, [&](int term, int32_t col, const double* v) {
+          if (!keep(r, col)) return;
           if (uni && U.shared(r, col, term, v)) return;
           const int64_t pos = S->sptr[sl] + 64 * k + lane;
           S->scol[pos] = uint32_t(col) | (uint32_t(term) << cfet::kTermShift);
@@ -622,6 +678,229 @@ bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
           S->sval[2 * pos + 1] = v[1];
           ++k;
         });
+      }
+    }
+  });
+  return true;
+}
+
+// Shared lists of slices, made compact: each slice's list (entries at
+// uptr[s], nuni[s] of them) is padded with empty entries (mask 0, which no
+// row holds) to a multiple of `pad`, and slices whose padded lists are equal
+// (same offsets, terms, values and masks -- the common case for site terms of
+// spin systems, whose lists depend on a few bits of the slice index) point to
+// one stored copy.  Afterwards uptr[s] is the start of slice s's list (no
+// longer increasing) and uptr[nsl] the number of stored entries.
+bool compact_shared_lists(int64_t nsl, int pad, std::vector<int32_t>* nuni,
+                          std::vector<int64_t>* uptr, std::vector<uint32_t>* ucol,
+                          std::vector<double>* uval, std::vector<uint64_t>* umask) {
+  std::vector<uint32_t> oc;
+  std::vector<double> ov;
+  std::vector<uint64_t> om;
+  std::vector<int64_t> optr;
+  try {
+    optr.assign(nsl + 1, 0);
+    oc.reserve(ucol->size() / 4 + 64);
+    ov.reserve(uval->size() / 4 + 128);
+    om.reserve(umask->size() / 4 + 64);
+  } catch (const std::bad_alloc&) {
+    return false;
+  }
+  // hash of a padded list -> slices whose stored list has that hash
+  std::unordered_map<uint64_t, std::vector<int64_t>> seen;
+  std::vector<uint32_t> lc;
+  std::vector<double> lv;
+  std::vector<uint64_t> lm;
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    const int64_t b = (*uptr)[sl];
+    int cnt = (*nuni)[sl];
+    lc.assign(ucol->begin() + b, ucol->begin() + b + cnt);
+    lv.assign(uval->begin() + 2 * b, uval->begin() + 2 * (b + cnt));
+    lm.assign(umask->begin() + b, umask->begin() + b + cnt);
+    while (pad > 1 && cnt % pad) {
+      lc.push_back(0u);
+      lv.push_back(0.0);
+      lv.push_back(0.0);
+      lm.push_back(0ull);
+      ++cnt;
+    }
+    uint64_t h = 0x9E3779B97F4A7C15ull ^ uint64_t(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      uint64_t re, im;
+      std::memcpy(&re, &lv[2 * i], 8);
+      std::memcpy(&im, &lv[2 * i + 1], 8);
+      for (uint64_t w : {uint64_t(lc[i]), re, im, lm[i]}) {
+        h ^= w + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+        h *= 0xBF58476D1CE4E5B9ull;
+      }
+    }
+    int64_t at = -1;
+    std::vector<int64_t>& cands = seen[h];
+    for (int64_t other : cands) {
+      if ((*nuni)[other] != cnt) continue;
+      const int64_t ob = optr[other];
+      if (std::equal(lc.begin(), lc.end(), oc.begin() + ob) &&
+          std::memcmp(lv.data(), ov.data() + 2 * ob, lv.size() * sizeof(double)) == 0 &&
+          std::equal(lm.begin(), lm.end(), om.begin() + ob)) {
+        at = ob;
+        break;
+      }
+    }
+    if (at < 0) {
+      at = int64_t(oc.size());
+      oc.insert(oc.end(), lc.begin(), lc.end());
+      ov.insert(ov.end(), lv.begin(), lv.end());
+      om.insert(om.end(), lm.begin(), lm.end());
+      cands.push_back(sl);
+    }
+    (*nuni)[sl] = cnt;
+    optr[sl] = at;
+  }
+  optr[nsl] = int64_t(oc.size());
+  ucol->swap(oc);
+  uval->swap(ov);
+  umask->swap(om);
+  uptr->swap(optr);
+  return true;
+}
+
+// Split of the shared-part layout into two passes (see DevSELLHi).  Applies to
+// operators on 2^nbits rows (nbits >= 8): entries whose offset row ^ col has a
+// bit at or above split_bit = min(16, nbits - 2) leave the first pass, whose
+// gathers then stay within 2^16 rows (1 MiB of a vector) of the row.
+constexpr int kSplitBitMax = 16;
+constexpr int kSplitMinBits = 8;
+
+struct SplitPlan {
+  int nbits = 0;
+  int split_bit = 0;      // 0: no split
+  int tbits = 0;          // tile of both passes: 2^tbits indices
+  int pos[32] = {};       // row position of permuted bit b
+  int64_t high = 0;       // entries of the second pass
+};
+
+// The permuted order: the three lowest row bits first (8 consecutive rows),
+// then every bit that a second-pass offset uses, then the remaining bits, each
+// group in increasing order.  Returns false if nothing would move.
+bool plan_split(const std::vector<HostCSR>& mats, int nterms, int64_t n, unsigned nth,
+                SplitPlan* P) {
+  int nbits = 0;
+  while ((int64_t(1) << nbits) < n) ++nbits;
+  if ((int64_t(1) << nbits) != n || nbits < kSplitMinBits) return false;
+  const int S = std::min(kSplitBitMax, nbits - 2);
+  std::vector<uint64_t> used(nth, 0);
+  std::vector<int64_t> cnt(nth, 0);
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nth; ++t)
+    pool.emplace_back([&, t]() {
+      const int64_t r0 = n * t / nth, r1 = n * (t + 1) / nth;
+      uint64_t u = 0;
+      int64_t c = 0;
+      for (int64_t r = r0; r < r1; ++r)
+        for_sell_row(mats, nterms, r, [&](int, int32_t col, const double*) {
+          if (!low_entry(r, col, S)) {
+            u |= uint64_t(r ^ int64_t(col));
+            ++c;
+          }
+        });
+      used[t] = u;
+      cnt[t] = c;
+    });
+  for (auto& th : pool) th.join();
+  uint64_t u = 0;
+  int64_t c = 0;
+  for (unsigned t = 0; t < nth; ++t) {
+    u |= used[t];
+    c += cnt[t];
+  }
+  if (c == 0) return false;
+  // the second pass's tile must hold every column its rows read: the three
+  // low bits and the bits of its offsets
+  const int tb = std::min(cfet::kTileBitsMax, nbits);
+  int nb2 = 3;
+  for (int b = 3; b < nbits; ++b) nb2 += int((u >> b) & 1u);
+  if (nb2 > tb) return false;
+  P->nbits = nbits;
+  P->split_bit = S;
+  P->tbits = tb;
+  P->high = c;
+  int k = 0;
+  for (int b = 0; b < 3; ++b) P->pos[k++] = b;
+  for (int b = 3; b < nbits; ++b)
+    if ((u >> b) & 1u) P->pos[k++] = b;
+  for (int b = 3; b < nbits; ++b)
+    if (!((u >> b) & 1u)) P->pos[k++] = b;
+  return true;
+}
+
+inline int64_t permuted_row(const SplitPlan& P, int64_t q) {
+  int64_t r = 0;
+  for (int b = 0; b < P.nbits; ++b) r |= ((q >> b) & 1) << P.pos[b];
+  return r;
+}
+
+// The offset in the permuted order: bit pos[b] of off becomes bit b.
+inline uint32_t permuted_offset(const SplitPlan& P, uint32_t off) {
+  uint32_t q = 0;
+  for (int b = 0; b < P.nbits; ++b) q |= ((off >> P.pos[b]) & 1u) << b;
+  return q;
+}
+
+struct SellHiStage {
+  std::vector<int32_t> nuni;
+  std::vector<int64_t> uptr;
+  std::vector<uint32_t> ucol;
+  std::vector<double> uval;
+  std::vector<uint64_t> umask;
+};
+
+// Stage the second pass: every high-offset entry, shared per permuted slice.
+bool stage_sell_hi(const std::vector<HostCSR>& mats, int nterms, int64_t n, const SplitPlan& P,
+                   unsigned nth, SellHiStage* H) {
+  const int64_t nsl = n / 64;
+  const int S = P.split_bit;
+  auto keep = [S](int64_t r, int32_t col) { return !low_entry(r, col, S); };
+  try {
+    H->nuni.assign(nsl, 0);
+    H->uptr.assign(nsl + 1, 0);
+  } catch (const std::bad_alloc&) {
+    return false;
+  }
+  auto slice_rows = [&](int64_t sl, int64_t* rows) {
+    for (int l = 0; l < 64; ++l) rows[l] = permuted_row(P, sl * 64 + l);
+  };
+  run_threads(nsl, nth, [&](int64_t s0, int64_t s1) {
+    SliceShared U;
+    int64_t rows[64];
+    for (int64_t sl = s0; sl < s1; ++sl) {
+      slice_rows(sl, rows);
+      H->nuni[sl] = U.run(mats, nterms, rows, 64, 1, keep);
+    }
+  });
+  for (int64_t sl = 0; sl < nsl; ++sl) H->uptr[sl + 1] = H->uptr[sl] + H->nuni[sl];
+  const int64_t us = H->uptr[nsl];
+  try {
+    H->ucol.assign(us, 0u);
+    H->uval.assign(2 * us, 0.0);
+    H->umask.assign(us, 0ull);
+  } catch (const std::bad_alloc&) {
+    return false;
+  }
+  run_threads(nsl, nth, [&](int64_t s0, int64_t s1) {
+    SliceShared U;
+    int64_t rows[64];
+    for (int64_t sl = s0; sl < s1; ++sl) {
+      slice_rows(sl, rows);
+      U.run(mats, nterms, rows, 64, 1, keep);
+      int64_t u = H->uptr[sl];
+      for (size_t i = 0; i < U.cand.size(); ++i) {
+        const SliceShared::Cand& cd = U.cand[i];
+        H->ucol[u] = permuted_offset(P, cd.key & cfet::kColMask) |
+                     (cd.key & ~cfet::kColMask);
+        std::memcpy(&H->uval[2 * u], &cd.re, sizeof(double));
+        std::memcpy(&H->uval[2 * u + 1], &cd.im, sizeof(double));
+        H->umask[u] = cd.mask;
+        ++u;
       }
     }
   });
@@ -718,7 +997,8 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     c->max_row = std::max<int>(c->max_row, rowlen[r]);
   }
   const bool use_sell =
-      (flags & (CFET_LAYOUT_SELL | CFET_LAYOUT_SELL_UNIFORM)) || n > kAutoCoopMaxN;
+      (flags & (CFET_LAYOUT_SELL | CFET_LAYOUT_SELL_UNIFORM | CFET_LAYOUT_SELL_SPLIT)) ||
+      n > kAutoCoopMaxN;
   const bool need_csr = !use_sell || n <= kAutoCoopMaxN;
   c->A.n = n;
   c->A.nnz = nnz;
@@ -816,10 +1096,39 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     const int64_t nsl = (n + 63) / 64;
     // large dimensions default to the uniform-part layout; CFET_LAYOUT_SELL
     // alone asks for plain SELL-64
-    const bool uniform = (flags & CFET_LAYOUT_SELL_UNIFORM) ||
-                         (!(flags & CFET_LAYOUT_SELL) && n > kAutoCoopMaxN);
+    const bool auto_layout =
+        !(flags & (CFET_LAYOUT_SELL | CFET_LAYOUT_SELL_UNIFORM | CFET_LAYOUT_SELL_SPLIT)) &&
+        n > kAutoCoopMaxN;
+    const bool uniform =
+        (flags & (CFET_LAYOUT_SELL_UNIFORM | CFET_LAYOUT_SELL_SPLIT)) || auto_layout;
+    const unsigned nth = (n < 65536) ? 1u : nth_all;
+    // the split into two passes: asked for, or the automatic large-dimension
+    // layout; kept when the second pass's entries are shared by at least
+    // kSharedMinRows rows on average (site operators of spin systems)
+    SplitPlan sp;
+    SellHiStage HS;
+    bool split = false;
+    if (((flags & CFET_LAYOUT_SELL_SPLIT) || auto_layout) &&
+        plan_split(mats, nterms, n, nth, &sp)) {
+      if (!stage_sell_hi(mats, nterms, n, sp, nth, &HS)) {
+        rc = fail(c, CFET_ENOMEM, "cannot stage the SELL matrix on the host");
+        free_ctx(c);
+        return rc;
+      }
+      split = HS.uptr.back() * kSharedMinRows <= sp.high;
+      if (!split) HS = SellHiStage();
+    }
     SellStage S;
-    if (!stage_sell(mats, nterms, n, rowlen, uniform, (n < 65536) ? 1u : nth_all, &S)) {
+    bool staged = stage_sell(mats, nterms, n, rowlen, uniform, split ? sp.split_bit : 0,
+                             split ? sp.tbits : 0, nth, &S);
+    // compact shared lists; the tiled kernels of the split layout read them in
+    // groups of four entries
+    if (staged && uniform)
+      staged = compact_shared_lists(nsl, split ? 4 : 1, &S.nuni, &S.uptr, &S.ucol, &S.uval,
+                                    &S.umask);
+    if (staged && split)
+      staged = compact_shared_lists(n / 64, 4, &HS.nuni, &HS.uptr, &HS.ucol, &HS.uval, &HS.umask);
+    if (!staged) {
       rc = fail(c, CFET_ENOMEM, "cannot stage the SELL matrix on the host");
       free_ctx(c);
       return rc;
@@ -865,11 +1174,44 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
         e = hipMemcpy(c->sell.umask, S.umask.data(), us * sizeof(uint64_t), hipMemcpyHostToDevice);
       c->sell_bytes += 28 * us + 12 * nsl;
     }
+    if (split) {
+      const int64_t hsl = n / 64;
+      const int64_t us = HS.uptr[hsl];
+      c->hi.n = n;
+      c->hi.nslices = hsl;
+      c->hi.nbits = sp.nbits;
+      for (int b = 0; b < 32; ++b) c->hi.pos[b] = sp.pos[b];
+      c->hi.uslots = us;
+      if (e == hipSuccess) e = hipMalloc(&c->hi.nuni, hsl * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc(&c->hi.uptr, (hsl + 1) * sizeof(int64_t));
+      if (e == hipSuccess) e = hipMalloc(&c->hi.ucolt, std::max<int64_t>(us, 1) * sizeof(uint32_t));
+      if (e == hipSuccess) e = hipMalloc(&c->hi.uval, std::max<int64_t>(us, 1) * sizeof(double2));
+      if (e == hipSuccess) e = hipMalloc(&c->hi.umask, std::max<int64_t>(us, 1) * sizeof(uint64_t));
+      if (e == hipSuccess)
+        e = hipMemcpy(c->hi.nuni, HS.nuni.data(), hsl * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(c->hi.uptr, HS.uptr.data(), (hsl + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess && us)
+        e = hipMemcpy(c->hi.ucolt, HS.ucol.data(), us * sizeof(uint32_t), hipMemcpyHostToDevice);
+      if (e == hipSuccess && us)
+        e = hipMemcpy(c->hi.uval, HS.uval.data(), us * sizeof(double2), hipMemcpyHostToDevice);
+      if (e == hipSuccess && us)
+        e = hipMemcpy(c->hi.umask, HS.umask.data(), us * sizeof(uint64_t), hipMemcpyHostToDevice);
+      c->sell_bytes += 28 * us + 12 * hsl;
+      c->tbits = sp.tbits;
+      bool real = true;
+      for (size_t q = 1; q < S.sval.size() && real; q += 2) real = (S.sval[q] == 0.0);
+      for (size_t q = 1; q < S.uval.size() && real; q += 2) real = (S.uval[q] == 0.0);
+      for (size_t q = 1; q < HS.uval.size() && real; q += 2) real = (HS.uval[q] == 0.0);
+      c->tile_real = real;
+      if (e == hipSuccess) e = cfet::tile_prepare();
+    }
     c->use_sell = true;
   }
   c->plan = cfet::make_plan(n, nnz);
   if (c->use_sell) c->plan.nb_spmv = cfet::sell_grid(n);
-  const int np = std::max(c->plan.nb_spmv, c->plan.nb_vec);
+  // alpha partials: one per SpMV block and pass
+  const int np = std::max(2 * c->plan.nb_spmv, c->plan.nb_vec);
   if (e == hipSuccess) e = hipMalloc(&c->partA, np * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->partB, np * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&c->S, sizeof(LzScalars));
@@ -887,6 +1229,7 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     if (khz <= 0) khz = 100000;
     c->spin_limit = (long long)khz * 1000LL * 10LL;  // 10 s
   }
+  if (c->hi.nuni) c->nb_tile = cfet::tile_grid(n, c->tbits, c->num_cus);
   c->preset_single = need_csr ? cfet::persistent_choose_preset(c->max_row, n, true) : -1;
   if (e == hipSuccess && c->num_cus > 0 && need_csr) {
     const int64_t nbw = coop_grid_blocks(n, c->num_cus);
@@ -970,7 +1313,11 @@ int cfet_apply(cfet_ctx* c, const void* x_dev, void* y_dev, double a, const doub
   for (int k = 0; k < c->nterms; ++k) tw.w[k + 1] = b[k];
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   hipError_t e;
-  if (c->use_sell) {
+  if (c->use_sell && c->hi.nuni) {
+    e = cfet::launch_tile_apply(c->sell, c->hi, c->tbits, c->nb_tile, c->nterms, tw,
+                                static_cast<const double2*>(x_dev), static_cast<double2*>(y_dev),
+                                st);
+  } else if (c->use_sell) {
     e = cfet::launch_sell_apply(c->sell, c->nterms, tw, static_cast<const double2*>(x_dev),
                                 static_cast<double2*>(y_dev), st);
   } else if (c->perm) {  // the stored row order: permute x in and y out
@@ -1047,6 +1394,10 @@ int propagate_impl(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nst
   wk.S = c->S;
   wk.stats = c->stats;
   wk.sell = c->use_sell ? &c->sell : nullptr;
+  wk.hi = (c->use_sell && c->hi.nuni) ? &c->hi : nullptr;
+  wk.tbits = c->tbits;
+  wk.nb_tile = c->nb_tile;
+  wk.tile_real = c->tile_real;
   if (c->profiling) {
     if (c->events.used > 0) {
       (void)hipStreamSynchronize(c->last_stream);
@@ -1445,7 +1796,7 @@ int cfet_stats(cfet_ctx* c, cfet_stats_t* s) {
   s->min_m_eff = d.exponentials ? d.min_m_eff : 0;
   s->breakdowns = d.breakdowns;
   s->path = c->last_path;
-  s->layout = !c->use_sell ? 0 : (c->sell.nuni ? 2 : 1);
+  s->layout = !c->use_sell ? 0 : (c->hi.nuni ? 3 : (c->sell.nuni ? 2 : 1));
   s->reordered = c->perm ? 1 : 0;
   s->matrix_bytes = c->use_sell ? c->sell_bytes : 20 * c->A.nnz + 8 * (c->n + 1);
   s->status = d.status;

@@ -98,7 +98,50 @@ struct DevSELL {
   int64_t uslots = 0;
 };
 
+// Second pass of the split shared-part layout (operators on 2^nbits rows whose
+// shared entries connect rows that differ in a few bits, e.g. spin chains).
+// Shared entries whose column offset (row XOR column) has a bit at or above a
+// split bit are taken out of the first pass (DevSELL above) and stored here
+// for slices of a bit-permuted row order: permuted index q has its bit b at
+// position pos[b] of the row, row = sum_b bit_b(q) << pos[b], and slice s holds
+// the 64 rows q = 64 s .. 64 s + 63.  The low permuted bits are the three
+// lowest row bits (8 consecutive rows, 128 bytes of a vector) and then every
+// bit that such an offset uses, so the rows one slice gathers from lie in the
+// same small block of permuted indices as the slice itself: a tile of 2^tbits
+// permuted indices holds every column its rows read.  Every entry of this
+// pass is shared (mask of the slice rows holding it) and stores its offset in
+// the permuted order (column index q ^ offset).
+struct DevSELLHi {
+  int64_t n = 0;
+  int64_t nslices = 0;
+  int nbits = 0;
+  int32_t pos[32] = {};
+  int32_t* nuni = nullptr;
+  int64_t* uptr = nullptr;
+  uint32_t* ucolt = nullptr;     // permuted offset | term << kTermShift
+  double2* uval = nullptr;
+  uint64_t* umask = nullptr;     // bit l: row of permuted index 64 s + l
+  int64_t uslots = 0;
+};
+
 int sell_grid(int64_t n);
+// LDS-tiled SpMV of the split layout (tile.hip): tiles of 2^tbits indices of
+// each pass's order (tbits <= kTileBitsMax); both passes in one call.
+constexpr int kTileBitsMax = 12;
+int tile_grid(int64_t n, int tbits, int num_cus);
+// Allows the tile kernels their LDS (once per process and device).
+hipError_t tile_prepare();
+// y = H x.
+hipError_t launch_tile_apply(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, int nterms,
+                             const TermWeights& tw, const double2* x, double2* y,
+                             hipStream_t st);
+// Lanczos SpMV, same contract as launch_sell_lz_spmv; the alpha partials of
+// the two passes go to pout[0 .. 2 nb).
+// real_vals: every stored value of both passes has imaginary part 0.
+hipError_t launch_tile_lz_spmv(const DevSELL& S, const DevSELLHi& H, int tbits, int nb,
+                               int nterms, bool real_vals, const TermWeights& tw,
+                               const double2* x, double2* y, const double* pin, int npin,
+                               double* pout, LzScalars* L, int j, hipStream_t st);
 hipError_t launch_sell_apply(const DevSELL& S, int nterms, const TermWeights& tw, const double2* x,
                              double2* y, hipStream_t st);
 hipError_t launch_sell_lz_spmv(const DevSELL& S, int nterms, const TermWeights& tw,
@@ -128,6 +171,10 @@ struct EventPool {
 struct ExpWork {
   double2* const* W_host;  // basis pointers: W[0] = psi, W[j] = workspace (W[j] = W[1] + (j-1) n)
   const DevSELL* sell;   // SELL layout for the SpMV (null: CSR)
+  const DevSELLHi* hi = nullptr;  // second pass of a split SELL layout (null: none)
+  int tbits = 0;                  // its tile size (2^tbits indices)
+  int nb_tile = 0;                // and grid
+  bool tile_real = false;         // its stored values are all real
   EventPool* events;     // optional SpMV timing (null: off)
   double* partA;         // partial sums (norms)
   double* partB;         // partial sums (alpha)

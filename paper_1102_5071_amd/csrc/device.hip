@@ -440,12 +440,17 @@ hipError_t launch_lanczos(const DevCSR& A, int nterms, const LaunchPlan& plan,
                               hipStream_t st) {
   LzScalars* S = wk.S;
   hipError_t e = hipSuccess;
+  // partial sums of alpha: one per block of the SpMV (of each of its passes)
+  const int np_alpha = (wk.sell && wk.hi) ? 2 * wk.nb_tile : plan.nb_spmv;
   for (int j = 0; j < m; ++j) {
     const double2* x = wk.W_host[j];
     double2* y = (j + 1 < m) ? wk.W_host[j + 1] : nullptr;
     EventPool* ev = (wk.events && wk.events->used < wk.events->cap) ? wk.events : nullptr;
     if (ev) (void)hipEventRecord(ev->begin[ev->used], st);
-    if (wk.sell)
+    if (wk.sell && wk.hi)
+      e = launch_tile_lz_spmv(*wk.sell, *wk.hi, wk.tbits, wk.nb_tile, nterms, wk.tile_real, tw, x,
+                              y, wk.partA, plan.nb_vec, wk.partB, S, j, st);
+    else if (wk.sell)
       e = launch_sell_lz_spmv(*wk.sell, nterms, tw, x, y, wk.partA, plan.nb_vec, wk.partB, S, j, st);
     else if (nterms == 1)
       e = dispatch_spmv<1>(plan.G, A, plan.nb_spmv, tw, wk.twp, x, y, wk.partA, plan.nb_vec,
@@ -461,12 +466,12 @@ hipError_t launch_lanczos(const DevCSR& A, int nterms, const LaunchPlan& plan,
     if (j + 1 < m) {
       const double2* wm1 = (j > 0) ? wk.W_host[j - 1] : nullptr;
       hipLaunchKernelGGL(k_lz_axpy, dim3(plan.nb_vec), dim3(kBlock), 0, st, A.n, x, wm1,
-                         wk.W_host[j + 1], wk.partB, plan.nb_spmv, wk.partA, S, j);
+                         wk.W_host[j + 1], wk.partB, np_alpha, wk.partA, S, j);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
   }
-  hipLaunchKernelGGL(k_lz_small, dim3(1), dim3(64), 0, st, wk.partB, plan.nb_spmv, S, m, dt,
+  hipLaunchKernelGGL(k_lz_small, dim3(1), dim3(64), 0, st, wk.partB, np_alpha, S, m, dt,
                      wk.stats);
   return hipGetLastError();
 }

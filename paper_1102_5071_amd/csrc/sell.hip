@@ -73,6 +73,46 @@ __device__ __forceinline__ void sell_acc(uint32_t ct, dvec2 v, double2 xv, const
   }
 }
 
+// Shared entries of a slice: entry k is (offset | term, value) held by the
+// rows of mask um[k] (bit = lane); a holding lane gathers x[row ^ offset],
+// the others gather x[xr] (a valid row) and add a zero product, so the
+// wavefront issues one gather per entry.
+template <int NT>
+__device__ __forceinline__ void shared_acc(const uint32_t* __restrict__ uc,
+                                           const dvec2* __restrict__ uv,
+                                           const uint64_t* __restrict__ um, int nu, int lane,
+                                           int64_t row, int64_t xr, const double2* __restrict__ x,
+                                           const double* wl, double& a0r, double& a0i,
+                                           double& a1r, double& a1i) {
+  int k = 0;
+  for (; k + 4 <= nu; k += 4) {
+    uint32_t ct[4];
+    dvec2 v[4];
+    bool on[4];
+    double2 xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ct[u] = uc[k + u];
+      v[u] = uv[k + u];
+      on[u] = (um[k + u] >> lane) & 1ull;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = x[on[u] ? row ^ (int64_t)(ct[u] & kColMask) : xr];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!on[u]) v[u] = dvec2{0.0, 0.0};
+      sell_acc<NT>(ct[u], v[u], xv[u], wl, a0r, a0i, a1r, a1i);
+    }
+  }
+  for (; k < nu; ++k) {
+    const uint32_t ct = uc[k];
+    const bool on = (um[k] >> lane) & 1ull;
+    const double2 xv = x[on ? row ^ (int64_t)(ct & kColMask) : xr];
+    const dvec2 v = on ? uv[k] : dvec2{0.0, 0.0};
+    sell_acc<NT>(ct, v, xv, wl, a0r, a0i, a1r, a1i);
+  }
+}
+
 // y_row = sum_k w_{term} val x[col] over the row's entries (lane = row; the
 // slice index is the same for the whole wavefront).
 template <int NT>
@@ -90,37 +130,8 @@ __device__ __forceinline__ double2 sell_row(const DevSELL& S, int64_t slice_in, 
   const int nu = S.nuni ? S.nuni[slice] : 0;
   if (nu > 0) {
     const int64_t ub = S.uptr[slice];
-    const uint32_t* __restrict__ uc = S.ucolt + ub;
-    const dvec2* __restrict__ uv = reinterpret_cast<const dvec2*>(S.uval) + ub;
-    const uint64_t* __restrict__ um = S.umask + ub;
-    const int64_t xr = valid ? row : 0;
-    int k = 0;
-    for (; k + 4 <= nu; k += 4) {
-      uint32_t ct[4];
-      dvec2 v[4];
-      bool on[4];
-      double2 xv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ct[u] = uc[k + u];
-        v[u] = uv[k + u];
-        on[u] = (um[k + u] >> lane) & 1ull;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) xv[u] = x[on[u] ? row ^ (int64_t)(ct[u] & kColMask) : xr];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (!on[u]) v[u] = dvec2{0.0, 0.0};
-        sell_acc<NT>(ct[u], v[u], xv[u], wl, a0r, a0i, a1r, a1i);
-      }
-    }
-    for (; k < nu; ++k) {
-      const uint32_t ct = uc[k];
-      const bool on = (um[k] >> lane) & 1ull;
-      const double2 xv = x[on ? row ^ (int64_t)(ct & kColMask) : xr];
-      const dvec2 v = on ? uv[k] : dvec2{0.0, 0.0};
-      sell_acc<NT>(ct, v, xv, wl, a0r, a0i, a1r, a1i);
-    }
+    shared_acc<NT>(S.ucolt + ub, reinterpret_cast<const dvec2*>(S.uval) + ub, S.umask + ub, nu,
+                   lane, row, valid ? row : 0, x, wl, a0r, a0i, a1r, a1i);
   }
   const uint32_t* __restrict__ cp = S.colt + base + lane;
   const dvec2* __restrict__ vp = reinterpret_cast<const dvec2*>(S.val) + base + lane;
@@ -259,6 +270,7 @@ __global__ __launch_bounds__(kSellBlock) CFET_SELL_OCCUPANCY void k_sell_lz_spmv
   apart = s_block_sum(apart, red);
   if (threadIdx.x == 0) part_out[blockIdx.x] = apart;
 }
+
 
 }  // namespace
 

@@ -1,0 +1,448 @@
+// LDS-tiled Lanczos SpMV for the split shared-part layout (two passes).
+//
+// Both passes walk the rows in tiles of 2^tbits consecutive indices of their
+// order (the identity for the first pass, the bit-permuted order of DevSELLHi
+// for the second).  A workgroup copies the tile's x values into LDS with
+// coalesced loads, then its wavefronts run the tile's 64-row slices: a shared
+// entry whose offset stays inside the tile (offset < 2^tbits in that order)
+// reads x from LDS, every other column is gathered from memory.  In the
+// second pass every offset stays inside the tile (the layout is built so); in
+// the first the out-of-tile entries of a slice are stored first, so the first
+// batch of a slice issues its gathers before its LDS reads.
+//
+// The entries' metadata is uniform across a wavefront and read with scalar
+// loads; an entry held by every row of its slice (a site flip) skips the
+// per-lane mask test, and operators whose stored values are all real
+// accumulate real products only (half the floating-point work).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "cfet_internal.h"
+
+namespace cfet {
+
+namespace {
+
+constexpr int kTileThreads = 512;  // 8 wavefronts; two workgroups per CU (64 KiB tiles)
+constexpr int kTileWaves = kTileThreads / 64;
+constexpr int kTileLoads = (1 << kTileBitsMax) / kTileThreads;  // tile elements per thread
+// The tile is staged through eight named registers per thread (an array here
+// is kept in scratch memory across the barrier by the compiler).
+static_assert(kTileLoads == 8, "tile staging is written out for eight loads per thread");
+#define CFET_TILE_8(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7)
+#define CFET_TS(u) xt[((int)threadIdx.x + u * kTileThreads) & (T - 1)] = b##u;
+constexpr int kTileScratch = 32;   // doubles after the tile: block sums and term weights
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double t_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ double t_block_sum(double v, double* red) {
+  v = t_wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kTileWaves; ++i) t += red[i];
+    red[16] = t;
+  }
+  __syncthreads();
+  return red[16];
+}
+
+__device__ double t_sum_partials(const double* __restrict__ part, int np, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+  return t_block_sum(s, red);
+}
+
+// The layout arrays are not written while the kernels run: reading them
+// through the constant address space lets uniform reads use scalar loads.
+#define CFET_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const CFET_CONST T* as_const(const T* p) {
+  return (const CFET_CONST T*)(p);
+}
+
+// Term weights as the kernels read them: NT = 1 (one driven term): w0, w1
+// in scalar registers; otherwise the table wl in LDS.
+struct Wts {
+  double w0, w1;
+  const double* wl;
+};
+
+// (ar, ai) += w_term v xv, the weight folded into the value (RV: the
+// imaginary part of v is zero).  ct is uniform for shared entries and
+// per-lane for per-row slots.
+template <int NT, bool RV>
+__device__ __forceinline__ void t_acc(uint32_t ct, dvec2 v, double2 xv, const Wts& W, double& ar,
+                                      double& ai) {
+  const double w = (NT == 1) ? ((ct >> kTermShift) ? W.w1 : W.w0) : W.wl[ct >> kTermShift];
+  const double er = w * v.x;
+  if (RV) {
+    ar = fma(er, xv.x, ar);
+    ai = fma(er, xv.y, ai);
+  } else {
+    const double ei = w * v.y;
+    ar = fma(er, xv.x, fma(-ei, xv.y, ar));
+    ai = fma(er, xv.y, fma(ei, xv.x, ai));
+  }
+}
+
+// Shared entries of one slice (count nu, a multiple of four: the lists of
+// this layout are padded with entries no row holds; first at uc/uv/um) for the
+// lane with tile-local index qloc, row `row` and mask bit lanebit.  Offsets up
+// to tmask read the tile in LDS at qloc ^ offset; larger ones (GLOBAL: only
+// the first pass, identity order) gather x[row ^ offset] -- they are stored
+// first, so the first group of a slice issues its gathers before its LDS
+// reads.  The metadata of four entries is read (scalar loads) before any of
+// it is used: one latency per group.
+template <int NT, bool RV, bool GLOBAL>
+__device__ __forceinline__ void t_shared(const CFET_CONST uint32_t* uc, const CFET_CONST dvec2* uv,
+                                         const CFET_CONST uint64_t* um, int nu,
+                                         uint64_t lanebit, int qloc, int64_t row, uint32_t tmask,
+                                         const double2* xt, const double2* __restrict__ x,
+                                         const Wts& W, double& ar, double& ai) {
+  for (int k = 0; k < nu; k += 4) {
+    uint32_t ct[4];
+    uint64_t m[4];
+    dvec2 v[4];
+    double2 xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ct[u] = uc[k + u];
+      m[u] = um[k + u];
+      v[u].x = uv[k + u].x;
+      v[u].y = RV ? 0.0 : uv[k + u].y;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t off = ct[u] & kColMask;
+      if (GLOBAL && off > tmask) xv[u] = x[(m[u] & lanebit) ? row ^ (int64_t)off : row];
+      else xv[u] = xt[(qloc ^ (int)off) & (int)tmask];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (m[u] & lanebit) t_acc<NT, RV>(ct[u], v[u], xv[u], W, ar, ai);
+  }
+}
+
+// Tile schedule: blocks are dealt to the 8 XCDs round-robin (block b on XCD
+// b % 8); each XCD takes a contiguous eighth of the tiles, swept by its
+// blocks together, so out-of-tile neighbours gathered by nearby tiles stay in
+// that XCD's L2.
+struct TileRange {
+  int64_t first, end, stride;
+};
+
+__device__ __forceinline__ TileRange tile_range(int64_t ntiles) {
+  constexpr int kXcds = 8;
+  const int nb = gridDim.x;
+  if (nb % kXcds != 0 || ntiles < nb) return {(int64_t)blockIdx.x, ntiles, (int64_t)nb};
+  const int xcd = blockIdx.x % kXcds;
+  const int rank = blockIdx.x / kXcds;
+  const int64_t per = (ntiles + kXcds - 1) / kXcds;
+  const int64_t beg = min(ntiles, (int64_t)xcd * per);
+  const int64_t end = min(ntiles, beg + per);
+  return {beg + rank, end, (int64_t)(nb / kXcds)};
+}
+
+// Row of the index q of the permuted order (pos: row position of bit b of q;
+// bits 0 .. nbits-1 of q, nbits <= MAXB).
+template <int MAXB>
+__device__ __forceinline__ int64_t perm_row(const int32_t* pos, int nbits, int64_t q) {
+  int64_t r = 0;
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b)
+    if (b < nbits) r |= ((q >> b) & 1) << pos[b];
+  return r;
+}
+
+// Finishes the pending norm reduction of Lanczos step j and applies the early
+// stop rule (the contract of the first SpMV launch of a step); returns false
+// when the recurrence has stopped, else 1/||w_j|| in *inv.
+__device__ bool t_lanczos_start(const double* __restrict__ part_in, int np_in, LzScalars* L,
+                                int j, double* red, double* inv) {
+  if (j > 0 && L->brk[j - 1]) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) L->brk[j] = 1;
+    return false;
+  }
+  const double nrm2 = t_sum_partials(part_in, np_in, red);
+  const bool b0 = (blockIdx.x == 0 && threadIdx.x == 0);
+  if (j == 0) {
+    const double beta0 = sqrt(nrm2);
+    const bool stop = (beta0 == 0.0);
+    if (b0) {
+      L->beta0 = beta0;
+      L->inv_nrm[0] = stop ? 0.0 : 1.0 / beta0;
+      L->brk[0] = stop ? 1 : 0;
+      if (stop) L->m_eff = 0;
+    }
+    if (stop) return false;
+    *inv = 1.0 / beta0;
+  } else {
+    const double b = sqrt(nrm2);
+    double sc = 0.0;
+    for (int k = 0; k < j - 1; ++k) sc = fmax(sc, fabs(L->alpha[k]) + L->beta[k]);
+    sc = fmax(sc, fabs(L->alpha[j - 1]) + b);
+    const bool stop = (b <= kBreakdownRel * sc);
+    if (b0) {
+      L->beta[j - 1] = b;
+      L->brk[j] = stop ? 1 : 0;
+      if (stop) L->m_eff = j;
+      else L->inv_nrm[j] = 1.0 / b;
+    }
+    if (stop) return false;
+    *inv = 1.0 / b;
+  }
+  return true;
+}
+
+// First pass over tiles of consecutive rows: shared entries (in-tile from
+// LDS, the rest gathered) and per-row slots.  LZ: Lanczos form (scale by
+// inv, partials of Re<v_j, y>); else y = H x.
+template <int NT, bool LZ, bool RV>
+__global__ __launch_bounds__(kTileThreads) void k_tile_pass1(
+    DevSELL S, int tbits, TermWeights tw, const double2* __restrict__ x, double2* __restrict__ y,
+    const double* __restrict__ part_in, int np_in, double* __restrict__ part_out, LzScalars* L,
+    int j) {
+  extern __shared__ double2 xt[];
+  const int T = 1 << tbits;
+  double* red = reinterpret_cast<double*>(xt + T);
+  double* wl = red + 20;
+  double inv = 1.0;
+  if (LZ && !t_lanczos_start(part_in, np_in, L, j, red, &inv)) return;
+  if (threadIdx.x <= kMaxTerms) wl[threadIdx.x] = tw.w[threadIdx.x];
+  const Wts W{tw.w[0], tw.w[1], wl};
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar metadata loads
+  const uint64_t lanebit = 1ull << lane;
+  const uint32_t tmask = (uint32_t)(T - 1);
+  const TileRange R = tile_range(S.n >> tbits);
+  double apart = 0.0;
+  for (int64_t tile = R.first; tile < R.end; tile += R.stride) {
+    const int64_t r0 = tile << tbits;
+    // all loads in flight at once; a tile smaller than the block's share
+    // (small operators) is read several times over (index masked into it)
+#define CFET_TL(u) const double2 b##u = x[r0 + (((int)threadIdx.x + u * kTileThreads) & (T - 1))];
+    CFET_TILE_8(CFET_TL)
+#undef CFET_TL
+    __syncthreads();  // the previous tile's readers are done (and wl is set)
+    CFET_TILE_8(CFET_TS)
+    __syncthreads();
+    for (int sl = wave; sl < (T >> 6); sl += kTileWaves) {
+      const int qloc = sl * 64 + lane;
+      const int64_t row = r0 + qloc;
+      const int64_t slice = (r0 >> 6) + sl;
+      double ar = 0.0, ai = 0.0;
+      // the row's first per-row slot is read before the shared entries, so
+      // its latency overlaps them
+      const int len = S.rowlen[row];
+      const int64_t base = as_const(S.slice_ptr)[slice];
+      const uint32_t* __restrict__ cp = S.colt + base + lane;
+      const dvec2* __restrict__ vp = reinterpret_cast<const dvec2*>(S.val) + base + lane;
+      uint32_t ct0 = 0u;
+      dvec2 v0 = dvec2{0.0, 0.0};
+      if (len > 0) {
+        ct0 = __builtin_nontemporal_load(cp);
+        v0 = __builtin_nontemporal_load(vp);
+      }
+      const int nu = as_const(S.nuni)[slice];
+      if (nu > 0) {
+        const int64_t ub = as_const(S.uptr)[slice];
+        t_shared<NT, RV, true>(as_const(S.ucolt + ub),
+                               as_const(reinterpret_cast<const dvec2*>(S.uval) + ub),
+                               as_const(S.umask + ub), nu, lanebit, qloc, row, tmask, xt, x, W,
+                               ar, ai);
+      }
+      for (int k = 0; k < len; ++k) {
+        uint32_t ct = ct0;
+        dvec2 v = v0;
+        if (k > 0) {
+          ct = __builtin_nontemporal_load(cp + (int64_t)k * 64);
+          v = __builtin_nontemporal_load(vp + (int64_t)k * 64);
+        }
+        const int64_t col = (int64_t)(ct & kColMask);
+        const double2 xv = ((col >> tbits) == (row >> tbits)) ? xt[col & tmask] : x[col];
+        t_acc<NT, RV>(ct, v, xv, W, ar, ai);
+      }
+      if (LZ) {
+        ar *= inv;
+        ai *= inv;
+        if (y) __builtin_nontemporal_store(dvec2{ar, ai}, reinterpret_cast<dvec2*>(y) + row);
+        const double2 xr = xt[qloc];
+        apart += (xr.x * ar + xr.y * ai) * inv;
+      } else {
+        y[row] = make_double2(ar, ai);
+      }
+    }
+  }
+  if (LZ) {
+    apart = t_block_sum(apart, red);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = apart;
+  }
+}
+
+// Second pass over tiles of the permuted order (every offset inside the tile):
+// y[row] += H_hi x.  LZ: Lanczos form (state of the first pass, partials).
+template <int NT, bool LZ, bool RV>
+__global__ __launch_bounds__(kTileThreads) void k_tile_pass2(
+    DevSELLHi H, int tbits, TermWeights tw, const double2* __restrict__ x,
+    double2* __restrict__ y, double* __restrict__ part_out, const LzScalars* L, int j) {
+  extern __shared__ double2 xt[];
+  const int T = 1 << tbits;
+  double* red = reinterpret_cast<double*>(xt + T);
+  double* wl = red + 20;
+  double inv = 1.0;
+  if (LZ) {
+    if (L->brk[j]) return;
+    inv = L->inv_nrm[j];
+  }
+  if (threadIdx.x <= kMaxTerms) wl[threadIdx.x] = tw.w[threadIdx.x];
+  const Wts W{tw.w[0], tw.w[1], wl};
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar metadata loads
+  const uint64_t lanebit = 1ull << lane;
+  const uint32_t tmask = (uint32_t)(T - 1);
+  // row bits (inside a tile) of the indices this thread loads and of this
+  // lane inside a slice: the same for every tile
+#define CFET_LOC(u) \
+  const int64_t loc##u = perm_row<kTileBitsMax>(H.pos, tbits, ((int)threadIdx.x + u * kTileThreads) & (T - 1));
+  CFET_TILE_8(CFET_LOC)
+#undef CFET_LOC
+  const int64_t lane_bits = perm_row<6>(H.pos, 6, lane);
+  const TileRange R = tile_range(H.n >> tbits);
+  double apart = 0.0;
+  for (int64_t tile = R.first; tile < R.end; tile += R.stride) {
+    const int64_t q0 = tile << tbits;
+    const int64_t rbase = perm_row<32>(H.pos, H.nbits, q0);
+#define CFET_TL(u) const double2 b##u = x[rbase | loc##u];
+    CFET_TILE_8(CFET_TL)
+#undef CFET_TL
+    __syncthreads();
+    CFET_TILE_8(CFET_TS)
+    __syncthreads();
+    for (int sl = wave; sl < (T >> 6); sl += kTileWaves) {
+      const int qloc = sl * 64 + lane;
+      const int64_t slice = (q0 >> 6) + sl;
+      const int64_t row = rbase | perm_row<kTileBitsMax>(H.pos, tbits, (int64_t)sl * 64) | lane_bits;
+      double ar = 0.0, ai = 0.0;
+      const int nu = as_const(H.nuni)[slice];
+      if (nu > 0) {
+        const int64_t ub = as_const(H.uptr)[slice];
+        t_shared<NT, RV, false>(as_const(H.ucolt + ub),
+                                as_const(reinterpret_cast<const dvec2*>(H.uval) + ub),
+                                as_const(H.umask + ub), nu, lanebit, qloc, row, tmask, xt, x, W,
+                                ar, ai);
+      }
+      if (LZ) {
+        ar *= inv;
+        ai *= inv;
+        if (y) {
+          const dvec2 y1 = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(y) + row);
+          __builtin_nontemporal_store(dvec2{y1.x + ar, y1.y + ai},
+                                      reinterpret_cast<dvec2*>(y) + row);
+        }
+        const double2 xr = xt[qloc];
+        apart += (xr.x * ar + xr.y * ai) * inv;
+      } else {
+        const double2 y1 = y[row];
+        y[row] = make_double2(y1.x + ar, y1.y + ai);
+      }
+    }
+  }
+  if (LZ) {
+    apart = t_block_sum(apart, red);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = apart;
+  }
+}
+
+size_t tile_lds_bytes(int tbits) {
+  return (size_t(1) << tbits) * sizeof(double2) + kTileScratch * sizeof(double);
+}
+
+template <class K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int NT, bool LZ, bool RV>
+hipError_t allow_pair() {
+  const size_t b = tile_lds_bytes(kTileBitsMax);
+  hipError_t e = allow_lds(k_tile_pass1<NT, LZ, RV>, b);
+  if (e == hipSuccess) e = allow_lds(k_tile_pass2<NT, LZ, RV>, b);
+  return e;
+}
+
+template <int NT, bool RV>
+void launch_lz(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, const TermWeights& tw,
+               const double2* x, double2* y, const double* pin, int npin, double* pout,
+               LzScalars* L, int j, hipStream_t st) {
+  const size_t lds = tile_lds_bytes(tbits);
+  hipLaunchKernelGGL((k_tile_pass1<NT, true, RV>), dim3(nb), dim3(kTileThreads), lds, st, S,
+                     tbits, tw, x, y, pin, npin, pout, L, j);
+  hipLaunchKernelGGL((k_tile_pass2<NT, true, RV>), dim3(nb), dim3(kTileThreads), lds, st, H,
+                     tbits, tw, x, y, pout + nb, L, j);
+}
+
+template <int NT>
+void launch_ap(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, const TermWeights& tw,
+               const double2* x, double2* y, hipStream_t st) {
+  const size_t lds = tile_lds_bytes(tbits);
+  hipLaunchKernelGGL((k_tile_pass1<NT, false, false>), dim3(nb), dim3(kTileThreads), lds, st, S,
+                     tbits, tw, x, y, nullptr, 0, nullptr, nullptr, 0);
+  hipLaunchKernelGGL((k_tile_pass2<NT, false, false>), dim3(nb), dim3(kTileThreads), lds, st, H,
+                     tbits, tw, x, y, nullptr, nullptr, 0);
+}
+
+}  // namespace
+
+int tile_grid(int64_t n, int tbits, int num_cus) {
+  const int64_t ntiles = n >> tbits;
+  const int64_t want = std::max<int64_t>(1, int64_t(2) * std::max(num_cus, 1));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, want));
+}
+
+hipError_t tile_prepare() {
+  hipError_t e = allow_pair<1, true, true>();
+  if (e == hipSuccess) e = allow_pair<1, true, false>();
+  if (e == hipSuccess) e = allow_pair<0, true, true>();
+  if (e == hipSuccess) e = allow_pair<0, true, false>();
+  if (e == hipSuccess) e = allow_pair<1, false, false>();
+  if (e == hipSuccess) e = allow_pair<0, false, false>();
+  return e;
+}
+
+hipError_t launch_tile_lz_spmv(const DevSELL& S, const DevSELLHi& H, int tbits, int nb,
+                               int nterms, bool real_vals, const TermWeights& tw,
+                               const double2* x, double2* y, const double* pin, int npin,
+                               double* pout, LzScalars* L, int j, hipStream_t st) {
+  if (nterms == 1 && real_vals)
+    launch_lz<1, true>(S, H, tbits, nb, tw, x, y, pin, npin, pout, L, j, st);
+  else if (nterms == 1)
+    launch_lz<1, false>(S, H, tbits, nb, tw, x, y, pin, npin, pout, L, j, st);
+  else if (real_vals)
+    launch_lz<0, true>(S, H, tbits, nb, tw, x, y, pin, npin, pout, L, j, st);
+  else
+    launch_lz<0, false>(S, H, tbits, nb, tw, x, y, pin, npin, pout, L, j, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_apply(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, int nterms,
+                             const TermWeights& tw, const double2* x, double2* y,
+                             hipStream_t st) {
+  if (nterms == 1) launch_ap<1>(S, H, tbits, nb, tw, x, y, st);
+  else launch_ap<0>(S, H, tbits, nb, tw, x, y, st);
+  return hipGetLastError();
+}
+
+}  // namespace cfet

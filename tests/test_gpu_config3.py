@@ -1,0 +1,209 @@
+"""GPU parity at the sizes and windows the benchmark runs, against stored
+oracle results and closed forms.
+
+* Heisenberg chain (the at-scale spin-chain workload: J = 1, h_i ~ U[-1, 1],
+  H1 = sum sx, f = 0.5 sin 1.3t, random product state, CF6:5Opt, dt = 0.02,
+  m = 24):
+  - L = 24 (dim 2^24), 2 steps from t = 0, on the default layout (SELL-64 with
+    shared parts split in two passes) and on the one-pass shared layout,
+    against the oracle's result stored by tests/golden/make_goldens.py:
+    entries at seeded sample rows (slice and half-space edges included), the
+    norm, and projections onto seeded complex Gaussian vectors (each involves
+    every entry: for an error vector d, <r|d> has standard deviation
+    sqrt(2) ||d||, so |<r|d>| <= 1e-9 says ||d|| is of order 1e-10 or less);
+  - L = 18, the whole 200-step run, on the default path (cooperative kernel)
+    and on the multi-kernel path with both shared layouts: whole final state.
+* Hydrogen on the radial grid: the benchmark's window (t0 = 40, dt = 0.002,
+  10 + 20 steps in calls of 10 steps, cooperative kernel).
+* Closed forms at dim 2^24 (no oracle run at full size):
+  - L = 24 non-interacting spins, each the circularly driven two-level system
+    H = Delta sz + V (cos 2wt sx + sin 2wt sy) (Sec. 6.2): every exponential
+    of the scheme factorises over the sites, so the CFET state is the tensor
+    product of the single-spin CFET states (oracle, exact 2 x 2 exponentials):
+    parity 1e-10; and the state is within the scheme's error of the tensor
+    product of the closed form eq. TwoLevelU;
+  - a diagonal H0 with f = 0: the scheme's weights of H0 sum to one, so every
+    step is exactly exp(-i dt H0): pure phases, 1e-12.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cfet as O
+from paper_1102_5071_amd import inputs as I
+from tests.closed_forms import two_level_U
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_1102_5071_amd.binding")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+PROP_TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    B.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.complex128)).to("cuda")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f"missing stored oracle result {name}: run tests/golden/make_goldens.py")
+    return np.load(path, allow_pickle=False)
+
+
+def sample_rows(n):
+    # the same seeded rows as the generator of the stored results
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_goldens",
+                                                  os.path.join(GOLDEN, "make_goldens.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    return mg.sample_rows(n), list(mg.projection_vectors(n))
+
+
+_cache = {}
+
+
+def heisenberg(L):
+    if L not in _cache:
+        _cache.clear()
+        _cache[L] = I.config_heisenberg(L=L)
+    return _cache[L]
+
+
+@pytest.mark.parametrize("layout,code", [(None, 3), ("sell_uniform", 2)],
+                         ids=["split_default", "shared_one_pass"])
+def test_heisenberg_L24_two_steps_vs_oracle(layout, code):
+    g = golden("heisenberg_L24_2steps.npz")
+    p = heisenberg(24)
+    n = p.dim
+    with B.Propagator(p.H0, p.Hk, p.drives, layout=layout) as P:
+        st = P.stats()
+        assert st["layout"] == code
+        psi = dev(p.psi0)
+        print(f"[L=24 {layout or 'default'}] propagating 2 steps", flush=True)
+        P.propagate(psi, 0.0, p.dt, 2, p.scheme, p.m)
+        st = P.stats()
+        out = psi.cpu().numpy()
+    del psi
+    assert st["status"] == 0 and B.PATH_NAMES[st["path"]] == "multi"
+    assert st["matvecs"] == int(g["n_matvec"])
+    rows, projs = sample_rows(n)
+    assert np.array_equal(rows, g["rows"])
+    assert rel(out[rows], g["psi_rows"]) <= PROP_TOL
+    assert abs(np.linalg.norm(out) - float(g["norm"])) <= 1e-12
+    for r, ref in zip(projs, g["proj"]):
+        assert abs(np.vdot(r, out) - ref) <= 1e-9
+
+
+@pytest.mark.parametrize("path", [None, "sell_uniform", "sell_split"])
+def test_heisenberg_L18_200_steps_vs_oracle(path):
+    g = golden("heisenberg_L18_200steps.npz")
+    p = heisenberg(18)
+    with B.Propagator(p.H0, p.Hk, p.drives, path=path) as P:
+        psi = dev(p.psi0)
+        P.propagate(psi, 0.0, p.dt, 200, p.scheme, p.m)
+        st = P.stats()
+        out = psi.cpu().numpy()
+    assert st["status"] == 0
+    if path is None:
+        assert B.PATH_NAMES[st["path"]] == "coop"
+    else:
+        assert B.PATH_NAMES[st["path"]] == "multi"
+        assert st["layout"] == {"sell_uniform": 2, "sell_split": 3}[path]
+    assert st["matvecs"] == int(g["n_matvec"])
+    assert rel(out, g["psi"]) <= PROP_TOL
+
+
+def test_hydrogen_bench_window_vs_oracle():
+    g = golden("hydrogen_t40_dt0.002_30steps.npz")
+    p = I.config_hydrogen()
+    t0, dt, steps = float(g["t0"]), float(g["dt"]), int(g["steps"])
+    assert (t0, dt, steps) == (40.0, 0.002, 30)
+    with B.Propagator(p.H0, p.Hk, p.drives) as P:
+        psi = dev(p.psi0)
+        for c in range(0, steps, 10):       # the benchmark's calls of 10 steps
+            P.propagate(psi, t0 + c * dt, dt, 10, p.scheme, p.m)
+        st = P.stats()
+        out = psi.cpu().numpy()
+    assert st["status"] == 0 and B.PATH_NAMES[st["path"]] == "coop"
+    assert st["matvecs"] == int(g["n_matvec"])
+    assert rel(out, g["psi"]) <= PROP_TOL
+
+
+def test_noninteracting_spins_L24_tensor_product():
+    L, Delta, V, w = 24, 0.5, 0.5, 1.0
+    dt, nsteps, scheme, m = 0.02, 50, "CF6:5Opt", 24
+    T = nsteps * dt
+    H0, Hk, drives = I.noninteracting_spins(L, Delta, V, w)
+    rng = np.random.default_rng(7)
+    sites = []
+    for _ in range(L):
+        v = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        sites.append(v / np.linalg.norm(v))
+    psi0 = I.product_state(sites)
+    with B.Propagator(H0, Hk, drives) as P:
+        assert P.stats()["layout"] == 3
+        psi = dev(psi0)
+        del psi0
+        P.propagate(psi, 0.0, dt, nsteps, scheme, m)
+        st = P.stats()
+        out = psi.cpu().numpy()
+    del psi
+    assert st["status"] == 0
+    h0, hk, dr = I.two_level(Delta, V, w)
+    cfet_sites, exact_sites, site_err = [], [], 0.0
+    for phi in sites:
+        c = O.propagate(h0, hk, dr, phi, 0.0, dt, nsteps, scheme, dense=True)
+        e = two_level_U(T, Delta, V, w) @ phi
+        cfet_sites.append(c)
+        exact_sites.append(e)
+        site_err += np.linalg.norm(c - e)
+    ref = I.product_state(cfet_sites)
+    assert rel(out, ref) <= PROP_TOL
+    del ref
+    exact = I.product_state(exact_sites)
+    # the tensor product's distance from the closed form is at most the sum of
+    # the single-spin scheme errors (first order; factor 2 for the rest)
+    assert np.linalg.norm(out - exact) <= 2.0 * site_err + 1e-10
+    assert site_err < 1e-8
+
+
+def test_diagonal_zero_drive_L24_pure_phase():
+    L = 24
+    n = 1 << L
+    rng = np.random.default_rng(11)
+    E = rng.uniform(-1.0, 1.0, n)
+    H0 = I.diagonal(E)
+    H1 = I.sigma_x_sum(L)
+    drives = [{"kind": "cos", "A": 0.0, "omega": 1.3, "phi": 0.0}]
+    psi0 = I.random_state(n, rng)
+    dt, nsteps = 0.02, 50
+    with B.Propagator(H0, [H1], drives) as P:
+        assert P.stats()["layout"] == 3
+        psi = dev(psi0)
+        P.propagate(psi, 0.0, dt, nsteps, "CF6:5Opt", 24)
+        st = P.stats()
+        out = psi.cpu().numpy()
+    del psi
+    assert st["status"] == 0
+    ref = psi0 * np.exp(-1j * E * (nsteps * dt))
+    assert rel(out, ref) <= 1e-12

@@ -50,7 +50,7 @@ def test_heisenberg_L24_sampled_rows_reversibility_and_norm():
     rng = np.random.default_rng(24)
     with B.Propagator(p.H0, p.Hk, p.drives) as P:
         st = P.stats()
-        assert st["layout"] == 2          # SELL-64 with shared parts, the default here
+        assert st["layout"] == 3          # SELL-64 with shared parts in two passes, the default here
         x = I.random_state(n, rng)
         a, b = 0.83, [-1.7]
         y = P.apply(dev(x), a, b).cpu().numpy()

@@ -20,7 +20,7 @@ torch = pytest.importorskip("torch")
 B = pytest.importorskip("paper_1102_5071_amd.binding")
 
 PROP_TOL = 1e-10
-PATHS = ["multi", "single", "coop", "sell", "sell_uniform"]
+PATHS = ["multi", "single", "coop", "sell", "sell_uniform", "sell_split"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -57,11 +57,32 @@ def run_gpu(prob_H0, Hk, drives, psi0, t0, dt, nsteps, scheme, m, path=None):
         # ("sell", "sell_uniform": the multi-kernel path on the sliced-ELL layouts)
         assert B.PATH_NAMES[st["path"]] in (path, "multi")
         if path.startswith("sell"):
-            assert st["layout"] == (2 if path == "sell_uniform" else 1)
+            # the split layout applies to 2^b rows (b >= 8) whose far entries are shared
+            want = {"sell": (1,), "sell_uniform": (2,), "sell_split": (2, 3)}[path]
+            assert st["layout"] in want
+            if path == "sell_split" and prob_H0.n >= 256 and is_spin_operator(prob_H0, Hk):
+                assert st["layout"] == 3
         if path in ("single", "coop") and prob_H0.n <= 1024:
             assert B.PATH_NAMES[st["path"]] == path
     assert st["status"] == 0, st
     return out, st
+
+
+def is_spin_operator(H0, Hk):
+    """Operators on 2^L rows built from site terms (every column = row XOR a
+    power of two or two adjacent powers, or the diagonal)."""
+    n = H0.n
+    if n & (n - 1):
+        return False
+    for h in [H0] + list(Hk):
+        rows = np.repeat(np.arange(n), np.diff(h.row_ptr))
+        off = rows ^ h.col.astype(np.int64)
+        single = (off & (off - 1)) == 0
+        pair = ((off // 3) & (off // 3 - 1)) == 0
+        pair &= (off % 3 == 0) & (off > 0)
+        if not np.all(single | pair):
+            return False
+    return True
 
 
 def ragged_hermitian(n, seed):
@@ -102,7 +123,7 @@ def heisenberg_principal(L, n, seed):
     return I._dense_to_csr(H0), I._dense_to_csr(H1)
 
 
-@pytest.mark.parametrize("layout", ["multi", "sell", "sell_uniform"])
+@pytest.mark.parametrize("layout", ["multi", "sell", "sell_uniform", "sell_split"])
 @pytest.mark.parametrize("case", ["ising10", "hydrogen_small", "ragged", "two_term", "heis12",
                                   "heis_block"])
 def test_apply_matches_reference(case, layout):

@@ -17,16 +17,7 @@ from scipy.integrate import solve_ivp
 from oracle import cfet as O
 from oracle import schemes as S
 from paper_1102_5071_amd import inputs as I
-
-
-def two_level_U(t, Delta, V, w):
-    """Sec. 6.2, eq. TwoLevelU."""
-    Om = math.sqrt((Delta - w) ** 2 + V ** 2)
-    c, s = math.cos(Om * t), math.sin(Om * t)
-    e = np.exp(-1j * w * t)
-    return np.array([
-        [e * (c - 1j * (Delta - w) / Om * s), -1j * V / Om * e * s],
-        [-1j * V / Om * np.conj(e) * s, np.conj(e) * (c + 1j * (Delta - w) / Om * s)]])
+from tests.closed_forms import two_level_U
 
 
 def _H_of_t(H0, Hk, drives):
