@@ -11,7 +11,7 @@ oracle results and closed forms.
     norm, and projections onto seeded complex Gaussian vectors (each involves
     every entry: for an error vector d, <r|d> has standard deviation
     sqrt(2) ||d||, so |<r|d>| <= 1e-9 says ||d|| is of order 1e-10 or less);
-  - L = 18, the whole 200-step run, on the default path (cooperative kernel)
+  - L = 18, the whole 200-step run, on the default path (multi-kernel, CSR)
     and on the multi-kernel path with both shared layouts: whole final state.
 * Hydrogen on the radial grid: the benchmark's window (t0 = 40, dt = 0.002,
   10 + 20 steps in calls of 10 steps, cooperative kernel).
@@ -125,7 +125,9 @@ def test_heisenberg_L18_200_steps_vs_oracle(path):
         out = psi.cpu().numpy()
     assert st["status"] == 0
     if path is None:
-        assert B.PATH_NAMES[st["path"]] == "coop"
+        # 36 entries per row at 4096 rows per block exceed the cooperative
+        # kernel's register presets: the default is the multi-kernel CSR path
+        assert B.PATH_NAMES[st["path"]] == "multi" and st["layout"] == 0
     else:
         assert B.PATH_NAMES[st["path"]] == "multi"
         assert st["layout"] == {"sell_uniform": 2, "sell_split": 3}[path]
