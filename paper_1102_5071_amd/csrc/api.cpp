@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstddef>
@@ -185,11 +186,13 @@ void free_ctx(cfet_ctx* c) {
   if (c->sell.ucolt) (void)hipFree(c->sell.ucolt);
   if (c->sell.uval) (void)hipFree(c->sell.uval);
   if (c->sell.umask) (void)hipFree(c->sell.umask);
+  if (c->sell.diag) (void)hipFree(c->sell.diag);
   if (c->hi.nuni) (void)hipFree(c->hi.nuni);
   if (c->hi.uptr) (void)hipFree(c->hi.uptr);
   if (c->hi.ucolt) (void)hipFree(c->hi.ucolt);
   if (c->hi.uval) (void)hipFree(c->hi.uval);
   if (c->hi.umask) (void)hipFree(c->hi.umask);
+  if (c->hi.tile_row) (void)hipFree(c->hi.tile_row);
   if (c->basis) (void)hipFree(c->basis);
   if (c->partA) (void)hipFree(c->partA);
   if (c->partB) (void)hipFree(c->partB);
@@ -449,6 +452,8 @@ struct SellStage {
   std::vector<uint32_t> ucol;
   std::vector<double> uval;
   std::vector<uint64_t> umask;
+  std::vector<double> diag;    // extracted diagonal of term diag_term (empty: none)
+  int diag_term = 0;
 };
 
 template <class F>
@@ -577,11 +582,30 @@ void run_threads(int64_t count, unsigned nth, Body body) {
 // Stage the SELL-64 layout of the first pass: all entries, or with split_bit
 // > 0 only the low-offset ones (the others go to the second pass).  Returns
 // false when the host buffers cannot be allocated.
+// With diag_term >= 0 the diagonal entries (all of that term and real) are
+// stored apart, one double per row, and left out of the slots.
 bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
                 const std::vector<int32_t>& rowlen_all, bool uniform, int split_bit,
-                int tbits, unsigned nth, SellStage* S) {
+                int tbits, int diag_term, unsigned nth, SellStage* S) {
   const int64_t nsl = (n + 63) / 64;
-  auto keep = [split_bit](int64_t r, int32_t col) { return low_entry(r, col, split_bit); };
+  const bool xdiag = diag_term >= 0;
+  auto keep = [split_bit, xdiag](int64_t r, int32_t col) {
+    return low_entry(r, col, split_bit) && !(xdiag && int64_t(col) == r);
+  };
+  if (xdiag) {
+    try {
+      S->diag.assign(n, 0.0);
+    } catch (const std::bad_alloc&) {
+      return false;
+    }
+    S->diag_term = diag_term;
+    const HostCSR& h = mats[diag_term];
+    run_threads(n, nth, [&](int64_t r0, int64_t r1) {
+      for (int64_t r = r0; r < r1; ++r)
+        for (int64_t q = h.rp[r]; q < h.rp[r + 1]; ++q)
+          if (int64_t(h.col[q]) == r) S->diag[r] = h.val[2 * q];
+    });
+  }
   try {
     S->sptr.assign(nsl + 1, 0);
     S->swid.assign(nsl, 0);
@@ -593,7 +617,7 @@ bool stage_sell(const std::vector<HostCSR>& mats, int nterms, int64_t n,
   } catch (const std::bad_alloc&) {
     return false;
   }
-  if (split_bit > 0) {
+  if (split_bit > 0 || xdiag) {
     // per-row counts of the first pass's entries
     run_threads(n, nth, [&](int64_t r0, int64_t r1) {
       for (int64_t r = r0; r < r1; ++r) {
@@ -1118,9 +1142,32 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       split = HS.uptr.back() * kSharedMinRows <= sp.high;
       if (!split) HS = SellHiStage();
     }
+    // the tiled kernels take the diagonal apart when it lies in one term and is
+    // real (a disordered field: one value per row)
+    int diag_term = -1;
+    if (split) {
+      std::atomic<int32_t> terms_seen{0};
+      std::atomic<bool> real{true};
+      run_threads(n, nth, [&](int64_t r0, int64_t r1) {
+        int32_t tm = 0;
+        bool good = true;
+        for (int64_t r = r0; r < r1 && good; ++r)
+          for_sell_row(mats, nterms, r, [&](int term, int32_t col, const double* v) {
+            if (int64_t(col) != r) return;
+            tm |= 1 << term;
+            if (v[1] != 0.0) good = false;
+          });
+        terms_seen.fetch_or(tm);
+        if (!good) real.store(false);
+      });
+      const int32_t tm = terms_seen.load();
+      if (real.load() && tm != 0 && (tm & (tm - 1)) == 0)
+        for (int k = 0; k <= nterms; ++k)
+          if (tm == (1 << k)) diag_term = k;
+    }
     SellStage S;
     bool staged = stage_sell(mats, nterms, n, rowlen, uniform, split ? sp.split_bit : 0,
-                             split ? sp.tbits : 0, nth, &S);
+                             split ? sp.tbits : 0, diag_term, nth, &S);
     // compact shared lists; the tiled kernels of the split layout read them in
     // groups of four entries
     if (staged && uniform)
@@ -1153,7 +1200,18 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       e = hipMemcpy(c->sell.val, S.sval.data(), slots * sizeof(double2), hipMemcpyHostToDevice);
     int64_t stored = 0;  // per-row entries actually present (padding excluded)
     for (int64_t r = 0; r < n; ++r) stored += S.rlen[r];
-    c->sell_bytes = 20 * stored + 4 * n + 12 * nsl;
+    // row lengths are read only in slices with per-row slots
+    int64_t rows_with_slots = 0;
+    for (int64_t sl = 0; sl < nsl; ++sl)
+      if (S.swid[sl] > 0) rows_with_slots += std::min<int64_t>(64, n - sl * 64);
+    c->sell_bytes = 20 * stored + 4 * rows_with_slots + 12 * nsl;
+    if (!S.diag.empty()) {
+      if (e == hipSuccess) e = hipMalloc(&c->sell.diag, n * sizeof(double));
+      if (e == hipSuccess)
+        e = hipMemcpy(c->sell.diag, S.diag.data(), n * sizeof(double), hipMemcpyHostToDevice);
+      c->sell.diag_term = S.diag_term;
+      c->sell_bytes += 8 * n;
+    }
     if (uniform) {
       const int64_t us = S.uptr[nsl];
       c->sell.uslots = us;
@@ -1199,6 +1257,15 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
         e = hipMemcpy(c->hi.umask, HS.umask.data(), us * sizeof(uint64_t), hipMemcpyHostToDevice);
       c->sell_bytes += 28 * us + 12 * hsl;
       c->tbits = sp.tbits;
+      {
+        const int64_t ntiles = n >> sp.tbits;
+        std::vector<int64_t> trow(ntiles);
+        for (int64_t t = 0; t < ntiles; ++t) trow[t] = permuted_row(sp, t << sp.tbits);
+        if (e == hipSuccess) e = hipMalloc(&c->hi.tile_row, ntiles * sizeof(int64_t));
+        if (e == hipSuccess)
+          e = hipMemcpy(c->hi.tile_row, trow.data(), ntiles * sizeof(int64_t),
+                        hipMemcpyHostToDevice);
+      }
       bool real = true;
       for (size_t q = 1; q < S.sval.size() && real; q += 2) real = (S.sval[q] == 0.0);
       for (size_t q = 1; q < S.uval.size() && real; q += 2) real = (S.uval[q] == 0.0);

@@ -96,6 +96,11 @@ struct DevSELL {
   double2* uval = nullptr;
   uint64_t* umask = nullptr;
   int64_t uslots = 0;
+  // Optional (split layout only): the diagonal of one term, real-valued, one
+  // double per row (rows without a diagonal entry hold 0); the per-row slots
+  // then leave the diagonal out.
+  double* diag = nullptr;
+  int32_t diag_term = 0;
 };
 
 // Second pass of the split shared-part layout (operators on 2^nbits rows whose
@@ -122,6 +127,8 @@ struct DevSELLHi {
   double2* uval = nullptr;
   uint64_t* umask = nullptr;     // bit l: row of permuted index 64 s + l
   int64_t uslots = 0;
+  int64_t* tile_row = nullptr;   // row of the first index of each tile of 2^tbits
+                                 // permuted indices (the tile's row bits above tbits)
 };
 
 int sell_grid(int64_t n);

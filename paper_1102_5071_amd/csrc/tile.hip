@@ -24,14 +24,27 @@ namespace cfet {
 
 namespace {
 
-constexpr int kTileThreads = 512;  // 8 wavefronts; two workgroups per CU (64 KiB tiles)
-constexpr int kTileWaves = kTileThreads / 64;
-constexpr int kTileLoads = (1 << kTileBitsMax) / kTileThreads;  // tile elements per thread
-// The tile is staged through eight named registers per thread (an array here
-// is kept in scratch memory across the barrier by the compiler).
-static_assert(kTileLoads == 8, "tile staging is written out for eight loads per thread");
+// Two workgroups share a CU (64 KiB tiles in LDS); the block size sets the
+// resident wavefronts: 12 per workgroup for the first pass (its registers
+// allow 6 per SIMD), 16 for the second (8 per SIMD).  More resident
+// wavefronts hide more of each slice's chain of metadata, LDS and gather
+// latencies.
+constexpr int kPass1Threads = 768;
+constexpr int kPass2Threads = 1024;
+constexpr int kMaxTileWaves = 16;
+// tile elements each thread stages (the index is masked into the tile, so a
+// count that does not divide it reads some elements twice)
+template <int THREADS>
+constexpr int tile_loads() {
+  return ((1 << kTileBitsMax) + THREADS - 1) / THREADS;
+}
+// The tile is staged through named registers per thread (an array here is
+// kept in scratch memory across the barrier by the compiler).
+static_assert(tile_loads<kPass1Threads>() <= 8 && tile_loads<kPass2Threads>() <= 8,
+              "tile staging is written out for at most eight loads per thread");
 #define CFET_TILE_8(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7)
-#define CFET_TS(u) xt[((int)threadIdx.x + u * kTileThreads) & (T - 1)] = b##u;
+#define CFET_TS(u) \
+  if constexpr (u < LOADS) xt[((int)threadIdx.x + u * THREADS) & (T - 1)] = b##u;
 constexpr int kTileScratch = 32;   // doubles after the tile: block sums and term weights
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
@@ -42,7 +55,9 @@ __device__ __forceinline__ double t_wave_sum(double v) {
   return v;
 }
 
+template <int WAVES>
 __device__ double t_block_sum(double v, double* red) {
+  static_assert(WAVES <= kMaxTileWaves, "block sums hold 16 wavefronts");
   v = t_wave_sum(v);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   __syncthreads();
@@ -50,17 +65,18 @@ __device__ double t_block_sum(double v, double* red) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int i = 0; i < kTileWaves; ++i) t += red[i];
+    for (int i = 0; i < WAVES; ++i) t += red[i];
     red[16] = t;
   }
   __syncthreads();
   return red[16];
 }
 
+template <int WAVES>
 __device__ double t_sum_partials(const double* __restrict__ part, int np, double* red) {
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
-  return t_block_sum(s, red);
+  return t_block_sum<WAVES>(s, red);
 }
 
 // The layout arrays are not written while the kernels run: reading them
@@ -168,13 +184,14 @@ __device__ __forceinline__ int64_t perm_row(const int32_t* pos, int nbits, int64
 // Finishes the pending norm reduction of Lanczos step j and applies the early
 // stop rule (the contract of the first SpMV launch of a step); returns false
 // when the recurrence has stopped, else 1/||w_j|| in *inv.
+template <int WAVES>
 __device__ bool t_lanczos_start(const double* __restrict__ part_in, int np_in, LzScalars* L,
                                 int j, double* red, double* inv) {
   if (j > 0 && L->brk[j - 1]) {
     if (blockIdx.x == 0 && threadIdx.x == 0) L->brk[j] = 1;
     return false;
   }
-  const double nrm2 = t_sum_partials(part_in, np_in, red);
+  const double nrm2 = t_sum_partials<WAVES>(part_in, np_in, red);
   const bool b0 = (blockIdx.x == 0 && threadIdx.x == 0);
   if (j == 0) {
     const double beta0 = sqrt(nrm2);
@@ -208,8 +225,8 @@ __device__ bool t_lanczos_start(const double* __restrict__ part_in, int np_in, L
 // First pass over tiles of consecutive rows: shared entries (in-tile from
 // LDS, the rest gathered) and per-row slots.  LZ: Lanczos form (scale by
 // inv, partials of Re<v_j, y>); else y = H x.
-template <int NT, bool LZ, bool RV>
-__global__ __launch_bounds__(kTileThreads) void k_tile_pass1(
+template <int NT, bool LZ, bool RV, int THREADS = kPass1Threads>
+__global__ __launch_bounds__(THREADS) void k_tile_pass1(
     DevSELL S, int tbits, TermWeights tw, const double2* __restrict__ x, double2* __restrict__ y,
     const double* __restrict__ part_in, int np_in, double* __restrict__ part_out, LzScalars* L,
     int j) {
@@ -218,7 +235,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass1(
   double* red = reinterpret_cast<double*>(xt + T);
   double* wl = red + 20;
   double inv = 1.0;
-  if (LZ && !t_lanczos_start(part_in, np_in, L, j, red, &inv)) return;
+  constexpr int WAVES = THREADS / 64;
+  constexpr int LOADS = tile_loads<THREADS>();
+  if (LZ && !t_lanczos_start<WAVES>(part_in, np_in, L, j, red, &inv)) return;
   if (threadIdx.x <= kMaxTerms) wl[threadIdx.x] = tw.w[threadIdx.x];
   const Wts W{tw.w[0], tw.w[1], wl};
   const int lane = threadIdx.x & 63;
@@ -231,20 +250,24 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass1(
     const int64_t r0 = tile << tbits;
     // all loads in flight at once; a tile smaller than the block's share
     // (small operators) is read several times over (index masked into it)
-#define CFET_TL(u) const double2 b##u = x[r0 + (((int)threadIdx.x + u * kTileThreads) & (T - 1))];
+#define CFET_TL(u)   \
+  double2 b##u;      \
+  if constexpr (u < LOADS) b##u = x[r0 + (((int)threadIdx.x + u * THREADS) & (T - 1))];
     CFET_TILE_8(CFET_TL)
 #undef CFET_TL
     __syncthreads();  // the previous tile's readers are done (and wl is set)
     CFET_TILE_8(CFET_TS)
     __syncthreads();
-    for (int sl = wave; sl < (T >> 6); sl += kTileWaves) {
+    for (int sl = wave; sl < (T >> 6); sl += WAVES) {
       const int qloc = sl * 64 + lane;
       const int64_t row = r0 + qloc;
       const int64_t slice = (r0 >> 6) + sl;
       double ar = 0.0, ai = 0.0;
-      // the row's first per-row slot is read before the shared entries, so
-      // its latency overlaps them
-      const int len = S.rowlen[row];
+      // per-row data (diagonal, first per-row slot) is read before the shared
+      // entries, so its latency overlaps them
+      const double d = S.diag ? __builtin_nontemporal_load(S.diag + row) : 0.0;
+      const int width = as_const(S.slice_width)[slice];
+      const int len = width > 0 ? S.rowlen[row] : 0;
       const int64_t base = as_const(S.slice_ptr)[slice];
       const uint32_t* __restrict__ cp = S.colt + base + lane;
       const dvec2* __restrict__ vp = reinterpret_cast<const dvec2*>(S.val) + base + lane;
@@ -273,6 +296,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass1(
         const double2 xv = ((col >> tbits) == (row >> tbits)) ? xt[col & tmask] : x[col];
         t_acc<NT, RV>(ct, v, xv, W, ar, ai);
       }
+      if (S.diag) {
+        const uint32_t dt = (uint32_t)S.diag_term << kTermShift;
+        t_acc<NT, true>(dt, dvec2{d, 0.0}, xt[qloc], W, ar, ai);
+      }
       if (LZ) {
         ar *= inv;
         ai *= inv;
@@ -285,15 +312,15 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass1(
     }
   }
   if (LZ) {
-    apart = t_block_sum(apart, red);
+    apart = t_block_sum<WAVES>(apart, red);
     if (threadIdx.x == 0) part_out[blockIdx.x] = apart;
   }
 }
 
 // Second pass over tiles of the permuted order (every offset inside the tile):
 // y[row] += H_hi x.  LZ: Lanczos form (state of the first pass, partials).
-template <int NT, bool LZ, bool RV>
-__global__ __launch_bounds__(kTileThreads) void k_tile_pass2(
+template <int NT, bool LZ, bool RV, int THREADS = kPass2Threads>
+__global__ __launch_bounds__(THREADS) void k_tile_pass2(
     DevSELLHi H, int tbits, TermWeights tw, const double2* __restrict__ x,
     double2* __restrict__ y, double* __restrict__ part_out, const LzScalars* L, int j) {
   extern __shared__ double2 xt[];
@@ -301,6 +328,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass2(
   double* red = reinterpret_cast<double*>(xt + T);
   double* wl = red + 20;
   double inv = 1.0;
+  constexpr int WAVES = THREADS / 64;
+  constexpr int LOADS = tile_loads<THREADS>();
   if (LZ) {
     if (L->brk[j]) return;
     inv = L->inv_nrm[j];
@@ -314,7 +343,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass2(
   // row bits (inside a tile) of the indices this thread loads and of this
   // lane inside a slice: the same for every tile
 #define CFET_LOC(u) \
-  const int64_t loc##u = perm_row<kTileBitsMax>(H.pos, tbits, ((int)threadIdx.x + u * kTileThreads) & (T - 1));
+  const int64_t loc##u = perm_row<kTileBitsMax>(H.pos, tbits, ((int)threadIdx.x + u * THREADS) & (T - 1));
   CFET_TILE_8(CFET_LOC)
 #undef CFET_LOC
   const int64_t lane_bits = perm_row<6>(H.pos, 6, lane);
@@ -322,18 +351,26 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass2(
   double apart = 0.0;
   for (int64_t tile = R.first; tile < R.end; tile += R.stride) {
     const int64_t q0 = tile << tbits;
-    const int64_t rbase = perm_row<32>(H.pos, H.nbits, q0);
-#define CFET_TL(u) const double2 b##u = x[rbase | loc##u];
+    const int64_t rbase = as_const(H.tile_row)[tile];
+#define CFET_TL(u) \
+  double2 b##u;    \
+  if constexpr (u < LOADS) b##u = x[rbase | loc##u];
     CFET_TILE_8(CFET_TL)
 #undef CFET_TL
     __syncthreads();
     CFET_TILE_8(CFET_TS)
     __syncthreads();
-    for (int sl = wave; sl < (T >> 6); sl += kTileWaves) {
+    for (int sl = wave; sl < (T >> 6); sl += WAVES) {
       const int qloc = sl * 64 + lane;
       const int64_t slice = (q0 >> 6) + sl;
-      const int64_t row = rbase | perm_row<kTileBitsMax>(H.pos, tbits, (int64_t)sl * 64) | lane_bits;
+      int64_t srow = 0;  // row bits of the slice inside the tile (bits 6 .. tbits-1)
+      for (int b = 6; b < tbits; ++b) srow |= (int64_t)((sl >> (b - 6)) & 1) << H.pos[b];
+      const int64_t row = rbase | srow | lane_bits;
       double ar = 0.0, ai = 0.0;
+      // the first pass's part of y is read before the entries (latency overlap)
+      dvec2 y1 = dvec2{0.0, 0.0};
+      if (LZ && y) y1 = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(y) + row);
+      else if (!LZ) y1 = dvec2{y[row].x, y[row].y};
       const int nu = as_const(H.nuni)[slice];
       if (nu > 0) {
         const int64_t ub = as_const(H.uptr)[slice];
@@ -345,21 +382,18 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass2(
       if (LZ) {
         ar *= inv;
         ai *= inv;
-        if (y) {
-          const dvec2 y1 = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(y) + row);
+        if (y)
           __builtin_nontemporal_store(dvec2{y1.x + ar, y1.y + ai},
                                       reinterpret_cast<dvec2*>(y) + row);
-        }
         const double2 xr = xt[qloc];
         apart += (xr.x * ar + xr.y * ai) * inv;
       } else {
-        const double2 y1 = y[row];
         y[row] = make_double2(y1.x + ar, y1.y + ai);
       }
     }
   }
   if (LZ) {
-    apart = t_block_sum(apart, red);
+    apart = t_block_sum<WAVES>(apart, red);
     if (threadIdx.x == 0) part_out[blockIdx.x] = apart;
   }
 }
@@ -388,9 +422,9 @@ void launch_lz(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, const Te
                const double2* x, double2* y, const double* pin, int npin, double* pout,
                LzScalars* L, int j, hipStream_t st) {
   const size_t lds = tile_lds_bytes(tbits);
-  hipLaunchKernelGGL((k_tile_pass1<NT, true, RV>), dim3(nb), dim3(kTileThreads), lds, st, S,
+  hipLaunchKernelGGL((k_tile_pass1<NT, true, RV>), dim3(nb), dim3(kPass1Threads), lds, st, S,
                      tbits, tw, x, y, pin, npin, pout, L, j);
-  hipLaunchKernelGGL((k_tile_pass2<NT, true, RV>), dim3(nb), dim3(kTileThreads), lds, st, H,
+  hipLaunchKernelGGL((k_tile_pass2<NT, true, RV>), dim3(nb), dim3(kPass2Threads), lds, st, H,
                      tbits, tw, x, y, pout + nb, L, j);
 }
 
@@ -398,9 +432,9 @@ template <int NT>
 void launch_ap(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, const TermWeights& tw,
                const double2* x, double2* y, hipStream_t st) {
   const size_t lds = tile_lds_bytes(tbits);
-  hipLaunchKernelGGL((k_tile_pass1<NT, false, false>), dim3(nb), dim3(kTileThreads), lds, st, S,
+  hipLaunchKernelGGL((k_tile_pass1<NT, false, false>), dim3(nb), dim3(kPass1Threads), lds, st, S,
                      tbits, tw, x, y, nullptr, 0, nullptr, nullptr, 0);
-  hipLaunchKernelGGL((k_tile_pass2<NT, false, false>), dim3(nb), dim3(kTileThreads), lds, st, H,
+  hipLaunchKernelGGL((k_tile_pass2<NT, false, false>), dim3(nb), dim3(kPass2Threads), lds, st, H,
                      tbits, tw, x, y, nullptr, nullptr, 0);
 }
 
