@@ -187,6 +187,8 @@ void free_ctx(cfet_ctx* c) {
   if (c->sell.uval) (void)hipFree(c->sell.uval);
   if (c->sell.umask) (void)hipFree(c->sell.umask);
   if (c->sell.diag) (void)hipFree(c->sell.diag);
+  if (c->sell.ugroups) (void)hipFree(c->sell.ugroups);
+  if (c->hi.ugroups) (void)hipFree(c->hi.ugroups);
   if (c->hi.nuni) (void)hipFree(c->hi.nuni);
   if (c->hi.uptr) (void)hipFree(c->hi.uptr);
   if (c->hi.ucolt) (void)hipFree(c->hi.ucolt);
@@ -788,6 +790,70 @@ bool compact_shared_lists(int64_t nsl, int pad, std::vector<int32_t>* nuni,
   return true;
 }
 
+// Shared lists of the tiled kernels: each slice's list is arranged in four
+// groups -- entries of the driven terms held by all 64 rows, the other
+// driven-term entries, then the same two for H0 -- each keeping the order it
+// had (entries reaching outside the tile first) and padded to a multiple of
+// four with entries that add nothing (value 0; mask all rows in the
+// all-rows groups, no row in the others).  groups[s] packs the four padded
+// counts in 16 bits each (group g at bits 16 g).  Returns false when a group
+// would not fit 16 bits or memory runs out.
+bool arrange_tiled_lists(int64_t nsl, std::vector<int32_t>* nuni, std::vector<int64_t>* uptr,
+                         std::vector<uint32_t>* ucol, std::vector<double>* uval,
+                         std::vector<uint64_t>* umask, std::vector<uint64_t>* groups) {
+  std::vector<uint32_t> oc;
+  std::vector<double> ov;
+  std::vector<uint64_t> om;
+  std::vector<int64_t> optr;
+  try {
+    optr.assign(nsl + 1, 0);
+    groups->assign(nsl, 0);
+    oc.reserve(ucol->size() + 16 * nsl);
+    ov.reserve(uval->size() + 32 * nsl);
+    om.reserve(umask->size() + 16 * nsl);
+  } catch (const std::bad_alloc&) {
+    return false;
+  }
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    const int64_t b = (*uptr)[sl];
+    const int cnt = (*nuni)[sl];
+    optr[sl] = int64_t(oc.size());
+    uint64_t packed = 0;
+    for (int g = 0; g < 4; ++g) {
+      const bool driven = g < 2, full = (g % 2) == 0;
+      int64_t taken = 0;
+      for (int i = 0; i < cnt; ++i) {
+        const uint32_t ct = (*ucol)[b + i];
+        const uint64_t m = (*umask)[b + i];
+        if (((ct >> cfet::kTermShift) != 0) != driven || (m == ~0ull) != full) continue;
+        oc.push_back(ct);
+        ov.push_back((*uval)[2 * (b + i)]);
+        ov.push_back((*uval)[2 * (b + i) + 1]);
+        om.push_back(m);
+        ++taken;
+      }
+      const uint32_t pad_term = driven ? (1u << cfet::kTermShift) : 0u;
+      while (taken % 4) {
+        oc.push_back(pad_term);
+        ov.push_back(0.0);
+        ov.push_back(0.0);
+        om.push_back(full ? ~0ull : 0ull);
+        ++taken;
+      }
+      if (taken >= 65536) return false;
+      packed |= uint64_t(taken) << (16 * g);
+    }
+    (*groups)[sl] = packed;
+    (*nuni)[sl] = int32_t(int64_t(oc.size()) - optr[sl]);
+  }
+  optr[nsl] = int64_t(oc.size());
+  ucol->swap(oc);
+  uval->swap(ov);
+  umask->swap(om);
+  uptr->swap(optr);
+  return true;
+}
+
 // Split of the shared-part layout into two passes (see DevSELLHi).  Applies to
 // operators on 2^nbits rows (nbits >= 8): entries whose offset row ^ col has a
 // bit at or above split_bit = min(16, nbits - 2) leave the first pass, whose
@@ -1170,11 +1236,15 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
                              split ? sp.tbits : 0, diag_term, nth, &S);
     // compact shared lists; the tiled kernels of the split layout read them in
     // groups of four entries
-    if (staged && uniform)
-      staged = compact_shared_lists(nsl, split ? 4 : 1, &S.nuni, &S.uptr, &S.ucol, &S.uval,
-                                    &S.umask);
+    std::vector<uint64_t> groups1, groups2;
     if (staged && split)
-      staged = compact_shared_lists(n / 64, 4, &HS.nuni, &HS.uptr, &HS.ucol, &HS.uval, &HS.umask);
+      staged = arrange_tiled_lists(nsl, &S.nuni, &S.uptr, &S.ucol, &S.uval, &S.umask, &groups1) &&
+               arrange_tiled_lists(n / 64, &HS.nuni, &HS.uptr, &HS.ucol, &HS.uval, &HS.umask,
+                                   &groups2);
+    if (staged && uniform)
+      staged = compact_shared_lists(nsl, 1, &S.nuni, &S.uptr, &S.ucol, &S.uval, &S.umask);
+    if (staged && split)
+      staged = compact_shared_lists(n / 64, 1, &HS.nuni, &HS.uptr, &HS.ucol, &HS.uval, &HS.umask);
     if (!staged) {
       rc = fail(c, CFET_ENOMEM, "cannot stage the SELL matrix on the host");
       free_ctx(c);
@@ -1231,6 +1301,17 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       if (e == hipSuccess && us)
         e = hipMemcpy(c->sell.umask, S.umask.data(), us * sizeof(uint64_t), hipMemcpyHostToDevice);
       c->sell_bytes += 28 * us + 12 * nsl;
+    }
+    if (split) {
+      if (e == hipSuccess) e = hipMalloc(&c->sell.ugroups, nsl * sizeof(uint64_t));
+      if (e == hipSuccess)
+        e = hipMemcpy(c->sell.ugroups, groups1.data(), nsl * sizeof(uint64_t),
+                      hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMalloc(&c->hi.ugroups, (n / 64) * sizeof(uint64_t));
+      if (e == hipSuccess)
+        e = hipMemcpy(c->hi.ugroups, groups2.data(), (n / 64) * sizeof(uint64_t),
+                      hipMemcpyHostToDevice);
+      c->sell_bytes += 8 * nsl + 8 * (n / 64);
     }
     if (split) {
       const int64_t hsl = n / 64;

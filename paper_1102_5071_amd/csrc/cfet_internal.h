@@ -101,6 +101,10 @@ struct DevSELL {
   // then leave the diagonal out.
   double* diag = nullptr;
   int32_t diag_term = 0;
+  // Split layout only: per slice the padded sizes of its four list groups
+  // (driven terms held by all rows / by some rows, H0 all / some), 16 bits
+  // each, group g at bits 16 g.
+  uint64_t* ugroups = nullptr;
 };
 
 // Second pass of the split shared-part layout (operators on 2^nbits rows whose
@@ -127,6 +131,7 @@ struct DevSELLHi {
   double2* uval = nullptr;
   uint64_t* umask = nullptr;     // bit l: row of permuted index 64 s + l
   int64_t uslots = 0;
+  uint64_t* ugroups = nullptr;   // per slice the four group sizes, as in DevSELL
   int64_t* tile_row = nullptr;   // row of the first index of each tile of 2^tbits
                                  // permuted indices (the tile's row bits above tbits)
 };

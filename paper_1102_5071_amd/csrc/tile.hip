@@ -112,41 +112,101 @@ __device__ __forceinline__ void t_acc(uint32_t ct, dvec2 v, double2 xv, const Wt
   }
 }
 
-// Shared entries of one slice (count nu, a multiple of four: the lists of
-// this layout are padded with entries no row holds; first at uc/uv/um) for the
-// lane with tile-local index qloc, row `row` and mask bit lanebit.  Offsets up
-// to tmask read the tile in LDS at qloc ^ offset; larger ones (GLOBAL: only
-// the first pass, identity order) gather x[row ^ offset] -- they are stored
-// first, so the first group of a slice issues its gathers before its LDS
-// reads.  The metadata of four entries is read (scalar loads) before any of
-// it is used: one latency per group.
-template <int NT, bool RV, bool GLOBAL>
-__device__ __forceinline__ void t_shared(const CFET_CONST uint32_t* uc, const CFET_CONST dvec2* uv,
-                                         const CFET_CONST uint64_t* um, int nu,
-                                         uint64_t lanebit, int qloc, int64_t row, uint32_t tmask,
-                                         const double2* xt, const double2* __restrict__ x,
-                                         const Wts& W, double& ar, double& ai) {
-  for (int k = 0; k < nu; k += 4) {
-    uint32_t ct[4];
+// x of the tile-local index (qb ^ ob) / 16: qb = 16 qloc, ob = 16 offset
+// (byte offsets; the mask keeps the read inside the tile)
+__device__ __forceinline__ double2 t_lds(const double2* xt, uint32_t qb, uint32_t ob,
+                                         uint32_t tmask16) {
+  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(xt) +
+                                           ((qb ^ ob) & tmask16));
+}
+
+// One group of a slice's shared entries (count cnt, a multiple of four) into
+// (ar, ai) without weights.  FULL: every row holds every entry (no lane test).
+// Offsets up to tmask read the tile in LDS; larger ones (GLOBAL: first pass,
+// identity order) gather x[row ^ offset].  The metadata of four entries is
+// read (scalar loads) before any of it is used: one latency per four.
+template <bool FULL, bool RV, bool GLOBAL>
+__device__ __forceinline__ void t_group(const CFET_CONST uint32_t* uc, const CFET_CONST dvec2* uv,
+                                        const CFET_CONST uint64_t* um, int k0, int cnt,
+                                        uint64_t lanebit, uint32_t qb, int64_t row,
+                                        uint32_t tmask, const double2* xt,
+                                        const double2* __restrict__ x, double& ar, double& ai) {
+  const uint32_t tmask16 = (tmask << 4) | 15u;
+  for (int k = k0; k < k0 + cnt; k += 4) {
+    uint32_t off[4];
     uint64_t m[4];
     dvec2 v[4];
     double2 xv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      ct[u] = uc[k + u];
-      m[u] = um[k + u];
+      off[u] = uc[k + u] & kColMask;
+      m[u] = FULL ? ~0ull : um[k + u];
       v[u].x = uv[k + u].x;
       v[u].y = RV ? 0.0 : uv[k + u].y;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const uint32_t off = ct[u] & kColMask;
-      if (GLOBAL && off > tmask) xv[u] = x[(m[u] & lanebit) ? row ^ (int64_t)off : row];
-      else xv[u] = xt[(qloc ^ (int)off) & (int)tmask];
+      if (GLOBAL && off[u] > tmask)
+        xv[u] = x[(FULL || (m[u] & lanebit)) ? row ^ (int64_t)off[u] : row];
+      else
+        xv[u] = t_lds(xt, qb, off[u] << 4, tmask16);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (m[u] & lanebit) t_acc<NT, RV>(ct[u], v[u], xv[u], W, ar, ai);
+    for (int u = 0; u < 4; ++u) {
+      if (FULL || (m[u] & lanebit)) {
+        if (RV) {
+          ar = fma(v[u].x, xv[u].x, ar);
+          ai = fma(v[u].x, xv[u].y, ai);
+        } else {
+          ar = fma(v[u].x, xv[u].x, fma(-v[u].y, xv[u].y, ar));
+          ai = fma(v[u].x, xv[u].y, fma(v[u].y, xv[u].x, ai));
+        }
+      }
+    }
+  }
+}
+
+// Unweighted sums of a slice's shared entries, by term: (a0r, a0i) over H0's
+// entries, (a1r, a1i) over the driven term's (one driven term: NT = 1).
+template <bool RV, bool GLOBAL>
+__device__ __forceinline__ void t_shared_nt1(const CFET_CONST uint32_t* uc,
+                                             const CFET_CONST dvec2* uv,
+                                             const CFET_CONST uint64_t* um, uint64_t groups,
+                                             uint64_t lanebit, uint32_t qb, int64_t row,
+                                             uint32_t tmask, const double2* xt,
+                                             const double2* __restrict__ x, double& a0r,
+                                             double& a0i, double& a1r, double& a1i) {
+  const int c0 = (int)(groups & 0xFFFF), c1 = (int)((groups >> 16) & 0xFFFF);
+  const int c2 = (int)((groups >> 32) & 0xFFFF), c3 = (int)(groups >> 48);
+  t_group<true, RV, GLOBAL>(uc, uv, um, 0, c0, lanebit, qb, row, tmask, xt, x, a1r, a1i);
+  t_group<false, RV, GLOBAL>(uc, uv, um, c0, c1, lanebit, qb, row, tmask, xt, x, a1r, a1i);
+  t_group<true, RV, GLOBAL>(uc, uv, um, c0 + c1, c2, lanebit, qb, row, tmask, xt, x, a0r, a0i);
+  t_group<false, RV, GLOBAL>(uc, uv, um, c0 + c1 + c2, c3, lanebit, qb, row, tmask, xt, x, a0r,
+                             a0i);
+}
+
+// Weighted sum of a slice's shared entries, any number of driven terms (the
+// weight of each entry's term from the LDS table): (ar, ai) += w v x.
+template <bool RV, bool GLOBAL>
+__device__ __forceinline__ void t_shared_any(const CFET_CONST uint32_t* uc,
+                                             const CFET_CONST dvec2* uv,
+                                             const CFET_CONST uint64_t* um, int nu,
+                                             uint64_t lanebit, uint32_t qb, int64_t row,
+                                             uint32_t tmask, const double2* xt,
+                                             const double2* __restrict__ x, const double* wl,
+                                             double& ar, double& ai) {
+  const uint32_t tmask16 = (tmask << 4) | 15u;
+  for (int k = 0; k < nu; ++k) {
+    const uint32_t ct = uc[k];
+    const uint32_t off = ct & kColMask;
+    const uint64_t m = um[k];
+    if (!(m & lanebit)) continue;
+    const double2 xv = (GLOBAL && off > tmask) ? x[row ^ (int64_t)off]
+                                               : t_lds(xt, qb, off << 4, tmask16);
+    const double w = wl[ct >> kTermShift];
+    const double er = w * uv[k].x, ei = RV ? 0.0 : w * uv[k].y;
+    ar = fma(er, xv.x, fma(-ei, xv.y, ar));
+    ai = fma(er, xv.y, fma(ei, xv.x, ai));
   }
 }
 
@@ -262,7 +322,6 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
       const int qloc = sl * 64 + lane;
       const int64_t row = r0 + qloc;
       const int64_t slice = (r0 >> 6) + sl;
-      double ar = 0.0, ai = 0.0;
       // per-row data (diagonal, first per-row slot) is read before the shared
       // entries, so its latency overlaps them
       const double d = S.diag ? __builtin_nontemporal_load(S.diag + row) : 0.0;
@@ -277,13 +336,20 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
         ct0 = __builtin_nontemporal_load(cp);
         v0 = __builtin_nontemporal_load(vp);
       }
+      const uint32_t qb = (uint32_t)qloc << 4;
+      double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;  // unweighted, by term (NT = 1)
+      double ar = 0.0, ai = 0.0;                          // weighted
       const int nu = as_const(S.nuni)[slice];
       if (nu > 0) {
         const int64_t ub = as_const(S.uptr)[slice];
-        t_shared<NT, RV, true>(as_const(S.ucolt + ub),
-                               as_const(reinterpret_cast<const dvec2*>(S.uval) + ub),
-                               as_const(S.umask + ub), nu, lanebit, qloc, row, tmask, xt, x, W,
-                               ar, ai);
+        const CFET_CONST uint32_t* uc = as_const(S.ucolt + ub);
+        const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(S.uval) + ub);
+        const CFET_CONST uint64_t* um = as_const(S.umask + ub);
+        if (NT == 1)
+          t_shared_nt1<RV, true>(uc, uv, um, as_const(S.ugroups)[slice], lanebit, qb, row, tmask,
+                                 xt, x, a0r, a0i, a1r, a1i);
+        else
+          t_shared_any<RV, true>(uc, uv, um, nu, lanebit, qb, row, tmask, xt, x, wl, ar, ai);
       }
       for (int k = 0; k < len; ++k) {
         uint32_t ct = ct0;
@@ -299,6 +365,10 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
       if (S.diag) {
         const uint32_t dt = (uint32_t)S.diag_term << kTermShift;
         t_acc<NT, true>(dt, dvec2{d, 0.0}, xt[qloc], W, ar, ai);
+      }
+      if (NT == 1) {
+        ar += W.w0 * a0r + W.w1 * a1r;
+        ai += W.w0 * a0i + W.w1 * a1i;
       }
       if (LZ) {
         ar *= inv;
@@ -366,18 +436,27 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass2(
       int64_t srow = 0;  // row bits of the slice inside the tile (bits 6 .. tbits-1)
       for (int b = 6; b < tbits; ++b) srow |= (int64_t)((sl >> (b - 6)) & 1) << H.pos[b];
       const int64_t row = rbase | srow | lane_bits;
-      double ar = 0.0, ai = 0.0;
       // the first pass's part of y is read before the entries (latency overlap)
       dvec2 y1 = dvec2{0.0, 0.0};
       if (LZ && y) y1 = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(y) + row);
       else if (!LZ) y1 = dvec2{y[row].x, y[row].y};
+      const uint32_t qb = (uint32_t)qloc << 4;
+      double ar = 0.0, ai = 0.0;
       const int nu = as_const(H.nuni)[slice];
       if (nu > 0) {
         const int64_t ub = as_const(H.uptr)[slice];
-        t_shared<NT, RV, false>(as_const(H.ucolt + ub),
-                                as_const(reinterpret_cast<const dvec2*>(H.uval) + ub),
-                                as_const(H.umask + ub), nu, lanebit, qloc, row, tmask, xt, x, W,
-                                ar, ai);
+        const CFET_CONST uint32_t* uc = as_const(H.ucolt + ub);
+        const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(H.uval) + ub);
+        const CFET_CONST uint64_t* um = as_const(H.umask + ub);
+        if (NT == 1) {
+          double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+          t_shared_nt1<RV, false>(uc, uv, um, as_const(H.ugroups)[slice], lanebit, qb, row,
+                                  tmask, xt, x, a0r, a0i, a1r, a1i);
+          ar = W.w0 * a0r + W.w1 * a1r;
+          ai = W.w0 * a0i + W.w1 * a1i;
+        } else {
+          t_shared_any<RV, false>(uc, uv, um, nu, lanebit, qb, row, tmask, xt, x, wl, ar, ai);
+        }
       }
       if (LZ) {
         ar *= inv;
