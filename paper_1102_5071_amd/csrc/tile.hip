@@ -390,7 +390,7 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
 // Second pass over tiles of the permuted order (every offset inside the tile):
 // y[row] += H_hi x.  LZ: Lanczos form (state of the first pass, partials).
 template <int NT, bool LZ, bool RV, int THREADS = kPass2Threads>
-__global__ __launch_bounds__(THREADS) void k_tile_pass2(
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tile_pass2(
     DevSELLHi H, int tbits, TermWeights tw, const double2* __restrict__ x,
     double2* __restrict__ y, double* __restrict__ part_out, const LzScalars* L, int j) {
   extern __shared__ double2 xt[];
@@ -430,16 +430,29 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass2(
     __syncthreads();
     CFET_TILE_8(CFET_TS)
     __syncthreads();
+    // row of this lane in slice sl of the tile
+    auto slice_row = [&](int sl) {
+      int64_t srow = 0;  // row bits of the slice inside the tile (bits 6 .. tbits-1)
+      for (int b = 6; b < tbits; ++b) srow |= (int64_t)((sl >> (b - 6)) & 1) << H.pos[b];
+      return rbase | srow | lane_bits;
+    };
+    // the first pass's part of y is read one slice ahead (latency overlap)
+    dvec2 y1n = dvec2{0.0, 0.0};
+    if (wave < (T >> 6) && (!LZ || y)) {
+      const int64_t r = slice_row(wave);
+      y1n = LZ ? __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(y) + r)
+               : dvec2{y[r].x, y[r].y};
+    }
     for (int sl = wave; sl < (T >> 6); sl += WAVES) {
       const int qloc = sl * 64 + lane;
       const int64_t slice = (q0 >> 6) + sl;
-      int64_t srow = 0;  // row bits of the slice inside the tile (bits 6 .. tbits-1)
-      for (int b = 6; b < tbits; ++b) srow |= (int64_t)((sl >> (b - 6)) & 1) << H.pos[b];
-      const int64_t row = rbase | srow | lane_bits;
-      // the first pass's part of y is read before the entries (latency overlap)
-      dvec2 y1 = dvec2{0.0, 0.0};
-      if (LZ && y) y1 = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(y) + row);
-      else if (!LZ) y1 = dvec2{y[row].x, y[row].y};
+      const int64_t row = slice_row(sl);
+      const dvec2 y1 = y1n;
+      if (sl + WAVES < (T >> 6) && (!LZ || y)) {
+        const int64_t r = slice_row(sl + WAVES);
+        y1n = LZ ? __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(y) + r)
+                 : dvec2{y[r].x, y[r].y};
+      }
       const uint32_t qb = (uint32_t)qloc << 4;
       double ar = 0.0, ai = 0.0;
       const int nu = as_const(H.nuni)[slice];
