@@ -318,13 +318,18 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
     __syncthreads();  // the previous tile's readers are done (and wl is set)
     CFET_TILE_8(CFET_TS)
     __syncthreads();
+    // the diagonal is read one slice ahead (latency overlap)
+    double dn = (S.diag && wave < (T >> 6)) ? __builtin_nontemporal_load(S.diag + r0 + wave * 64 + lane)
+                                            : 0.0;
     for (int sl = wave; sl < (T >> 6); sl += WAVES) {
       const int qloc = sl * 64 + lane;
       const int64_t row = r0 + qloc;
       const int64_t slice = (r0 >> 6) + sl;
-      // per-row data (diagonal, first per-row slot) is read before the shared
-      // entries, so its latency overlaps them
-      const double d = S.diag ? __builtin_nontemporal_load(S.diag + row) : 0.0;
+      const double d = dn;
+      if (S.diag && sl + WAVES < (T >> 6))
+        dn = __builtin_nontemporal_load(S.diag + row + WAVES * 64);
+      // the first per-row slot is read before the shared entries, so its
+      // latency overlaps them
       const int width = as_const(S.slice_width)[slice];
       const int len = width > 0 ? S.rowlen[row] : 0;
       const int64_t base = as_const(S.slice_ptr)[slice];
