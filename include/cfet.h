@@ -209,6 +209,25 @@ CFET_API int cfet_create(const cfet_csr *H0, int32_t nterms, const cfet_csr *Hk,
 CFET_API int cfet_propagate(cfet_ctx *c, void *psi_dev, double t0, double dt, int64_t nsteps,
                             int32_t scheme, int32_t krylov_m, void *hip_stream);
 
+/* cfet_propagate for callers that cannot allocate device memory during the
+ * call: code being captured into a HIP graph, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments, same result as cfet_propagate on
+ * the multi-kernel path (CFET_FORCE_MULTIKERNEL), which it always takes; it
+ * calls no hipMalloc/hipFree and allocates no host memory.  Its Krylov basis,
+ * partial sums, Lanczos scalars and (for reordered operators) the state in the
+ * stored row order live in a fixed 64 MiB device array of the library, one
+ * per GPU, set up by the first cfet_create on that GPU and held until the
+ * process ends: it needs
+ *     (m - 1) n 16 bytes + (reordered: n 16) + about 100 KiB <= 64 MiB
+ * (m = min(krylov_m, n)) and returns CFET_EINVAL with a message otherwise,
+ * before enqueueing anything.  The array is shared by every call on a GPU
+ * (and keeps the last call's contents): calls that overlap on one GPU --
+ * concurrent streams, several threads, several contexts -- race and must be
+ * serialised by the caller. */
+CFET_API int cfet_propagate_static(cfet_ctx *c, void *psi_dev, double t0, double dt,
+                                   int64_t nsteps, int32_t scheme, int32_t krylov_m,
+                                   void *hip_stream);
+
 /* Gradient of the final-state fidelity F = |<target|psi_N>|^2, psi_N the
  * state after nsteps CFET steps from psi0 (exactly the map of cfet_propagate:
  * same scheme, time grid and Lanczos exponentials with krylov_m vectors), with

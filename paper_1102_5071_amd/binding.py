@@ -96,6 +96,8 @@ def load():
                                 POINTER(c_void_p)]
     lib.cfet_propagate.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int64, c_int32,
                                    c_int32, c_void_p]
+    lib.cfet_propagate_static.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int64,
+                                          c_int32, c_int32, c_void_p]
     lib.cfet_gradient.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_double, c_int64,
                                   c_int32, c_int32, c_void_p, c_int32, POINTER(c_double),
                                   c_void_p, c_void_p]
@@ -118,7 +120,7 @@ def load():
     lib.cfet_batch_destroy.argtypes = [c_void_p]
     lib.cfet_batch_last_error.restype = ctypes.c_char_p
     lib.cfet_batch_last_error.argtypes = [c_void_p]
-    for name in ("cfet_create", "cfet_propagate", "cfet_gradient", "cfet_apply", "cfet_stats",
+    for name in ("cfet_create", "cfet_propagate", "cfet_propagate_static", "cfet_gradient", "cfet_apply", "cfet_stats",
                  "cfet_destroy", "cfet_scheme_info", "cfet_step_weights", "cfet_tridiag_expm",
                  "cfet_profile", "cfet_batch_create", "cfet_batch_propagate", "cfet_batch_stats",
                  "cfet_batch_instance_matvecs", "cfet_batch_destroy"):
@@ -230,6 +232,16 @@ class Propagator:
         _check(load().cfet_propagate(self._ctx, c_void_p(psi.data_ptr()), float(t0), float(dt),
                                      int(nsteps), scheme_id(scheme), int(m),
                                      _stream_handle(stream)), self._ctx)
+        return psi
+
+    def propagate_static(self, psi, t0: float, dt: float, nsteps: int, scheme, m: int,
+                         stream=None):
+        """cfet_propagate_static: the multi-kernel propagation with the library's
+        fixed device scratch (no allocation during the call)."""
+        self._check_vec(psi)
+        _check(load().cfet_propagate_static(self._ctx, c_void_p(psi.data_ptr()), float(t0),
+                                            float(dt), int(nsteps), scheme_id(scheme), int(m),
+                                            _stream_handle(stream)), self._ctx)
         return psi
 
     def apply(self, x, a: float, b, y=None, stream=None):

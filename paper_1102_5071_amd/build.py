@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcfet.so")
 
 SOURCES = ["device.hip", "persistent.hip", "sell.hip", "tile.hip", "batch.hip", "grad.hip", "api.cpp", "schemes.cpp",
-           "host_common.cpp", "batch_api.cpp"]
+           "host_common.cpp", "batch_api.cpp", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

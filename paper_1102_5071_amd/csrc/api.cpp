@@ -1390,6 +1390,13 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       if (c->coop_blocks == 0) c->preset_coop = -1;
     }
   }
+  // set up this device's scratch of cfet_propagate_static (first context on
+  // the device only): the runtime materialises the array here, not in a call
+  // that must not allocate
+  if (e == hipSuccess) {
+    void* scratch_ptr = nullptr;
+    e = cfet::static_scratch(c->device, &scratch_ptr);
+  }
   if (e == hipSuccess) e = cfet::launch_stats_init(c->stats, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -1487,6 +1494,59 @@ int cfet_apply(cfet_ctx* c, const void* x_dev, void* y_dev, double a, const doub
 
 namespace {
 
+// The multi-kernel path over nsteps steps on W[0] (the state, stored row
+// order), with the Krylov basis W[1..m-1], partial sums partA/partB and
+// Lanczos scalars S supplied by the caller (the context's workspace, or the
+// static scratch of cfet_propagate_static).  Allocates nothing.
+int run_multi(cfet_ctx* c, double t0, double dt, int64_t nsteps, const SchemeTable& sc, int m,
+              double2* const* W, double* partA, double* partB, LzScalars* S, bool timed,
+              hipStream_t st) {
+  hipError_t e;
+  cfet::ExpWork wk;
+  wk.W_host = W;
+  wk.partA = partA;
+  wk.partB = partB;
+  wk.S = S;
+  wk.stats = c->stats;
+  wk.sell = c->use_sell ? &c->sell : nullptr;
+  wk.hi = (c->use_sell && c->hi.nuni) ? &c->hi : nullptr;
+  wk.tbits = c->tbits;
+  wk.nb_tile = c->nb_tile;
+  wk.tile_real = c->tile_real;
+  if (timed) {
+    if (c->events.used > 0) {
+      (void)hipStreamSynchronize(c->last_stream);
+      harvest_events(c);
+    }
+    wk.events = &c->events;
+  } else {
+    wk.events = nullptr;
+  }
+  e = cfet::launch_norm_start(W[0], c->n, c->plan, partA, st);
+  if (e != hipSuccess) return hip_fail(c, e, "norm kernel");
+  double a[cfet::kMaxStages], b[cfet::kMaxStages * cfet::kMaxTerms];
+  cfet::TermWeights tw;
+  std::memset(&tw, 0, sizeof(tw));
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const double tn = t0 + double(n) * dt;
+    cfet::step_weights(sc, c->drives, tn, dt, a, b);
+    for (int i = sc.s - 1; i >= 0; --i) {
+      tw.w[0] = a[i];
+      for (int k = 0; k < c->nterms; ++k) tw.w[k + 1] = b[i * c->nterms + k];
+      e = cfet::launch_exponential(c->A, c->nterms, c->plan, tw, dt, m, wk, st);
+      if (e != hipSuccess) return hip_fail(c, e, "exponential kernels");
+    }
+  }
+  e = cfet::launch_final_norm(partA, c->plan.nb_vec, c->stats, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->stats_host, c->stats, sizeof(DevStats), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(c, e, "final kernels");
+  c->last_stream = st;
+  c->have_work = true;
+  c->last_path = 1;
+  return CFET_OK;
+}
+
 // cfet_propagate on psi_dev in the stored row order (user_order false: the
 // gradient's own buffers) or in the caller's order (permuted in and out when
 // the CSR paths run on a row order of their own).
@@ -1534,50 +1594,9 @@ int propagate_impl(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nst
     return rp == CFET_OK ? permute_out() : rp;
   }
   c->h_W[0] = static_cast<double2*>(psi_dev);
-  hipError_t e;
-  cfet::ExpWork wk;
-  wk.W_host = c->h_W.data();
-  wk.partA = c->partA;
-  wk.partB = c->partB;
-  wk.S = c->S;
-  wk.stats = c->stats;
-  wk.sell = c->use_sell ? &c->sell : nullptr;
-  wk.hi = (c->use_sell && c->hi.nuni) ? &c->hi : nullptr;
-  wk.tbits = c->tbits;
-  wk.nb_tile = c->nb_tile;
-  wk.tile_real = c->tile_real;
-  if (c->profiling) {
-    if (c->events.used > 0) {
-      (void)hipStreamSynchronize(c->last_stream);
-      harvest_events(c);
-    }
-    wk.events = &c->events;
-  } else {
-    wk.events = nullptr;
-  }
-  e = cfet::launch_norm_start(c->h_W[0], c->n, c->plan, c->partA, st);
-  if (e != hipSuccess) return hip_fail(c, e, "norm kernel");
-  std::vector<double> a(sc.s), b(sc.s * c->nterms);
-  cfet::TermWeights tw;
-  std::memset(&tw, 0, sizeof(tw));
-  for (int64_t n = 0; n < nsteps; ++n) {
-    const double tn = t0 + double(n) * dt;
-    cfet::step_weights(sc, c->drives, tn, dt, a.data(), b.data());
-    for (int i = sc.s - 1; i >= 0; --i) {
-      tw.w[0] = a[i];
-      for (int k = 0; k < c->nterms; ++k) tw.w[k + 1] = b[i * c->nterms + k];
-      e = cfet::launch_exponential(c->A, c->nterms, c->plan, tw, dt, m, wk, st);
-      if (e != hipSuccess) return hip_fail(c, e, "exponential kernels");
-    }
-  }
-  e = cfet::launch_final_norm(c->partA, c->plan.nb_vec, c->stats, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(c->stats_host, c->stats, sizeof(DevStats), hipMemcpyDeviceToHost, st);
-  if (e != hipSuccess) return hip_fail(c, e, "final kernels");
-  c->last_stream = st;
-  c->have_work = true;
-  c->last_path = 1;
-  return permute_out();
+  const int rm = run_multi(c, t0, dt, nsteps, sc, m, c->h_W.data(), c->partA, c->partB, c->S,
+                           c->profiling, st);
+  return rm == CFET_OK ? permute_out() : rm;
 }
 
 }  // namespace
@@ -1587,6 +1606,65 @@ extern "C" {
 int cfet_propagate(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
                    int32_t scheme, int32_t krylov_m, void* hip_stream) {
   return propagate_impl(c, psi_dev, t0, dt, nsteps, scheme, krylov_m, hip_stream, true);
+}
+
+int cfet_propagate_static(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
+                          int32_t scheme, int32_t krylov_m, void* hip_stream) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  if (!psi_dev) return fail(c, CFET_EINVAL, "null psi");
+  if (nsteps < 0) return fail(c, CFET_EINVAL, "nsteps < 0");
+  if (krylov_m < 1 || krylov_m > CFET_MAX_KRYLOV)
+    return fail(c, CFET_EINVAL, "krylov_m must be in 1..64");
+  if (!std::isfinite(t0) || !std::isfinite(dt)) return fail(c, CFET_EINVAL, "non-finite t0/dt");
+  SchemeTable sc;
+  if (!cfet::scheme_build(scheme, &sc)) return fail(c, CFET_EINVAL, "unknown scheme");
+  if (!is_device_ptr(psi_dev)) return fail(c, CFET_EINVAL, "psi must be device memory");
+  DeviceGuard g(c->device);
+  if (c->have_work && hipStreamQuery(c->last_stream) == hipSuccess &&
+      c->stats_host->status != CFET_OK) {
+    const int st = c->stats_host->status;
+    c->stats_host->status = CFET_OK;
+    return fail(c, st, "device fault latched by an earlier call (see cfet_stats)");
+  }
+  const int m = int(std::min<int64_t>(krylov_m, c->n));
+  // scratch layout: Lanczos scalars, two partial-sum arrays, the state in
+  // the stored row order (reordered operators only), the basis vectors 1..m-1
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t np = size_t(std::max(2 * c->plan.nb_spmv, c->plan.nb_vec));
+  const size_t nn = size_t(c->n);
+  const size_t off_a = up(sizeof(LzScalars));
+  const size_t off_b = off_a + up(np * sizeof(double));
+  const size_t off_pv = off_b + up(np * sizeof(double));
+  const size_t off_basis = off_pv + (c->perm ? up(nn * sizeof(double2)) : 0);
+  const size_t need = off_basis + size_t(m - 1) * nn * sizeof(double2);
+  if (need > cfet::static_scratch_bytes())
+    return fail(c, CFET_EINVAL,
+                "cfet_propagate_static: the problem needs " + std::to_string(need) +
+                    " bytes of scratch (Krylov basis of n (m - 1) complex values), more than "
+                    "the " + std::to_string(cfet::static_scratch_bytes()) + " it has");
+  if (nsteps == 0) return CFET_OK;
+  void* base = nullptr;
+  hipError_t e = cfet::static_scratch(c->device, &base);
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_propagate_static: scratch address");
+  char* sb = static_cast<char*>(base);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double2* W[cfet::kMaxM] = {};
+  W[0] = static_cast<double2*>(psi_dev);
+  if (c->perm) {
+    W[0] = reinterpret_cast<double2*>(sb + off_pv);
+    e = cfet::launch_permute(W[0], static_cast<const double2*>(psi_dev), c->perm, c->n, st);
+    if (e != hipSuccess) return hip_fail(c, e, "permute psi in");
+  }
+  for (int j = 1; j < m; ++j)
+    W[j] = reinterpret_cast<double2*>(sb + off_basis) + size_t(j - 1) * nn;
+  int rc = run_multi(c, t0, dt, nsteps, sc, m, W, reinterpret_cast<double*>(sb + off_a),
+                     reinterpret_cast<double*>(sb + off_b), reinterpret_cast<LzScalars*>(sb),
+                     false, st);
+  if (rc == CFET_OK && c->perm) {
+    e = cfet::launch_permute(static_cast<double2*>(psi_dev), W[0], c->iperm, c->n, st);
+    if (e != hipSuccess) rc = hip_fail(c, e, "permute psi out");
+  }
+  return rc;
 }
 
 int cfet_profile(cfet_ctx* c, int32_t enable, int32_t max_launches) {

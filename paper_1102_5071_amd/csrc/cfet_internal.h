@@ -290,6 +290,12 @@ int persistent_block_threads(int preset, bool single);
 int persistent_barrier_words();
 int persistent_choose_preset(int max_row, int64_t min_rows_per_block, bool single);
 
+// File-scope device array of the allocation-free entry point (noalloc.hip):
+// its size, and its address on `device` (looked up once per device; the
+// device must be current).
+size_t static_scratch_bytes();
+hipError_t static_scratch(int device, void** out);
+
 hipError_t launch_tridiag_expm(const double* alpha, const double* beta, int k, double dt,
                                double2* c, int32_t* status, hipStream_t st);
 hipError_t launch_stats_init(DevStats* st_dev, hipStream_t st);

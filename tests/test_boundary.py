@@ -76,6 +76,7 @@ def test_host_side_argument_errors():
     assert lib.cfet_tridiag_expm(None, None, 0, 0.1, None, None, None) == 1
     assert lib.cfet_tridiag_expm(None, None, 65, 0.1, None, None, None) == 1
     assert lib.cfet_propagate(None, None, 0.0, 0.1, 1, 1, 4, None) == 1
+    assert lib.cfet_propagate_static(None, None, 0.0, 0.1, 1, 1, 4, None) == 1
     assert lib.cfet_stats(None, None) == 1
     assert lib.cfet_destroy(None) == 1
     assert b"null" in lib.cfet_last_error(None)
