@@ -14,7 +14,8 @@ oracle results and closed forms.
   - L = 18, the whole 200-step run, on the default path (multi-kernel, CSR)
     and on the multi-kernel path with both shared layouts: whole final state.
 * Hydrogen on the radial grid: the benchmark's window (t0 = 40, dt = 0.002,
-  10 + 20 steps in calls of 10 steps, cooperative kernel).
+  10 + 20 steps in calls of 10 steps, cooperative kernel), and one exponential
+  at the configuration's dt = 0.05.
 * Closed forms at dim 2^24 (no oracle run at full size):
   - L = 24 non-interacting spins, each the circularly driven two-level system
     H = Delta sz + V (cos 2wt sx + sin 2wt sy) (Sec. 6.2): every exponential
@@ -149,6 +150,24 @@ def test_hydrogen_bench_window_vs_oracle():
     assert st["status"] == 0 and B.PATH_NAMES[st["path"]] == "coop"
     assert st["matvecs"] == int(g["n_matvec"])
     assert rel(out, g["psi"]) <= PROP_TOL
+
+
+@pytest.mark.parametrize("path", [None, "multi"])
+def test_hydrogen_one_exponential_at_table_dt(path):
+    # the configuration's own dt = 0.05 on the full grid: a whole CF8:11 step
+    # there moves by 4e-7 under 1e-16 input noise (the oracle alone), but the
+    # first exponential from the 1s state is well conditioned (2e-16): CF2:1
+    # (one exponential exp(-i dt H(t + dt/2)) per step), one step, m = 30
+    p = I.config_hydrogen()
+    out, st = None, None
+    with B.Propagator(p.H0, p.Hk, p.drives, path=path) as P:
+        psi = dev(p.psi0)
+        P.propagate(psi, 40.0, 0.05, 1, "CF2:1", p.m)
+        st = P.stats()
+        out = psi.cpu().numpy()
+    ref = O.propagate(p.H0, p.Hk, p.drives, p.psi0, 40.0, 0.05, 1, "CF2:1", m=p.m)
+    assert st["status"] == 0 and st["matvecs"] == p.m
+    assert rel(out, ref) <= PROP_TOL
 
 
 def test_noninteracting_spins_L24_tensor_product():

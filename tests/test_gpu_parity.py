@@ -200,6 +200,18 @@ def _tridiag_cases():
     a = np.zeros(20)
     b = np.ones(19)
     cases.append(("zero_diag", a, b, 0.7))
+    # theta = |dt| (lambda_max - lambda_min) / 2 above 7000: the diagonalisation
+    # route (implicit QR) instead of the expansion; random spectra up to k = 64
+    # and a Lanczos-like one (the hydrogen operator's spread at dt = 0.2)
+    for k, spread, dt in ((16, 1.0e4, 0.9), (30, 1.0e4, 2.0), (47, 5.0e4, 2.0),
+                          (64, 1.0e6, 1.0), (64, 2.0e4, -1.5)):
+        a = rng.uniform(-spread, spread, k)
+        b = np.abs(rng.standard_normal(k - 1)) * 0.1 * spread + 1.0
+        cases.append((f"qr_rand{k}_s{spread:g}_dt{dt}", a, b, dt))
+    k = 30
+    a = np.concatenate([np.linspace(-0.5, 2.0e5, k - 4), [1.0, 1.0 + 1e-12, 3.0, 3.0]])
+    b = np.abs(rng.standard_normal(k - 1)) * 10 + 1e-9
+    cases.append(("qr_spread_lanczos", a, b, 0.2))
     a = np.full(10, 2.5)
     b = np.full(9, 1e-200)
     cases.append(("diagonal_limit", a, b, 0.3))
@@ -208,6 +220,9 @@ def _tridiag_cases():
 
 @pytest.mark.parametrize("name,a,b,dt", _tridiag_cases(), ids=[c[0] for c in _tridiag_cases()])
 def test_tridiag_exponential(name, a, b, dt):
+    if name.startswith("qr_"):
+        lam = np.linalg.eigvalsh(np.diag(a) + np.diag(b, 1) + np.diag(b, -1))
+        assert abs(dt) * 0.5 * (lam[-1] - lam[0]) > 7000.0   # the QR route is taken
     ta = torch.tensor(a, dtype=torch.float64, device="cuda")
     tb = torch.tensor(b, dtype=torch.float64, device="cuda")
     c, status = B.tridiag_expm(ta, tb, dt)
