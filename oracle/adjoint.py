@@ -34,6 +34,16 @@ which is exact when both Krylov spaces are invariant (e.g. m >= dim).  The
 adjoint state moves back by the same Lanczos basis:
 lambda_{n,i-before} = E^H lambda = beta_lam W exp(+i dt S) e_1.
 
+A second, independent route (route="augmented") takes each term straight
+from the definition: the Krylov technique of Sec. 8.1 applied to the
+2n-dimensional block-triangular operator  A = [[X, D], [0, X]]  (X = Omega,
+D = -i dt H_k*) started from [0; psi]: exp(A) [0; psi] = [L(X, D) psi;
+exp(X) psi], so <lambda| L |psi> is <lambda| with the top half of the Krylov
+approximation of exp(A) [0; psi].  A is not skew-Hermitian, so the basis is
+built by Arnoldi with full (modified Gram-Schmidt) orthogonalisation and the
+small exponential is scipy's expm of the Hessenberg matrix; m_aug = 2 m
+vectors by default (the augmented space holds both chains).
+
 Memory: psi is kept at every ceil(sqrt(N))-th step; each segment is recomputed
 forward (storing the states before each exponential) when the backward sweep
 reaches it.
@@ -49,7 +59,7 @@ from .cfet import _as_matrix, drive_value, expv, lanczos, step_weights, tridiag_
 from .schemes import gl_weights, scheme as get_scheme
 
 __all__ = ["piece_of", "weight_derivatives", "fidelity", "fidelity_gradient",
-           "frechet_term"]
+           "frechet_term", "frechet_term_augmented", "arnoldi_expv"]
 
 
 def piece_of(d: dict, t: float) -> int:
@@ -106,6 +116,67 @@ def frechet_term(Hi, Hk, psi, lam, dt: float, m: int):
     return g, lam_before
 
 
+def arnoldi_expv(matvec, b: np.ndarray, m: int, dim: int, info: dict | None = None):
+    """Krylov approximation of exp(A) b for a general (non-normal) A given by
+    matvec: Arnoldi with modified Gram-Schmidt, ||b|| Q_k expm(H_k) e_1 with
+    k <= m the basis size reached (stops early when the next vector vanishes,
+    relative to the Hessenberg entries so far, as the Lanczos rule).
+    info (optional) receives k and the a-posteriori estimate of the error,
+    ||b|| h_{k+1,k} |e_k^T expm(H_k) e_1| (zero when the space is invariant)."""
+    beta = float(np.linalg.norm(b))
+    if beta == 0.0:
+        if info is not None:
+            info.update(k=0, estimate=0.0)
+        return np.zeros_like(b)
+    m = min(m, dim)
+    Q = np.zeros((b.shape[0], m), dtype=np.complex128)
+    Hh = np.zeros((m, m), dtype=np.complex128)
+    Q[:, 0] = b / beta
+    k = m
+    scale = 0.0
+    h_next = 0.0
+    for j in range(m):
+        w = matvec(Q[:, j])
+        for i in range(j + 1):
+            Hh[i, j] = np.vdot(Q[:, i], w)
+            w = w - Hh[i, j] * Q[:, i]
+        nw = float(np.linalg.norm(w))
+        scale = max(scale, float(np.max(np.abs(Hh[:j + 1, j]))) + nw)
+        if nw <= 1e-12 * scale:
+            k = j + 1
+            break
+        if j == m - 1:
+            h_next = nw
+            break
+        Hh[j + 1, j] = nw
+        Q[:, j + 1] = w / nw
+    c = sla.expm(Hh[:k, :k])[:, 0]
+    if info is not None:
+        info.update(k=k, estimate=beta * h_next * abs(c[k - 1]))
+    return beta * (Q[:, :k] @ c)
+
+
+def frechet_term_augmented(Hi, Hk, psi, lam, dt: float, m: int, m_aug: int | None = None,
+                           info: dict | None = None):
+    """<lam| L(-i dt Hi, -i dt Hk) |psi> by Arnoldi on the augmented operator
+    [[X, D], [0, X]] from [0; psi] (m_aug vectors, default 2 m), and the adjoint
+    state moved back by the Lanczos exponential with m vectors.  info receives
+    the Arnoldi basis size and error estimate (of the whole 2n-vector)."""
+    n = psi.shape[0]
+    m_aug = 2 * m if m_aug is None else m_aug
+
+    def aug(v):
+        top, bot = v[:n], v[n:]
+        return np.concatenate([-1j * dt * (Hi @ top) - 1j * dt * (Hk @ bot),
+                               -1j * dt * (Hi @ bot)])
+
+    b = np.concatenate([np.zeros(n, dtype=np.complex128), np.asarray(psi, np.complex128)])
+    y = arnoldi_expv(aug, b, m_aug, 2 * n, info)
+    g = np.vdot(lam, y[:n])
+    lam_before = expv(Hi, lam, -dt, m)
+    return g, lam_before
+
+
 def _exponentials_of_step(sc, H0, Hk, drives, t_n, dt):
     """The step's exponent operators in application order: list of (i, H_i)."""
     a, b = step_weights(sc, drives, t_n, dt)
@@ -127,8 +198,13 @@ def fidelity(H0, Hk, drives, psi0, target, t0, dt, nsteps, scheme_name, m):
 
 
 def fidelity_gradient(H0, Hk, drives, psi0, target, t0: float, dt: float, nsteps: int,
-                      scheme_name: str, m: int, term: int = 0, stats: dict | None = None):
-    """(F, dF/du) for the pieces u of the 'pwc' drive of driven term ``term``."""
+                      scheme_name: str, m: int, term: int = 0, stats: dict | None = None,
+                      route: str = "projected", m_aug: int | None = None):
+    """(F, dF/du) for the pieces u of the 'pwc' drive of driven term ``term``.
+    route: "projected" (the augmented operator projected on the two Lanczos
+    spaces) or "augmented" (Arnoldi on the augmented operator, m_aug vectors)."""
+    if route not in ("projected", "augmented"):
+        raise ValueError("route is 'projected' or 'augmented'")
     sc = get_scheme(scheme_name)
     d = drives[term]
     if d["kind"] != "pwc":
@@ -165,7 +241,10 @@ def fidelity_gradient(H0, Hk, drives, psi0, target, t0: float, dt: float, nsteps
                 before.append((n, i, Hi, psi.copy(), db[i]))
                 psi = expv(Hi, psi, dt, m)
         for n, i, Hi, psi_b, dbi in reversed(before):
-            g, lam = frechet_term(Hi, H1, psi_b, lam, dt, m)
+            if route == "projected":
+                g, lam = frechet_term(Hi, H1, psi_b, lam, dt, m)
+            else:
+                g, lam = frechet_term_augmented(Hi, H1, psi_b, lam, dt, m, m_aug)
             for p, w in dbi.items():
                 dz[p] += w * g
     grad = 2.0 * np.real(np.conj(z) * dz)

@@ -104,8 +104,8 @@ def test_batched_256_chains_sampled_trajectories():
 def test_control_problem_full_size_gradient_properties():
     # L = 14, K = 200 pieces, 2000 steps of CF6:5Opt, m = 20 (the gradient
     # benchmark): F equals |<target|psi_N>|^2 of the plain propagation, and
-    # central differences of the forward map (h = 1e-4) agree with dF/du on
-    # sampled pieces (the oracle needs minutes for the whole gradient here;
+    # central differences of the forward map (h = 1e-6) and fourth-order ones
+    # (h = 1e-3) agree with dF/du on sampled pieces (the oracle needs minutes for the whole gradient here;
     # it is compared with the GPU gradient at reduced sizes)
     p = I.config_adjoint()
     N = p.nsteps
@@ -123,11 +123,19 @@ def test_control_problem_full_size_gradient_properties():
         assert P.stats()["status"] == 0
     g = np.asarray(g)
     assert abs(F - forward_F(u)) <= 1e-12
-    h = 1e-4
     scale = np.max(np.abs(g))
+
+    def shifted(q, d):
+        uu = u.copy()
+        uu[q] += d
+        return forward_F(uu)
+
     for q in (3, 117):
-        up, um = u.copy(), u.copy()
-        up[q] += h
-        um[q] -= h
-        fd = (forward_F(up) - forward_F(um)) / (2 * h)
-        assert abs(fd - g[q]) <= 2e-8 * scale, (q, fd, g[q])
+        # central, h = 1e-6 (rounding-limited), and fourth order at h = 1e-3
+        h = 1e-6
+        fd = (shifted(q, h) - shifted(q, -h)) / (2 * h)
+        assert abs(fd - g[q]) <= 3e-7 * scale, (q, fd, g[q])
+        h = 1e-3
+        fd4 = (-shifted(q, 2 * h) + 8 * shifted(q, h) - 8 * shifted(q, -h)
+               + shifted(q, -2 * h)) / (12 * h)
+        assert abs(fd4 - g[q]) <= 2e-9 * scale, (q, fd4, g[q])

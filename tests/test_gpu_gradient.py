@@ -3,8 +3,17 @@
 gradient against the GPU forward map, and the autograd wrapper.
 
 Bar: F to 1e-12 absolute, dF/du to 1e-10 in relative 2-norm, for the same
-scheme and Krylov dimension.  Finite differences: central, h = 1e-4 (see the
-oracle pins for the choice), 2e-8 of max |dF/du|.
+scheme and Krylov dimension, against both oracle routes: the projected
+augmented operator (the kernels' own construction) and plain Arnoldi on the
+2n-dimensional augmented operator (an independent route; its Krylov space is
+converged at these sizes, so the two differ only by rounding).
+
+Finite differences of the GPU forward map, on every piece at L = 10:
+* central, h = 1e-6: rounding-limited.  F is about 1e-4 there and its rounding
+  after 1000 exponentials is of order 1e-17, which h turns into about 1e-11,
+  some 5e-8 of max |dF/du| (2.4e-4); bound 3e-7 of max |dF/du|;
+* fourth order, h = 1e-3 (f(u-2h), f(u-h), f(u+h), f(u+2h)): truncation
+  O(h^4) and rounding 1e-17 / h both near 1e-13; bound 2e-9 of max |dF/du|.
 """
 import numpy as np
 import pytest
@@ -65,6 +74,35 @@ def test_gradient_matches_oracle(scheme, m, path):
     assert np.linalg.norm(g - go) <= 1e-10 * np.linalg.norm(go)
 
 
+@pytest.mark.parametrize("case", ["ising5_cf6", "ising6_dt015_cf4", "ising7_m40", "term1"])
+def test_gradient_matches_augmented_route(case):
+    kw = {}
+    if case == "ising5_cf6":
+        H0, Hk, drives, psi0, target = control_problem(5, 8, 0.4, 11)
+        args = (0.0, 0.01, 40, "CF6:5Opt", 12)
+    elif case == "ising6_dt015_cf4":
+        H0, Hk, drives, psi0, target = control_problem(6, 6, 0.6, 27)
+        args = (0.0, 0.15, 4, "CF4:2", 16)
+    elif case == "ising7_m40":
+        H0, Hk, drives, psi0, target = control_problem(7, 6, 0.6, 28)
+        args = (0.0, 0.15, 4, "CF4:2", 40)
+    else:
+        rng = np.random.default_rng(13)
+        n = 40
+        H0 = I.random_hermitian(n, rng, 0.3, 1.0)
+        Hk = [I.random_hermitian(n, rng, 0.2, 0.5), I.random_hermitian(n, rng, 0.2, 0.7)]
+        drives = [{"kind": "cos", "A": 0.6, "omega": 1.7, "phi": 0.2},
+                  {"kind": "pwc", "t_edges": np.linspace(0, 0.3, 7),
+                   "u": rng.uniform(-1, 1, 6)}]
+        psi0, target = I.random_state(n, rng), I.random_state(n, rng)
+        args = (0.0, 0.015, 20, "CF6:5Opt", 14)
+        kw = {"term": 1}
+    F, g = gpu_grad(H0, Hk, drives, psi0, target, *args)
+    Fa, ga = A.fidelity_gradient(H0, Hk, drives, psi0, target, *args, route="augmented", **kw)
+    assert abs(F - Fa) < 1e-12
+    assert np.linalg.norm(g - ga) <= 1e-10 * np.linalg.norm(ga)
+
+
 @pytest.mark.parametrize("L,m", [(6, 16), (7, 40)])
 def test_gradient_block_exponential_forms(L, m):
     # the small block exponential exp(M), M = -i dt [[S, C], [0, T]]: one
@@ -119,21 +157,25 @@ def _gpu_F(P, psi0, target, t0, dt, N, scheme, m):
     return abs(torch.vdot(dev(target), x).item()) ** 2
 
 
-def test_finite_differences_on_the_gpu():
+def test_finite_differences_on_the_gpu_every_piece():
     H0, Hk, drives, psi0, target = control_problem(10, 20, 2.0, 15)
     N, m, dt = 200, 20, 0.01
     F, g = gpu_grad(H0, Hk, drives, psi0, target, 0.0, dt, N, "CF6:5Opt", m)
-    h = 1e-4
     scale = np.max(np.abs(g))
-    for p in (0, 7, 19):
-        vals = []
-        for sgn in (+1, -1):
-            u = drives[0]["u"].copy()
-            u[p] += sgn * h
-            with B.Propagator(H0, Hk, [dict(drives[0], u=u)], path="multi") as P:
-                vals.append(_gpu_F(P, psi0, target, 0.0, dt, N, "CF6:5Opt", m))
-        fd = (vals[0] - vals[1]) / (2 * h)
-        assert abs(fd - g[p]) <= 2e-8 * scale, (p, fd, g[p])
+
+    def F_at(p, d):
+        u = drives[0]["u"].copy()
+        u[p] += d
+        with B.Propagator(H0, Hk, [dict(drives[0], u=u)], path="multi") as P:
+            return _gpu_F(P, psi0, target, 0.0, dt, N, "CF6:5Opt", m)
+
+    for p in range(len(drives[0]["u"])):
+        h = 1e-6
+        fd = (F_at(p, h) - F_at(p, -h)) / (2 * h)
+        assert abs(fd - g[p]) <= 3e-7 * scale, ("central", p, fd, g[p])
+        h = 1e-3
+        fd4 = (-F_at(p, 2 * h) + 8 * F_at(p, h) - 8 * F_at(p, -h) + F_at(p, -2 * h)) / (12 * h)
+        assert abs(fd4 - g[p]) <= 2e-9 * scale, ("fourth order", p, fd4, g[p])
 
 
 def test_zero_steps_and_errors():

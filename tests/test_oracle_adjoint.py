@@ -8,6 +8,17 @@
   of the oracle's own forward map (the Krylov CFET propagator), for pieces
   aligned with the steps and for pieces that cut steps.
 * F is the fidelity of the forward propagator.
+
+The second route (Arnoldi on the 2n-dimensional augmented operator
+[[X, D], [0, X]] from [0; psi], route="augmented") is pinned on its own:
+* with m_aug = 2 dim it equals scipy's Frechet derivative (dim <= 64);
+* for commuting X and D (both diagonal) L(X, D) = D exp(X), a closed form;
+* at m_aug < 2 dim its error is within the Arnoldi a-posteriori estimate.
+The projected route at m < dim is then held to a bound that follows from its
+construction: it is the integral over s of <a~(s)| D |b~(s)> with a~, b~ the
+Lanczos approximations (same m) of exp(+i s dt H) lam and exp(-i(1-s) dt H) psi,
+so its distance from the exact term is at most
+||D|| (||psi|| sup_s |a~ - a| + ||lam|| sup_s |b~ - b|).
 """
 import numpy as np
 import pytest
@@ -137,3 +148,94 @@ def test_adjoint_config_recipe():
     d = p.drives[0]
     assert len(d["u"]) == 20 and np.all(np.abs(d["u"]) <= 1)
     assert abs(np.linalg.norm(p.meta["target"]) - 1) < 1e-14
+
+
+def _frechet_problem(n, seed, dt):
+    rng = np.random.default_rng(seed)
+    Hi = I.random_hermitian(n, rng, 0.3, 1.0).to_scipy()
+    Hk = I.random_hermitian(n, rng, 0.3, 0.5).to_scipy()
+    psi, lam = I.random_state(n, rng), I.random_state(n, rng)
+    X, D = -1j * dt * Hi.toarray(), -1j * dt * Hk.toarray()
+    _, Lf = sla.expm_frechet(X, D)
+    return Hi, Hk, psi, lam, np.vdot(lam, Lf @ psi)
+
+
+@pytest.mark.parametrize("n,seed,dt", [(8, 1, 0.7), (24, 2, 0.3), (40, 3, -0.5), (64, 4, 0.4)])
+def test_augmented_route_equals_expm_frechet(n, seed, dt):
+    Hi, Hk, psi, lam, exact = _frechet_problem(n, seed, dt)
+    info = {}
+    g, lam_b = A.frechet_term_augmented(Hi, Hk, psi, lam, dt, n, m_aug=2 * n, info=info)
+    assert abs(g - exact) <= 1e-12 * abs(exact)
+    # the adjoint state moves back by exp(+i dt H)
+    ref = sla.expm(1j * dt * Hi.toarray()) @ lam
+    assert np.linalg.norm(lam_b - ref) <= 1e-12
+
+
+def test_augmented_route_commuting_closed_form():
+    # X = -i dt diag(E), D = -i dt diag(c): L(X, D) = D exp(X) exactly
+    rng = np.random.default_rng(9)
+    n, dt = 32, 0.6
+    E, c = rng.uniform(-2, 2, n), rng.uniform(-1, 1, n)
+    Hi, Hk = I.diagonal(E).to_scipy(), I.diagonal(c).to_scipy()
+    psi, lam = I.random_state(n, rng), I.random_state(n, rng)
+    exact = np.sum(np.conj(lam) * (-1j * dt * c) * np.exp(-1j * dt * E) * psi)
+    g, _ = A.frechet_term_augmented(Hi, Hk, psi, lam, dt, n, m_aug=2 * n)
+    assert abs(g - exact) <= 1e-13
+    g0, _ = A.frechet_term_augmented(Hi, Hk, np.zeros(n, complex), lam, dt, 8)
+    assert g0 == 0.0
+
+
+@pytest.mark.parametrize("m_aug", [10, 14, 18, 22])
+def test_augmented_route_within_arnoldi_estimate(m_aug):
+    Hi, Hk, psi, lam, exact = _frechet_problem(64, 5, 0.4)
+    info = {}
+    g, _ = A.frechet_term_augmented(Hi, Hk, psi, lam, 0.4, 12, m_aug=m_aug, info=info)
+    assert info["k"] == m_aug
+    # |<lam|top(y~ - y)>| <= ||lam|| ||y~ - y||, the estimate being of the latter
+    assert abs(g - exact) <= np.linalg.norm(lam) * info["estimate"]
+    assert abs(g - exact) > 1e-15        # the truncation is real at this size
+
+
+@pytest.mark.parametrize("m", [5, 7, 9, 11])
+def test_projected_route_within_krylov_bound(m):
+    n, dt = 64, 0.4
+    Hi, Hk, psi, lam, exact = _frechet_problem(n, 5, dt)
+    g_aug, _ = A.frechet_term_augmented(Hi, Hk, psi, lam, dt, n, m_aug=2 * n)
+    g_proj, _ = A.frechet_term(Hi, Hk, psi, lam, dt, m)
+    Hd = Hi.toarray()
+    ss = np.linspace(0.0, 1.0, 65)
+    e_psi = max(np.linalg.norm(O.expv(Hi, psi, (1 - s) * dt, m)
+                               - sla.expm(-1j * (1 - s) * dt * Hd) @ psi) for s in ss)
+    e_lam = max(np.linalg.norm(O.expv(Hi, lam, -s * dt, m)
+                               - sla.expm(1j * s * dt * Hd) @ lam) for s in ss)
+    bound = abs(dt) * np.linalg.norm(Hk.toarray(), 2) * (
+        np.linalg.norm(psi) * e_lam + np.linalg.norm(lam) * e_psi)
+    assert 1e-12 < abs(g_proj - g_aug) <= 1.05 * bound
+    # and the two routes at the same m agree within both estimates
+    info = {}
+    g_aug_m, _ = A.frechet_term_augmented(Hi, Hk, psi, lam, dt, m, info=info)
+    assert abs(g_proj - g_aug_m) <= 1.05 * bound + np.linalg.norm(lam) * info["estimate"]
+
+
+@pytest.mark.parametrize("scheme", ["CF4:2", "CF6:5Opt"])
+def test_gradient_augmented_route_equals_dense_frechet(scheme):
+    H0, H1, drives, psi0, target = small_problem(3, 5, 0.6, 0.05, 1)
+    N = 12
+    F, g = A.fidelity_gradient(H0, [H1], drives, psi0, target, 0.0, 0.05, N, scheme, m=8,
+                               route="augmented", m_aug=16)
+    Fr, gr = exact_gradient(H0, H1, drives, psi0, target, 0.0, 0.05, N, scheme)
+    assert abs(F - Fr) < 1e-12
+    assert np.linalg.norm(g - gr) <= 1e-11 * np.linalg.norm(gr)
+
+
+def test_gradient_routes_agree_at_realistic_sizes():
+    # dim 32, m = 12: both routes far from exact Krylov, both converged
+    H0, H1, drives, psi0, target = small_problem(5, 8, 0.4, 0.01, 2)
+    N, m = 40, 12
+    _, gp = A.fidelity_gradient(H0, [H1], drives, psi0, target, 0.0, 0.01, N, "CF6:5Opt", m)
+    _, ga = A.fidelity_gradient(H0, [H1], drives, psi0, target, 0.0, 0.01, N, "CF6:5Opt", m,
+                                route="augmented")
+    assert np.linalg.norm(gp - ga) <= 1e-11 * np.linalg.norm(ga)
+    with pytest.raises(ValueError):
+        A.fidelity_gradient(H0, [H1], drives, psi0, target, 0.0, 0.01, 1, "CF4:2", m,
+                            route="dense")
