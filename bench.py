@@ -9,8 +9,12 @@ size one GPU holds.  A "step" is one CFET step: 5 exponentials, each 24
 Lanczos iterations (SpMV + reductions), the small tridiagonal exponential and
 the recombination -- the whole path, on inputs already resident in HBM.
 
-The state error over the timed window is measured against a run at dt/4 with
-m = 40 and reported with the window length.  Other workloads:
+The time step is chosen for the accuracy goal (default 1e-8 over the
+workload's time span) by the library's two-run selection (cfet_select_dt,
+Sec. 6.6) on a probe window, unless --dt fixes it; the choice, its estimated
+error constant and its verification estimate are reported.  The state error
+over the timed window is measured against a run at dt/4 with m = 40 and
+reported with the window length.  Other workloads:
 --workload hydrogen | ising | batched | adjoint.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -30,7 +34,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 DEFAULT_CHUNK = {"hydrogen": 10, "ising": 50, "heisenberg": 1, "batched": 0, "adjoint": 0}
-# (timed steps, warm-up steps) when not given on the command line
+# (timed steps, warm-up steps) when not given on the command line; the plain
+# workloads time the selected number of steps instead (unless --dt fixes dt)
 DEFAULT_STEPS = {"hydrogen": (200, 20), "ising": (1000, 100), "heisenberg": (20, 2),
                  "batched": (200, 20), "adjoint": (200, 20)}
 # what limits the dominant kernel of each plain workload: the Heisenberg chain's
@@ -38,6 +43,17 @@ DEFAULT_STEPS = {"hydrogen": (200, 20), "ising": (1000, 100), "heisenberg": (20,
 # the hydrogen and Ising operators and Krylov bases stay in the caches and their
 # persistent kernels wait on grid-wide round trips
 BOUND = {"heisenberg": "hbm", "hydrogen": "latency", "ising": "latency"}
+# step selection per plain workload: (probe window start, probe window length,
+# probe steps n1, time span T the accuracy goal refers to).  The probe steps
+# are a few times the selected ones, so the distance of the two probe runs
+# (1e-11 .. 1e-6) stands well above rounding; the spans: the table's 200 steps
+# of 0.02 (Heisenberg), 1000 of 0.01 (Ising), and for hydrogen a window of 0.4
+# inside the pulse.  Without --steps the timed run covers the span: the
+# selected number of steps.
+SELECT = {"heisenberg": (0.0, 1.0, 8, 4.0), "ising": (0.0, 0.8, 8, 10.0),
+          "hydrogen": (40.0, 0.4, 40, 0.4)}
+# refinement rounds from the verification pair when its estimate misses the goal
+SELECT_REFINE = 4
 
 
 def log(msg):
@@ -111,7 +127,6 @@ def make_workload(name, L):
     if name == "hydrogen":
         p = I.config_hydrogen()
         p.t0 = 40.0           # inside the pulse
-        p.dt = 0.002          # meets the 1e-8 state-error bar (the table's dt is 0.05)
         label = "hydrogen-fd Nr=2000 dr=0.1 l<=63 dim=128000 CF8:11 m=30"
         key = "hydrogen"
     elif name == "ising":
@@ -120,7 +135,7 @@ def make_workload(name, L):
         key = f"ising_L{p.meta['L']}"
     elif name == "heisenberg":
         p = I.config_heisenberg(L=L or 24)
-        label = f"heisenberg L={p.meta['L']} dim={p.dim} CF6:5Opt dt={p.dt} m=24"
+        label = f"heisenberg L={p.meta['L']} dim={p.dim} CF6:5Opt m=24"
         key = f"heisenberg_L{p.meta['L']}"
     else:
         raise SystemExit(f"unknown workload {name}")
@@ -390,7 +405,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20,
                     help="batched: steps timed on the plain path per chain length")
     ap.add_argument("--L", type=int, default=0)
-    ap.add_argument("--dt", type=float, default=0.0, help="override the time step")
+    ap.add_argument("--dt", type=float, default=0.0,
+                    help="fix the time step (skips the step selection)")
+    ap.add_argument("--eps", type=float, default=1e-8,
+                    help="accuracy goal of the step selection over the workload's time span")
     ap.add_argument("--cpu-steps", type=int, default=-1,
                     help="oracle sample length (steps); 0 disables")
     ap.add_argument("--cpu-L", type=int, default=20,
@@ -412,6 +430,7 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     dsteps, dwarm = DEFAULT_STEPS[args.workload]
+    args.steps_given = args.steps is not None
     if args.steps is None:
         args.steps = dsteps
     if args.warmup is None:
@@ -447,12 +466,12 @@ def run_plain(args):
     from paper_1102_5071_amd import binding as B
 
     p, label, key = make_workload(args.workload, args.L)
+    dt_table = p.dt
     if args.dt:
         p.dt = args.dt
     chunk = args.chunk or DEFAULT_CHUNK[args.workload]
     K = max(chunk, (args.steps + chunk - 1) // chunk * chunk)
     W = (args.warmup + chunk - 1) // chunk * chunk
-    log(f"workload {label}, dt={p.dt}, steps={K}, warmup={W}, {chunk} steps per call")
 
     def run(psi, t0, dt, nsteps, m):
         for c in range(0, nsteps, chunk):
@@ -466,6 +485,32 @@ def run_plain(args):
     s = B.scheme_info(p.scheme)[1].shape[0]
 
     psi = torch.from_numpy(np.ascontiguousarray(p.psi0)).to("cuda")
+    # the time step for the accuracy goal (Sec. 6.6), unless given
+    selection = None
+    if not args.dt:
+        t0s, Wp, n1p, T_span = SELECT[args.workload]
+        t = time.perf_counter()
+        sel = P.select_dt(psi, t0s, Wp, n1p, p.scheme, p.m, T_span, args.eps,
+                          refine=SELECT_REFINE)
+        sel_s = time.perf_counter() - t
+        p.dt = sel["dt"]
+        if not args.steps_given:
+            K = max(chunk, (sel["nsteps"] + chunk - 1) // chunk * chunk)
+        selection = {"eps": args.eps, "T": T_span, "probe_window": [t0s, t0s + Wp],
+                     "probe_steps": [sel["n1"], sel["n2"]], "probe_distance": sel["diff"],
+                     "c": sel["c"], "order": sel["order"], "nsteps_for_T": sel["nsteps"],
+                     "err_est": sel["err_est"], "err_check": sel["err_check"],
+                     "check_steps": [sel["check_n1"], sel["check_n2"]],
+                     "refine_rounds": sel["rounds"],
+                     "dt_table": dt_table,
+                     "err_est_at_dt_table": sel["c"] * T_span * dt_table ** sel["order"],
+                     "seconds": round(sel_s, 2)}
+        log(f"step selection for eps={args.eps:g} over T={T_span:g}: probes n1={sel['n1']} "
+            f"n2={sel['n2']} on [{t0s:g}, {t0s + Wp:g}], distance {sel['diff']:.3e}, "
+            f"c={sel['c']:.3e} -> dt={p.dt:.6g} ({sel['nsteps']} steps), "
+            f"estimate {sel['err_est']:.2e}, check {sel['err_check']:.2e}, "
+            f"{sel['rounds']} refinement rounds ({sel_s:.1f}s)")
+    log(f"workload {label}, dt={p.dt:.6g}, steps={K}, warmup={W}, {chunk} steps per call")
     # warm-up
     run(psi, p.t0, p.dt, W, p.m)
     torch.cuda.synchronize()
@@ -586,11 +631,14 @@ def run_plain(args):
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": label, "dim": p.dim, "nnz": nnz_total, "scheme": p.scheme,
-                   "krylov_m": p.m, "dt": p.dt, "t0": t_start, "path": path,
+                   "krylov_m": p.m, "dt": p.dt, "dt_selection": selection,
+                   "t0": t_start, "path": path,
                    "layout": layout if path == "multi" else "csr",
                    "steps_per_call": chunk,
                    "state_error": state_error,
                    "state_error_window": [t_start, t_start + K * p.dt],
+                   "seconds_for_T": (round(selection["nsteps_for_T"] * elapsed / K, 4)
+                                     if selection else None),
                    "matvecs_per_step": matvecs / K},
         "roofline": roof,
         "cpu_baseline": cpu,

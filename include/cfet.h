@@ -254,6 +254,51 @@ CFET_API int cfet_gradient(cfet_ctx *c, const void *psi0_dev, const void *target
                            const double *u, int32_t K, double *F_out, double *dFdu_out,
                            void *hip_stream);
 
+/* Result of cfet_select_dt. */
+typedef struct {
+  double dt;            /* selected step, T_total / nsteps */
+  int64_t nsteps;       /* whole steps of size dt covering T_total */
+  double c;             /* estimated error constant of eps = c T dt^N */
+  double dt1, dt2;      /* probe steps window / n1, window / n2 */
+  double diff;          /* largest ||x1 - x2|| over the checkpoints */
+  double err_est;       /* c T_total dt^N (<= eps unless dt was capped at T_total) */
+  double err_check;     /* error of dt over T_total from the verification runs
+                           (NaN without verification) */
+  double check_window;  /* their window: check_n1 steps of dt */
+  int32_t order;        /* N of the scheme */
+  int32_t n1, n2;       /* probe step counts over the window */
+  int32_t check_n1, check_n2; /* step counts of the last verification runs (0: none) */
+  int32_t rounds;       /* refinement rounds taken (see refine) */
+} cfet_dt_choice;
+
+/* Time step for an accuracy goal from two runs (Sec. 6.6; the error of an
+ * order-N scheme over a time T behaves as eps = c T dt^N, Sec. 6.1).
+ * Propagates copies of psi0 over the probe window [t0, t0 + window] with n1
+ * steps and with n2 = J round((n1 / J) ratio^(1/N)) steps (at least n1 + J;
+ * J = checkpoints, n1 a multiple of J), takes the largest distance d of the
+ * two states at the J checkpoints t0 + j window / J, and sets
+ *     c = d / (window |dt1^N - dt2^N|),   dt = (eps / (c T_total))^(1/N),
+ * capped at T_total and rounded down to T_total / nsteps.  verify != 0 runs
+ * the window stretched to whole multiples of J steps of the selected dt, with
+ * dt and with the step of the same ratio below it, and reports their distance
+ * d' scaled to the error of dt over T_total:
+ *     err_check = d' dt^N / (dt^N - dt'^N) * T_total / check_window.
+ * refine > 0 (needs verify): while err_check > eps, at most refine times, the
+ * verification pair becomes the probe -- c = d' / (check_window |dt^N - dt'^N|),
+ * a new (smaller) dt, a new verification; the output describes the last
+ * round.  This catches probes taken where the error does not yet follow dt^N.
+ * ratio = (dt1 / dt2)^N is meant to lie in 2 .. 3.  Every run is a
+ * cfet_propagate with the given scheme and krylov_m on hip_stream.
+ * psi0_dev: complex128[n] device buffer (read only).  Writes *out (host) and
+ * synchronises hip_stream; device workspace of two state vectors, allocated
+ * for the call.  CFET_EINVAL for window, T_total, eps <= 0, ratio <= 1,
+ * checkpoints < 1, n1 not a positive multiple of checkpoints, refine < 0 or
+ * refine > 0 without verify. */
+CFET_API int cfet_select_dt(cfet_ctx *c, const void *psi0_dev, double t0, double window,
+                            int32_t n1, int32_t checkpoints, double ratio, int32_t scheme,
+                            int32_t krylov_m, double T_total, double eps, int32_t verify,
+                            int32_t refine, cfet_dt_choice *out, void *hip_stream);
+
 /* y = (a H0 + sum_k b[k] Hk[k]) x on the device (the weighted apply that the
  * Lanczos recursion uses; Sec. 8: the sparsity pattern of the sum is the
  * union of the patterns).  x_dev, y_dev: complex128[n] device buffers, must

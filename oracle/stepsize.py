@@ -32,7 +32,12 @@ Readings where the paper leaves a choice (each one a parameter here):
   stretched to W' = a whole number of selected steps (a multiple of J), with
   the selected step dt and with dt' of the same ratio (again on J
   checkpoints) and scales their largest distance d to the error of dt over
-  the total time:  err(dt) = d dt^N / (dt^N - dt'^N) * T_total / W'.
+  the total time:  err(dt) = d dt^N / (dt^N - dt'^N) * T_total / W';
+* refinement (optional, `refine` rounds at most): when that estimate exceeds
+  eps, the verification pair becomes the probe -- c from d and W' by the same
+  relation, a new dt, a new verification -- until the estimate meets eps.
+  This guards against probes taken outside the asymptotic range of dt^N
+  (the distance of the probes then underestimates c); the step only shrinks.
 """
 from __future__ import annotations
 
@@ -98,25 +103,35 @@ def _max_distance(run, psi0, t0: float, W: float, n_a: int, n_b: int, J: int) ->
     return d
 
 
+def _whole_steps(c: float, eps: float, T_total: float, N: int):
+    """(dt, nsteps): the step for eps, capped at T_total, rounded down to
+    T_total / nsteps."""
+    dt_raw = min(step_for(eps, c, T_total, N), T_total)
+    nsteps = max(1, math.ceil(T_total / dt_raw * (1.0 - 1e-12)))
+    return T_total / nsteps, nsteps
+
+
 def select_dt_from_runs(run, N: int, psi0, t0: float, W: float, n1: int, T_total: float,
-                        eps: float, ratio: float = 2.5, J: int = 1, verify: bool = True) -> dict:
+                        eps: float, ratio: float = 2.5, J: int = 1, verify: bool = True,
+                        refine: int = 0) -> dict:
     """The procedure of Sec. 6.6 for any propagator run(psi, t, dt, nsteps) -> psi
     of order N: probe the window [t0, t0 + W] with n1 and n2 steps, estimate c,
     extrapolate the step for eps over T_total, optionally check it with one
-    more pair of runs."""
-    if not (W > 0 and T_total > 0 and eps > 0 and ratio > 1):
-        raise ValueError("W, T_total, eps must be positive and ratio > 1")
+    more pair of runs (and refine from that pair up to `refine` times)."""
+    if not (W > 0 and T_total > 0 and eps > 0 and ratio > 1) or refine < 0:
+        raise ValueError("W, T_total, eps must be positive, ratio > 1, refine >= 0")
+    if refine and not verify:
+        raise ValueError("refinement needs the verification runs")
     n2 = probe_steps(n1, ratio, N, J)
     dt1, dt2 = W / n1, W / n2
     diff = _max_distance(run, psi0, t0, W, n1, n2, J)
     c = error_constant(diff, W, dt1, dt2, N)
-    dt_raw = min(step_for(eps, c, T_total, N), T_total)
-    nsteps = max(1, math.ceil(T_total / dt_raw * (1.0 - 1e-12)))
-    dt = T_total / nsteps
+    dt, nsteps = _whole_steps(c, eps, T_total, N)
     out = {"dt": dt, "nsteps": nsteps, "c": c, "order": N, "n1": n1, "n2": n2,
            "dt1": dt1, "dt2": dt2, "diff": diff, "err_est": c * T_total * dt ** N,
-           "err_check": None}
-    if verify:
+           "err_check": None, "rounds": 0}
+    rounds = 0
+    while verify:
         # the window stretched to whole steps of dt (J checkpoints), run with dt
         # and with the smaller step of the same ratio
         na = J * max(1, math.ceil(W / (J * dt) * (1.0 - 1e-12)))
@@ -124,14 +139,20 @@ def select_dt_from_runs(run, N: int, psi0, t0: float, W: float, n1: int, T_total
         nb = probe_steps(na, ratio, N, J)
         d = _max_distance(run, psi0, t0, Wc, na, nb, J)
         db = Wc / nb
-        out.update(check_window=Wc, check_steps=(na, nb), check_diff=d,
-                   err_check=d * dt ** N / (dt ** N - db ** N) * T_total / Wc)
+        err_check = d * dt ** N / (dt ** N - db ** N) * T_total / Wc
+        out.update(dt=dt, nsteps=nsteps, c=c, err_est=c * T_total * dt ** N, rounds=rounds,
+                   check_window=Wc, check_steps=(na, nb), check_diff=d, err_check=err_check)
+        if err_check <= eps or rounds >= refine:
+            break
+        rounds += 1
+        c = error_constant(d, Wc, dt, db, N)
+        dt, nsteps = _whole_steps(c, eps, T_total, N)
     return out
 
 
 def select_dt(H0, Hk, drives, psi0, t0: float, W: float, n1: int, scheme_name: str, m: int,
               T_total: float, eps: float, ratio: float = 2.5, J: int = 1, verify: bool = True,
-              dense: bool = False) -> dict:
+              dense: bool = False, refine: int = 0) -> dict:
     """select_dt_from_runs with the oracle's CFET propagator (Lanczos with m
     vectors, or exact exponentials with dense=True)."""
     sc = get_scheme(scheme_name)
@@ -139,4 +160,5 @@ def select_dt(H0, Hk, drives, psi0, t0: float, W: float, n1: int, scheme_name: s
     def run(psi, t, dt, nsteps):
         return propagate(H0, Hk, drives, psi, t, dt, nsteps, scheme_name, m=m, dense=dense)
 
-    return select_dt_from_runs(run, sc.order, psi0, t0, W, n1, T_total, eps, ratio, J, verify)
+    return select_dt_from_runs(run, sc.order, psi0, t0, W, n1, T_total, eps, ratio, J, verify,
+                               refine)

@@ -61,6 +61,14 @@ class _Stats(ctypes.Structure):
                 ("matrix_bytes", c_int64)]
 
 
+class _DtChoice(ctypes.Structure):
+    _fields_ = [("dt", c_double), ("nsteps", c_int64), ("c", c_double), ("dt1", c_double),
+                ("dt2", c_double), ("diff", c_double), ("err_est", c_double),
+                ("err_check", c_double), ("check_window", c_double), ("order", c_int32),
+                ("n1", c_int32), ("n2", c_int32), ("check_n1", c_int32), ("check_n2", c_int32),
+                ("rounds", c_int32)]
+
+
 class _Instance(ctypes.Structure):
     _fields_ = [("h0", c_int32), ("nterms", c_int32), ("hk", c_int32 * 7),
                 ("fk", _Drive * 7)]
@@ -101,6 +109,9 @@ def load():
     lib.cfet_gradient.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_double, c_int64,
                                   c_int32, c_int32, c_void_p, c_int32, POINTER(c_double),
                                   c_void_p, c_void_p]
+    lib.cfet_select_dt.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int32, c_int32,
+                                   c_double, c_int32, c_int32, c_double, c_double, c_int32,
+                                   c_int32, POINTER(_DtChoice), c_void_p]
     lib.cfet_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p]
     lib.cfet_stats.argtypes = [c_void_p, POINTER(_Stats)]
     lib.cfet_destroy.argtypes = [c_void_p]
@@ -305,6 +316,25 @@ class Propagator:
                                     ctypes.byref(F), g.ctypes.data, _stream_handle(stream)),
                self._ctx)
         return F.value, g
+
+    def select_dt(self, psi0, t0: float, window: float, n1: int, scheme, m: int,
+                  T_total: float, eps: float, ratio: float = 2.5, checkpoints: int = 1,
+                  verify: bool = True, refine: int = 0, stream=None) -> dict:
+        """cfet_select_dt: the step for an accuracy goal eps over T_total from
+        two probe runs of [t0, t0 + window] (n1 steps and the next count in
+        the given ratio), optionally checked by two more runs and refined
+        from them up to `refine` times."""
+        self._check_vec(psi0)
+        r = _DtChoice()
+        _check(load().cfet_select_dt(self._ctx, c_void_p(psi0.data_ptr()), float(t0),
+                                     float(window), int(n1), int(checkpoints), float(ratio),
+                                     scheme_id(scheme), int(m), float(T_total), float(eps),
+                                     1 if verify else 0, int(refine), ctypes.byref(r),
+                                     _stream_handle(stream)), self._ctx)
+        out = {f[0]: getattr(r, f[0]) for f in _DtChoice._fields_}
+        if not verify:
+            out["err_check"] = None
+        return out
 
     def pwc_pieces(self) -> int:
         return self._pwc_pieces

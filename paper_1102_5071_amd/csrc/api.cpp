@@ -99,6 +99,8 @@ int64_t coop_grid_blocks(int64_t n, int cus) {
 
 // device bytes the gradient may spend on keeping the recomputed projections
 constexpr size_t kGradStoreMax = size_t(16) << 30;
+static_assert(sizeof(cfet_dt_choice) == 96 && offsetof(cfet_dt_choice, rounds) == 92,
+              "cfet_dt_choice layout is part of the ABI");
 static_assert(sizeof(cfet_stats_t) == 120 && offsetof(cfet_stats_t, matrix_bytes) == 112,
               "cfet_stats_t layout is part of the ABI");
 
@@ -2002,6 +2004,131 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
     const int code = c->stats_host->status;
     return fail(c, code, "cfet_gradient: device fault (non-finite values or no convergence)");
   }
+  return CFET_OK;
+}
+
+int cfet_select_dt(cfet_ctx* c, const void* psi0_dev, double t0, double window, int32_t n1,
+                   int32_t checkpoints, double ratio, int32_t scheme, int32_t krylov_m,
+                   double T_total, double eps, int32_t verify, int32_t refine,
+                   cfet_dt_choice* out, void* hip_stream) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  if (!psi0_dev || !out) return fail(c, CFET_EINVAL, "null psi0 or output");
+  if (!(window > 0.0) || !(T_total > 0.0) || !(eps > 0.0) || !(ratio > 1.0) ||
+      !std::isfinite(window) || !std::isfinite(T_total) || !std::isfinite(ratio) ||
+      !std::isfinite(t0))
+    return fail(c, CFET_EINVAL, "window, T_total and eps must be positive, ratio > 1, all finite");
+  const int J = checkpoints;
+  if (J < 1 || n1 < 1 || n1 % J != 0)
+    return fail(c, CFET_EINVAL, "n1 must be a positive multiple of checkpoints >= 1");
+  if (refine < 0 || (refine > 0 && !verify))
+    return fail(c, CFET_EINVAL, "refine must be >= 0 and needs verify");
+  SchemeTable sc;
+  if (!cfet::scheme_build(scheme, &sc)) return fail(c, CFET_EINVAL, "unknown scheme");
+  if (!is_device_ptr(psi0_dev)) return fail(c, CFET_EINVAL, "psi0 must be device memory");
+  DeviceGuard g(c->device);
+  const int N = sc.order;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t nn = size_t(c->n);
+  const int nbp = cfet::dist2_blocks(c->n);
+  GradBuffers gb;
+  double2 *xa = nullptr, *xb = nullptr;
+  double* part = nullptr;
+  hipError_t e = gb.get(&xa, nn);
+  if (e == hipSuccess) e = gb.get(&xb, nn);
+  if (e == hipSuccess) e = gb.get(&part, size_t(nbp));
+  if (e != hipSuccess) return hip_fail(c, e, "cfet_select_dt: workspace");
+  std::vector<double> hpart(static_cast<size_t>(nbp), 0.0);
+  // n2 = J round((n1 / J) ratio^(1/N)), at least n1 + J
+  auto probe = [&](int64_t na) {
+    const int64_t nb = int64_t(J) * int64_t(std::llround(double(na / J) *
+                                                         std::pow(ratio, 1.0 / N)));
+    return std::max<int64_t>(nb, na + J);
+  };
+  // largest distance over the J checkpoints of runs of [t0, t0 + W] with
+  // na and nb steps, both started from psi0
+  auto max_distance = [&](double W, int64_t na, int64_t nb, double* d_out) -> int {
+    hipError_t ec = hipMemcpyAsync(xa, psi0_dev, nn * sizeof(double2), hipMemcpyDeviceToDevice, st);
+    if (ec == hipSuccess)
+      ec = hipMemcpyAsync(xb, psi0_dev, nn * sizeof(double2), hipMemcpyDeviceToDevice, st);
+    if (ec != hipSuccess) return hip_fail(c, ec, "cfet_select_dt: copy psi0");
+    const double dta = W / double(na), dtb = W / double(nb);
+    const int64_t ka = na / J, kb = nb / J;
+    double d = 0.0;
+    for (int j = 0; j < J; ++j) {
+      int rc = propagate_impl(c, xa, t0 + double(j * ka) * dta, dta, ka, scheme, krylov_m,
+                              hip_stream, true);
+      if (rc == CFET_OK)
+        rc = propagate_impl(c, xb, t0 + double(j * kb) * dtb, dtb, kb, scheme, krylov_m,
+                            hip_stream, true);
+      if (rc != CFET_OK) return rc;
+      ec = cfet::launch_dist2(xa, xb, c->n, part, st);
+      if (ec == hipSuccess)
+        ec = hipMemcpyAsync(hpart.data(), part, size_t(nbp) * sizeof(double),
+                            hipMemcpyDeviceToHost, st);
+      if (ec == hipSuccess) ec = hipStreamSynchronize(st);
+      if (ec != hipSuccess) return hip_fail(c, ec, "cfet_select_dt: distance");
+      if (c->stats_host->status != CFET_OK) {
+        const int code = c->stats_host->status;
+        c->stats_host->status = CFET_OK;
+        return fail(c, code, "cfet_select_dt: device fault in a probe run (see cfet_stats)");
+      }
+      double s2 = 0.0;
+      for (int i = 0; i < nbp; ++i) s2 += hpart[size_t(i)];
+      d = std::max(d, std::sqrt(s2));
+    }
+    *d_out = d;
+    return CFET_OK;
+  };
+  cfet_dt_choice r{};
+  r.order = N;
+  r.n1 = n1;
+  const int64_t n2 = probe(n1);
+  if (n2 > INT32_MAX) return fail(c, CFET_EINVAL, "probe step count overflows");
+  r.n2 = int32_t(n2);
+  r.dt1 = window / double(n1);
+  r.dt2 = window / double(n2);
+  int rc = max_distance(window, n1, n2, &r.diff);
+  if (rc != CFET_OK) return rc;
+  // dt for eps over T_total from the constant cc, capped at T_total and
+  // rounded down to whole steps
+  auto whole_steps = [&](double cc) -> int {
+    double dt_raw = cc > 0.0 ? std::pow(eps / (cc * T_total), 1.0 / N) : T_total;
+    dt_raw = std::min(dt_raw, T_total);
+    const double ns = std::ceil(T_total / dt_raw * (1.0 - 1e-12));
+    if (!(ns < 9.0e18)) return fail(c, CFET_EINVAL, "selected step count overflows");
+    r.c = cc;
+    r.nsteps = std::max<int64_t>(1, int64_t(ns));
+    r.dt = T_total / double(r.nsteps);
+    r.err_est = cc * T_total * std::pow(r.dt, N);
+    return CFET_OK;
+  };
+  rc = whole_steps(r.diff / (window * std::fabs(std::pow(r.dt1, N) - std::pow(r.dt2, N))));
+  if (rc != CFET_OK) return rc;
+  r.err_check = std::nan("");
+  for (int round = 0; verify; ++round) {
+    // the window stretched to whole multiples of J steps of dt, run with dt
+    // and with the smaller step of the same ratio
+    const double blocks = std::ceil(window / (double(J) * r.dt) * (1.0 - 1e-12));
+    if (!(blocks * J < 2.0e9)) return fail(c, CFET_EINVAL, "verification step count overflows");
+    const int64_t na = int64_t(J) * std::max<int64_t>(1, int64_t(blocks));
+    const int64_t nb = probe(na);
+    if (nb > INT32_MAX) return fail(c, CFET_EINVAL, "verification step count overflows");
+    const double Wc = double(na) * r.dt;
+    double d = 0.0;
+    rc = max_distance(Wc, na, nb, &d);
+    if (rc != CFET_OK) return rc;
+    const double db = Wc / double(nb);
+    const double pa = std::pow(r.dt, N), pb = std::pow(db, N);
+    r.check_window = Wc;
+    r.check_n1 = int32_t(na);
+    r.check_n2 = int32_t(nb);
+    r.err_check = d * pa / (pa - pb) * T_total / Wc;
+    r.rounds = round;
+    if (r.err_check <= eps || round >= refine) break;
+    rc = whole_steps(d / (Wc * std::fabs(pa - pb)));
+    if (rc != CFET_OK) return rc;
+  }
+  *out = r;
   return CFET_OK;
 }
 

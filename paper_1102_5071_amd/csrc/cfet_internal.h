@@ -242,6 +242,10 @@ hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
                             const double2* psi_rest, const double2* lam0, const double2* lam_rest,
                             const LzScalars* Spsi, const LzScalars* Slam, double2* part,
                             double2* C, hipStream_t st);
+// part[0 .. dist2_blocks(n) - 1] = block partial sums of ||a - b||^2
+int dist2_blocks(int64_t n);
+hipError_t launch_dist2(const double2* a, const double2* b, int64_t n, double* part,
+                        hipStream_t st);
 int zdot_blocks(int64_t n);
 hipError_t launch_zdot(const double2* a, const double2* b, int64_t n, double2* part,
                        double2* out, hipStream_t st);

@@ -86,6 +86,24 @@ __global__ __launch_bounds__(kBlock) void k_norm_start(const double2* __restrict
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// part[block] = sum over the block's rows of |a_r - b_r|^2 (the distance of
+// two states, taken on their difference so that it keeps full relative
+// accuracy when the states agree to many digits)
+__global__ __launch_bounds__(kBlock) void k_dist2(const double2* __restrict__ a,
+                                                  const double2* __restrict__ b, int64_t n,
+                                                  double* __restrict__ part) {
+  __shared__ double red[17];
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const double2 u = a[r], v = b[r];
+    const double dx = u.x - v.x, dy = u.y - v.y;
+    s += dx * dx + dy * dy;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 // y = H_w x for one row handled by a group of G lanes; NT = 1 specialises the
 // single-drive case (term bit selects the accumulator), NT = 0 is generic.
 template <int G, int NT>
@@ -492,6 +510,16 @@ hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& pla
 
 hipError_t launch_final_norm(const double* part, int np, DevStats* st_dev, hipStream_t st) {
   hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(kBlock), 0, st, part, np, st_dev);
+  return hipGetLastError();
+}
+
+int dist2_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kMaxBlocks));
+}
+
+hipError_t launch_dist2(const double2* a, const double2* b, int64_t n, double* part,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_dist2, dim3(dist2_blocks(n)), dim3(kBlock), 0, st, a, b, n, part);
   return hipGetLastError();
 }
 

@@ -63,6 +63,12 @@ def test_library_scheme_weights_match_oracle(name):
     assert np.allclose(g, go, atol=1e-15, rtol=0)
 
 
+def test_dt_choice_struct_layout():
+    # the binding's mirror of cfet_dt_choice: 9 doubles/int64 then 6 int32
+    assert ctypes.sizeof(B._DtChoice) == 96
+    assert B._DtChoice.order.offset == 72 and B._DtChoice.rounds.offset == 92
+
+
 def test_host_side_argument_errors():
     lib = _lib()
     assert lib.cfet_scheme_info(99, None, None, None, None) == 1
@@ -77,6 +83,8 @@ def test_host_side_argument_errors():
     assert lib.cfet_tridiag_expm(None, None, 65, 0.1, None, None, None) == 1
     assert lib.cfet_propagate(None, None, 0.0, 0.1, 1, 1, 4, None) == 1
     assert lib.cfet_propagate_static(None, None, 0.0, 0.1, 1, 1, 4, None) == 1
+    assert lib.cfet_select_dt(None, None, 0.0, 1.0, 10, 1, 2.5, 1, 8, 5.0, 1e-8, 1, 0, None,
+                              None) == 1
     assert lib.cfet_stats(None, None) == 1
     assert lib.cfet_destroy(None) == 1
     assert b"null" in lib.cfet_last_error(None)

@@ -16,6 +16,9 @@ the order comparison (Sec. 6.5, eq. ErrOrder).
   and eps from 1e-6 to 1e-10; the verification estimate is within a factor 4
   of the true error; and cbar = s c^(1/N) of the estimated c agrees with the
   measured (s / dt) (eps / T)^(1/N) (Sec. 6.3) within the accuracy of c.
+* Refinement from the verification pair (a reading, not in the paper): on a
+  modelled error that saturates above a step a, the plain procedure misses
+  the goal and its verification says so; refinement meets it.
 """
 import math
 import os
@@ -104,6 +107,35 @@ def test_exact_error_model(N, J):
     assert abs(r["err_check"] - c * T * r["dt"] ** N) <= 1e-4 * r["err_check"]
 
 
+def test_refinement_recovers_from_a_probe_outside_the_asymptotic_range():
+    # error c (t - t0) g(dt) with g = dt^N / (1 + (dt / a)^(N - 2)): dt^N below
+    # a, only dt^2 above it.  Probes far above a see a much smaller difference
+    # than the dt^N law implies, so the first c is far too small; the
+    # verification pair (at the extrapolated step) exposes it, and refinement
+    # brings the step below a, where the law holds.
+    N, a, c, w, t0 = 6, 0.05, 2e-3, 0.7, 0.0
+    W, T, eps = 4.0, 10.0, 1e-12
+    rng = np.random.default_rng(17)
+    u, v = I.random_state(4, rng), I.random_state(4, rng)
+
+    def g(dt):
+        return dt ** N / (1.0 + (dt / a) ** (N - 2))
+
+    def run(psi, t, dt, nsteps):
+        tau = nsteps * dt
+        return np.exp(-1j * w * tau) * psi + c * tau * g(dt) * np.exp(-1j * w * (t + tau)) * v
+
+    plain = SS.select_dt_from_runs(run, N, u, t0, W, 8, T, eps)
+    assert plain["rounds"] == 0 and plain["err_check"] > 10 * eps
+    r = SS.select_dt_from_runs(run, N, u, t0, W, 8, T, eps, refine=6)
+    assert 1 <= r["rounds"] <= 4
+    assert r["err_check"] <= eps
+    assert r["dt"] < plain["dt"]
+    assert c * T * g(r["dt"]) <= 1.1 * eps                 # the model's own error
+    with pytest.raises(ValueError):
+        SS.select_dt_from_runs(run, N, u, t0, W, 8, T, eps, verify=False, refine=1)
+
+
 def test_exact_propagator_gives_the_whole_time_in_one_step():
     # f = 0, diagonal H0: every CFET step is exact (the weights of H0 sum to
     # one), the probes agree to rounding and the cap dt <= T applies
@@ -150,6 +182,7 @@ def test_two_level_selected_step_meets_goal(scheme, eps):
     phi = np.array([1.0, 0.0], dtype=complex)
     T = 5 * math.pi / W_DRIVE
     r = SS.select_dt(H0, Hk, dr, phi, 0.0, T / 5, 20, scheme, 2, T, eps, J=4, dense=True)
+    assert r["rounds"] == 0
     sc = S.scheme(scheme)
     assert r["order"] == sc.order
     err = _true_error(scheme, r["dt"], r["nsteps"], phi)
