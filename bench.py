@@ -77,11 +77,12 @@ def exponential_algorithmic_bytes(dim, nnz_total, ncsr, m):
 
 def measured_traffic(kernel, key, chunk):
     """HBM bytes per launch of `kernel` from the committed counter summary
-    profiles/<kernel>__<key>.txt (FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    profiles/<kernel>__<key>.txt ('+' of a kernel pair written '_and_';
+    FETCH_SIZE + WRITE_SIZE, scaled by a copy
     kernel of known size), or None when there is none, when it was taken on
     other library sources (digest mismatch) or with another launch size."""
     from paper_1102_5071_amd.build import source_digest
-    path = os.path.join(PROFILES, f"{kernel}__{key}.txt")
+    path = os.path.join(PROFILES, f"{kernel.replace('+', '_and_')}__{key}.txt")
     if not os.path.exists(path):
         return None
     fields = {}

@@ -31,7 +31,7 @@ PATH_NAMES = {0: "none", 1: "multi", 2: "single", 3: "coop"}
 LAYOUT_NAMES = {0: "csr", 1: "sell", 2: "sell_uniform", 3: "sell_split"}
 # the kernel(s) of one Lanczos SpMV on the multi-kernel path, per layout
 SPMV_KERNEL_NAMES = {0: "k_lz_spmv", 1: "k_sell_lz_spmv", 2: "k_sell_lz_spmv",
-                     3: "k_sell_lz_spmv+k_sell_hi_spmv"}
+                     3: "k_tile_pass1+k_tile_pass2"}
 MAX_KRYLOV = 64
 
 
