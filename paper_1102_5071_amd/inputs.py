@@ -47,9 +47,12 @@ class CSR:
         return int(self.row_ptr[-1])
 
     def to_scipy(self):
+        """A scipy CSR copy (its arrays share no memory with this container:
+        scipy sorts a non-canonical matrix's entries in place on some
+        operations, e.g. abs(), which would reorder the values here alone)."""
         import scipy.sparse as sp
-        return sp.csr_matrix((self.val, self.col.astype(np.int64), self.row_ptr),
-                             shape=(self.n, self.n))
+        return sp.csr_matrix((self.val.copy(), self.col.astype(np.int64),
+                              self.row_ptr.copy()), shape=(self.n, self.n))
 
     def toarray(self):
         return self.to_scipy().toarray()
