@@ -422,6 +422,11 @@ def main():
     ap.add_argument("--chunk", type=int, default=0,
                     help="steps per propagate call (default per workload); every launch "
                          "of the timed kernel then covers the same work")
+    ap.add_argument("--exp", default="lanczos", choices=["lanczos", "chebyshev"],
+                    help="plain workloads: exponential by Lanczos (m vectors) or by the "
+                         "Chebyshev series (cfet_propagate_chebyshev)")
+    ap.add_argument("--cheb-tol", type=float, default=1e-12,
+                    help="Chebyshev: series truncation per exponential")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -474,9 +479,14 @@ def run_plain(args):
     K = max(chunk, (args.steps + chunk - 1) // chunk * chunk)
     W = (args.warmup + chunk - 1) // chunk * chunk
 
+    cheb = args.exp == "chebyshev"
+
     def run(psi, t0, dt, nsteps, m):
         for c in range(0, nsteps, chunk):
-            P.propagate(psi, t0 + c * dt, dt, chunk, p.scheme, m)
+            if cheb and m == p.m:
+                P.propagate_chebyshev(psi, t0 + c * dt, dt, chunk, p.scheme, args.cheb_tol)
+            else:
+                P.propagate(psi, t0 + c * dt, dt, chunk, p.scheme, m)
 
     t = time.perf_counter()
     P = B.Propagator(p.H0, p.Hk, p.drives, path=args.path, layout=args.layout)
@@ -529,7 +539,8 @@ def run_plain(args):
     steps_per_s = K / elapsed
     matvecs = st1["matvecs"] - st0["matvecs"]
     log(f"timed: {elapsed * 1e3:.1f} ms for {K} steps -> {steps_per_s:.2f} steps/s; "
-        f"matvecs {matvecs} (expected {K * s * min(p.m, p.dim)}), min m_eff {st1['min_m_eff']}")
+        f"matvecs {matvecs} ({'Chebyshev terms' if cheb else f'expected {K * s * min(p.m, p.dim)}'}), "
+        f"min m_eff {st1['min_m_eff']}")
     psi_end = psi.clone()
 
     path = B.PATH_NAMES[st1["path"]]
@@ -538,7 +549,8 @@ def run_plain(args):
     # launch of the dominant kernel (the SpMV on the multi-kernel path, the
     # whole-call kernel on the persistent paths)
     psi.copy_(psi_start)
-    P.profile(True, max_launches=min(K * s * p.m, 1 << 18), segments=False)
+    P.profile(True, max_launches=(1 << 18) if cheb else min(K * s * p.m, 1 << 18),
+              segments=False)
     run(psi, t_start, p.dt, K, p.m)
     torch.cuda.synchronize()
     stp = P.stats()
@@ -558,6 +570,10 @@ def run_plain(args):
             extra["csr_equivalent_GBps"] = round(csr_bytes / (avg_ms * 1e-3) / 1e9, 1)
         else:
             bytes_per_launch = csr_bytes
+        if cheb:
+            # the Chebyshev path times its applies (no Lanczos epilogue)
+            key += "_cheb"
+            kernel = {"k_lz_spmv": "k_apply", "k_sell_lz_spmv": "k_sell_apply"}.get(kernel, kernel)
     else:
         kernel = "k_propagate"
         bytes_per_launch = chunk * s * exponential_algorithmic_bytes(p.dim, nnz_total, ncsr, m_eff)
@@ -632,7 +648,10 @@ def run_plain(args):
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": label, "dim": p.dim, "nnz": nnz_total, "scheme": p.scheme,
-                   "krylov_m": p.m, "dt": p.dt, "dt_selection": selection,
+                   "krylov_m": None if cheb else p.m,
+                   "exponential": (f"chebyshev tol={args.cheb_tol:g}" if cheb
+                                   else f"lanczos m={p.m}"),
+                   "dt": p.dt, "dt_selection": selection,
                    "t0": t_start, "path": path,
                    "layout": layout if path == "multi" else "csr",
                    "steps_per_call": chunk,

@@ -228,6 +228,27 @@ CFET_API int cfet_propagate_static(cfet_ctx *c, void *psi_dev, double t0, double
                                    int64_t nsteps, int32_t scheme, int32_t krylov_m,
                                    void *hip_stream);
 
+/* cfet_propagate with every exponential taken by the Chebyshev technique
+ * instead of Lanczos (Sec. 8.1; compared with Krylov in Sec. 8.2): with an
+ * interval [lo, hi] holding the spectrum of H_i = a_i H0 + sum_k b_ik H_k --
+ * the terms' Gershgorin intervals (computed at cfet_create) summed with the
+ * weights, a negative weight swapping the ends -- sigma = (lo + hi)/2,
+ * h = (hi - lo)/2, theta = dt h,
+ *     psi <- e^{-i dt sigma} sum_{k=0..K} (2 - delta_k0) (-i)^k J_k(theta) T_k((H_i - sigma)/h) psi
+ * with T_k by its three-term recurrence, K the smallest index whose tail
+ * bound 2 (|theta|/2)^(K+1)/(K+1)! / (1 - |theta|/(2(K+2))) is at most tol
+ * (so the error of each exponential is at most tol ||psi||).  Same step
+ * driver, time grid and scheme as cfet_propagate; runs on the multi-kernel
+ * path's operator layout (one apply and one update kernel per term), needs
+ * three n-vectors of workspace (the context's Krylov workspace, grown to at
+ * least that).  cfet_stats counts the exponentials, their K products
+ * (matvecs) and the smallest K (min_m_eff); with cfet_profile on, the
+ * applies are timed.  psi_dev: complex128[n] device buffer, in place; tol in
+ * (0, 1); stream-ordered. */
+CFET_API int cfet_propagate_chebyshev(cfet_ctx *c, void *psi_dev, double t0, double dt,
+                                      int64_t nsteps, int32_t scheme, double tol,
+                                      void *hip_stream);
+
 /* Gradient of the final-state fidelity F = |<target|psi_N>|^2, psi_N the
  * state after nsteps CFET steps from psi0 (exactly the map of cfet_propagate:
  * same scheme, time grid and Lanczos exponentials with krylov_m vectors), with

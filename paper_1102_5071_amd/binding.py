@@ -109,6 +109,8 @@ def load():
     lib.cfet_gradient.argtypes = [c_void_p, c_void_p, c_void_p, c_double, c_double, c_int64,
                                   c_int32, c_int32, c_void_p, c_int32, POINTER(c_double),
                                   c_void_p, c_void_p]
+    lib.cfet_propagate_chebyshev.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int64,
+                                             c_int32, c_double, c_void_p]
     lib.cfet_select_dt.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int32, c_int32,
                                    c_double, c_int32, c_int32, c_double, c_double, c_int32,
                                    c_int32, POINTER(_DtChoice), c_void_p]
@@ -253,6 +255,16 @@ class Propagator:
         _check(load().cfet_propagate_static(self._ctx, c_void_p(psi.data_ptr()), float(t0),
                                             float(dt), int(nsteps), scheme_id(scheme), int(m),
                                             _stream_handle(stream)), self._ctx)
+        return psi
+
+    def propagate_chebyshev(self, psi, t0: float, dt: float, nsteps: int, scheme, tol: float,
+                            stream=None):
+        """cfet_propagate_chebyshev: the CFET steps with Chebyshev exponentials
+        (series truncated at tol per exponential); psi updated in place."""
+        self._check_vec(psi)
+        _check(load().cfet_propagate_chebyshev(self._ctx, c_void_p(psi.data_ptr()), float(t0),
+                                               float(dt), int(nsteps), scheme_id(scheme),
+                                               float(tol), _stream_handle(stream)), self._ctx)
         return psi
 
     def apply(self, x, a: float, b, y=None, stream=None):

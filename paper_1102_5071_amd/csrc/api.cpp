@@ -81,6 +81,9 @@ struct cfet_ctx {
   int preset_single = -1;           // register preset of the one-workgroup kernel (-1: none)
   int preset_coop = -1;             // register preset of the cooperative kernel (-1: none)
   int coop_blocks = 0;              // grid of the cooperative kernel
+  // Gershgorin interval of each term (0: H0, 1 + k: H_k), for the Chebyshev
+  // exponential's spectral bounds
+  std::vector<double> glo, ghi;
   std::string err;
 };
 
@@ -246,6 +249,66 @@ int ensure_workspace(cfet_ctx* c, int m) {
   for (int j = 1; j < m; ++j) c->h_W[j] = c->basis + size_t(j - 1) * size_t(c->n);
   c->m_alloc = m;
   return CFET_OK;
+}
+
+// The last index K of the Chebyshev series kept for tol: the smallest K >= 0
+// with 2 (|theta|/2)^(K+1) / (K+1)! / (1 - q) <= tol, q = |theta| / (2 (K+2)) < 1
+// (|J_k(theta)| <= (|theta|/2)^k / k! and |T_k| <= 1 on [-1, 1]).
+int cheb_terms(double theta, double tol) {
+  const double x = std::fabs(theta) / 2.0;
+  if (x == 0.0) return 0;
+  const double lt = std::log(tol);
+  for (int k = 0;; ++k) {
+    const double q = x / double(k + 2);
+    if (q < 1.0) {
+      const double lg = std::log(2.0) + double(k + 1) * std::log(x) - std::lgamma(double(k + 2)) -
+                        std::log1p(-q);
+      if (lg <= lt) return k;
+    }
+  }
+}
+
+// J_0(theta) .. J_K(theta): the power series for |theta| <= 1, Miller's
+// backward recurrence J_{k-1} = (2k/x) J_k - J_{k+1} from far above K,
+// normalised by J_0 + 2 sum J_2k = 1, otherwise; J_k(-x) = (-1)^k J_k(x).
+void bessel_j(double theta, int K, double* J) {
+  const double x = std::fabs(theta);
+  if (x <= 1.0) {
+    for (int k = 0; k <= K; ++k) {
+      // (x/2)^k / k! sum_m (-(x/2)^2)^m / (m! (m+k)!)
+      double term = 1.0;
+      for (int i = 1; i <= k; ++i) term *= (x / 2.0) / double(i);
+      double sum = 0.0;
+      const double q = -(x / 2.0) * (x / 2.0);
+      for (int m = 0; m < 40 && term != 0.0; ++m) {
+        sum += term;
+        term *= q / (double(m + 1) * double(m + 1 + k));
+      }
+      J[k] = sum;
+    }
+  } else {
+    const double top = std::max(double(K), x);
+    int M = int(top + 2.0 * std::sqrt(40.0 * (top + 1.0))) + 20;
+    M += M & 1;
+    double jp = 0.0, jk = 1e-30, norm = 0.0;
+    for (int k = M; k >= 1; --k) {
+      const double jm = (2.0 * double(k) / x) * jk - jp;
+      jp = jk;
+      jk = jm;                              // jk = J_{k-1} (unnormalised)
+      if (k - 1 <= K) J[k - 1] = jk;
+      if ((k - 1) % 2 == 0 && k - 1 > 0) norm += 2.0 * jk;
+      if (std::fabs(jk) > 1e200) {
+        jk *= 1e-200;
+        jp *= 1e-200;
+        norm *= 1e-200;
+        for (int i = k - 1; i <= K; ++i) J[i] *= 1e-200;
+      }
+    }
+    norm += jk;                             // + J_0
+    for (int k = 0; k <= K; ++k) J[k] /= norm;
+  }
+  if (theta < 0.0)
+    for (int k = 1; k <= K; k += 2) J[k] = -J[k];
 }
 
 // 1: one kernel per phase, 2: one workgroup, 3: cooperative grid
@@ -581,6 +644,37 @@ void run_threads(int64_t count, unsigned nth, Body body) {
   for (unsigned t = 0; t < nth; ++t)
     pool.emplace_back([&, t]() { body(count * t / nth, count * (t + 1) / nth); });
   for (auto& th : pool) th.join();
+}
+
+// Gershgorin interval of one Hermitian CSR matrix (Sec. 8.1: the Chebyshev
+// technique needs a-priori bounds on the spectrum): row r contributes
+// [d_r - R_r, d_r + R_r], d_r the real part of its diagonal entries, R_r the
+// sum of |H_rc| over its other entries.
+void gershgorin(const cfet::HostCSR& h, unsigned nth, double* lo, double* hi) {
+  std::vector<double> tlo(std::max(1u, nth), 1e300), thi(std::max(1u, nth), -1e300);
+  std::atomic<unsigned> next{0};
+  auto body = [&](int64_t r0, int64_t r1) {
+    const unsigned t = next.fetch_add(1);
+    double l = 1e300, u = -1e300;
+    for (int64_t r = r0; r < r1; ++r) {
+      double d = 0.0, R = 0.0;
+      for (int64_t e = h.rp[r]; e < h.rp[r + 1]; ++e) {
+        const double re = h.val[2 * e], im = h.val[2 * e + 1];
+        if (int64_t(h.col[e]) == r)
+          d += re;
+        else
+          R += std::hypot(re, im);
+      }
+      l = std::min(l, d - R);
+      u = std::max(u, d + R);
+    }
+    tlo[t] = l;
+    thi[t] = u;
+  };
+  run_threads(h.n, nth, body);
+  *lo = *std::min_element(tlo.begin(), tlo.end());
+  *hi = *std::max_element(thi.begin(), thi.end());
+  if (h.n == 0) *lo = *hi = 0.0;
 }
 
 // Stage the SELL-64 layout of the first pass: all entries, or with split_bit
@@ -1068,6 +1162,13 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
   c->n = n;
   c->nterms = nterms;
   c->flags = flags;
+  {
+    const unsigned nth = (n < 65536) ? 1u
+                                     : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    c->glo.assign(nterms + 1, 0.0);
+    c->ghi.assign(nterms + 1, 0.0);
+    for (int k = 0; k <= nterms; ++k) gershgorin(mats[k], nth, &c->glo[k], &c->ghi[k]);
+  }
 
   // Device layouts.  CSR (row r: entries of H0, then H1, ...) serves the
   // persistent paths and small problems; SELL (row r: H1.., then H0) serves the
@@ -1471,9 +1572,9 @@ int cfet_apply(cfet_ctx* c, const void* x_dev, void* y_dev, double a, const doub
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   hipError_t e;
   if (c->use_sell && c->hi.nuni) {
-    e = cfet::launch_tile_apply(c->sell, c->hi, c->tbits, c->nb_tile, c->nterms, tw,
-                                static_cast<const double2*>(x_dev), static_cast<double2*>(y_dev),
-                                st);
+    e = cfet::launch_tile_apply(c->sell, c->hi, c->tbits, c->nb_tile, c->nterms, c->tile_real,
+                                tw, static_cast<const double2*>(x_dev),
+                                static_cast<double2*>(y_dev), st);
   } else if (c->use_sell) {
     e = cfet::launch_sell_apply(c->sell, c->nterms, tw, static_cast<const double2*>(x_dev),
                                 static_cast<double2*>(y_dev), st);
@@ -1543,6 +1644,102 @@ int run_multi(cfet_ctx* c, double t0, double dt, int64_t nsteps, const SchemeTab
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->stats_host, c->stats, sizeof(DevStats), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_fail(c, e, "final kernels");
+  c->last_stream = st;
+  c->have_work = true;
+  c->last_path = 1;
+  return CFET_OK;
+}
+
+// y = H_w x in the stored row order on the layout of the multi-kernel path.
+hipError_t apply_stored(cfet_ctx* c, const cfet::TermWeights& tw, const double2* x, double2* y,
+                        hipStream_t st) {
+  if (c->use_sell && c->hi.nuni)
+    return cfet::launch_tile_apply(c->sell, c->hi, c->tbits, c->nb_tile, c->nterms, c->tile_real,
+                                   tw, x, y, st);
+  if (c->use_sell) return cfet::launch_sell_apply(c->sell, c->nterms, tw, x, y, st);
+  return cfet::launch_apply(c->A, c->nterms, c->plan, tw, x, y, st);
+}
+
+// The CFET step loop with Chebyshev exponentials on psi (stored row order):
+// per exponential the interval of H_i = a_i H0 + sum_k b_ik H_k from the terms'
+// Gershgorin intervals (a negative weight swaps the ends), sigma and h its
+// centre and half-width, theta = dt h, K terms for tol, and
+//   psi <- e^{-i dt sigma} sum_{k<=K} (2 - delta_k0) (-i)^k J_k(theta) T_k(H~) psi,
+// H~ = (H_i - sigma) / h, by the three-term recurrence of T_k.
+int run_cheb(cfet_ctx* c, double t0, double dt, int64_t nsteps, const SchemeTable& sc, double tol,
+             double2* psi, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  double2* V[3] = {c->h_W[1], c->h_W[2], c->h_W[3]};
+  const bool timed = c->profiling;
+  if (timed && c->events.used > 0) {
+    (void)hipStreamSynchronize(c->last_stream);
+    harvest_events(c);
+  }
+  double a[cfet::kMaxStages], b[cfet::kMaxStages * cfet::kMaxTerms];
+  std::vector<double> J;
+  cfet::TermWeights tw;
+  std::memset(&tw, 0, sizeof(tw));
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const double tn = t0 + double(n) * dt;
+    cfet::step_weights(sc, c->drives, tn, dt, a, b);
+    for (int i = sc.s - 1; i >= 0; --i) {
+      tw.w[0] = a[i];
+      for (int k = 0; k < c->nterms; ++k) tw.w[k + 1] = b[i * c->nterms + k];
+      double lo = 0.0, hi = 0.0;
+      for (int k = 0; k <= c->nterms; ++k) {
+        const double w = tw.w[k];
+        if (w >= 0.0) {
+          lo += w * c->glo[k];
+          hi += w * c->ghi[k];
+        } else {
+          lo += w * c->ghi[k];
+          hi += w * c->glo[k];
+        }
+      }
+      const double sigma = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+      const double ph = -dt * sigma;
+      const double2 phase = make_double2(std::cos(ph), std::sin(ph));
+      const int K = h > 0.0 ? cheb_terms(dt * h, tol) : 0;
+      J.assign(size_t(K) + 1, 0.0);
+      if (h > 0.0)
+        bessel_j(dt * h, K, J.data());
+      else
+        J[0] = 1.0;
+      // c_k = (2 - delta_k0) (-i)^k J_k e^{-i dt sigma}
+      auto coef = [&](int k) {
+        const double m = (k == 0 ? 1.0 : 2.0) * J[size_t(k)];
+        double re = 0.0, im = 0.0;   // (-i)^k m
+        switch (k & 3) {
+          case 0: re = m; break;
+          case 1: im = -m; break;
+          case 2: re = -m; break;
+          default: im = m; break;
+        }
+        return make_double2(re * phase.x - im * phase.y, re * phase.y + im * phase.x);
+      };
+      e = cfet::launch_cheb_start(psi, V[0], c->n, coef(0), K, c->stats, st);
+      if (e != hipSuccess) return hip_fail(c, e, "Chebyshev start");
+      double2* cur = V[0];
+      double2* prev = V[1];
+      double2* y = V[2];
+      for (int k = 1; k <= K; ++k) {
+        const bool ev = timed && c->events.used < c->events.cap;
+        if (ev) (void)hipEventRecord(c->events.begin[c->events.used], st);
+        e = apply_stored(c, tw, cur, y, st);
+        if (e != hipSuccess) return hip_fail(c, e, "Chebyshev apply");
+        if (ev) {
+          (void)hipEventRecord(c->events.end[c->events.used], st);
+          c->events.used += 1;
+        }
+        e = cfet::launch_cheb_update(y, cur, prev, psi, c->n, (k == 1 ? 1.0 : 2.0) / h, sigma,
+                                     k == 1, coef(k), st);
+        if (e != hipSuccess) return hip_fail(c, e, "Chebyshev update");
+        std::swap(cur, prev);
+      }
+    }
+  }
+  e = hipMemcpyAsync(c->stats_host, c->stats, sizeof(DevStats), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(c, e, "statistics");
   c->last_stream = st;
   c->have_work = true;
   c->last_path = 1;
@@ -1664,6 +1861,42 @@ int cfet_propagate_static(cfet_ctx* c, void* psi_dev, double t0, double dt, int6
                      false, st);
   if (rc == CFET_OK && c->perm) {
     e = cfet::launch_permute(static_cast<double2*>(psi_dev), W[0], c->iperm, c->n, st);
+    if (e != hipSuccess) rc = hip_fail(c, e, "permute psi out");
+  }
+  return rc;
+}
+
+int cfet_propagate_chebyshev(cfet_ctx* c, void* psi_dev, double t0, double dt, int64_t nsteps,
+                             int32_t scheme, double tol, void* hip_stream) {
+  if (!c) return fail(nullptr, CFET_EINVAL, "null context");
+  if (!psi_dev) return fail(c, CFET_EINVAL, "null psi");
+  if (nsteps < 0) return fail(c, CFET_EINVAL, "nsteps < 0");
+  if (!(tol > 0.0 && tol < 1.0)) return fail(c, CFET_EINVAL, "tol must be in (0, 1)");
+  if (!std::isfinite(t0) || !std::isfinite(dt)) return fail(c, CFET_EINVAL, "non-finite t0/dt");
+  SchemeTable sc;
+  if (!cfet::scheme_build(scheme, &sc)) return fail(c, CFET_EINVAL, "unknown scheme");
+  if (!is_device_ptr(psi_dev)) return fail(c, CFET_EINVAL, "psi must be device memory");
+  DeviceGuard g(c->device);
+  if (c->have_work && hipStreamQuery(c->last_stream) == hipSuccess &&
+      c->stats_host->status != CFET_OK) {
+    const int st = c->stats_host->status;
+    c->stats_host->status = CFET_OK;
+    return fail(c, st, "device fault latched by an earlier call (see cfet_stats)");
+  }
+  if (nsteps == 0) return CFET_OK;
+  int rc = ensure_workspace(c, 4);
+  if (rc != CFET_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double2* psi = static_cast<double2*>(psi_dev);
+  hipError_t e;
+  if (c->perm) {
+    e = cfet::launch_permute(c->pv, psi, c->perm, c->n, st);
+    if (e != hipSuccess) return hip_fail(c, e, "permute psi in");
+    psi = c->pv;
+  }
+  rc = run_cheb(c, t0, dt, nsteps, sc, tol, psi, st);
+  if (rc == CFET_OK && c->perm) {
+    e = cfet::launch_permute(static_cast<double2*>(psi_dev), c->pv, c->iperm, c->n, st);
     if (e != hipSuccess) rc = hip_fail(c, e, "permute psi out");
   }
   return rc;

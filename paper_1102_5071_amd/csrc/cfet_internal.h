@@ -143,9 +143,9 @@ constexpr int kTileBitsMax = 12;
 int tile_grid(int64_t n, int tbits, int num_cus);
 // Allows the tile kernels their LDS (once per process and device).
 hipError_t tile_prepare();
-// y = H x.
+// y = H x (real_vals: every stored value is real; real products only).
 hipError_t launch_tile_apply(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, int nterms,
-                             const TermWeights& tw, const double2* x, double2* y,
+                             bool real_vals, const TermWeights& tw, const double2* x, double2* y,
                              hipStream_t st);
 // Lanczos SpMV, same contract as launch_sell_lz_spmv; the alpha partials of
 // the two passes go to pout[0 .. 2 nb).
@@ -242,6 +242,14 @@ hipError_t launch_frechet_c(const DevCSR& A, int term, const double2* psi0,
                             const double2* psi_rest, const double2* lam0, const double2* lam_rest,
                             const LzScalars* Spsi, const LzScalars* Slam, double2* part,
                             double2* C, hipStream_t st);
+// Chebyshev series: v0 = psi, psi = c0 psi (and the statistics of one
+// exponential of K products); one term: w = scale (y - sigma v) - prev (no prev
+// when first), prev = w, psi += ck w.
+hipError_t launch_cheb_start(double2* psi, double2* v0, int64_t n, double2 c0, int K,
+                             DevStats* st_dev, hipStream_t st);
+hipError_t launch_cheb_update(const double2* y, const double2* v, double2* prev, double2* psi,
+                              int64_t n, double scale, double sigma, bool first, double2 ck,
+                              hipStream_t st);
 // part[0 .. dist2_blocks(n) - 1] = block partial sums of ||a - b||^2
 int dist2_blocks(int64_t n);
 hipError_t launch_dist2(const double2* a, const double2* b, int64_t n, double* part,

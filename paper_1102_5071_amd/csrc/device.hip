@@ -104,6 +104,50 @@ __global__ __launch_bounds__(kBlock) void k_dist2(const double2* __restrict__ a,
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Chebyshev exponential (Sec. 8.1): start of the series.  v0 = psi,
+// psi = c0 psi; block 0 counts the exponential and its K products.
+__global__ __launch_bounds__(kBlock) void k_cheb_start(double2* __restrict__ psi,
+                                                       double2* __restrict__ v0, int64_t n,
+                                                       double2 c0, int K,
+                                                       DevStats* __restrict__ st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const double2 p = psi[r];
+    v0[r] = p;
+    psi[r] = make_double2(c0.x * p.x - c0.y * p.y, c0.x * p.y + c0.y * p.x);
+  }
+  if (block0_thread0()) {
+    st->exponentials += 1;
+    st->matvecs += (unsigned long long)K;
+    if (K < st->min_m_eff) st->min_m_eff = K;
+  }
+}
+
+// One term of the series: w = scale (y - sigma v) - prev  (prev omitted for
+// the first term), prev <- w (the next polynomial), psi += ck w.  y = H_w v
+// from the apply kernels; scale is 1/h for T_1 and 2/h after it.
+__global__ __launch_bounds__(kBlock) void k_cheb_update(const double2* __restrict__ y,
+                                                        const double2* __restrict__ v,
+                                                        double2* __restrict__ prev,
+                                                        double2* __restrict__ psi, int64_t n,
+                                                        double scale, double sigma, int first,
+                                                        double2 ck) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const double2 yy = y[r], vv = v[r];
+    double wr = scale * (yy.x - sigma * vv.x);
+    double wi = scale * (yy.y - sigma * vv.y);
+    if (!first) {
+      const double2 pp = prev[r];
+      wr -= pp.x;
+      wi -= pp.y;
+    }
+    prev[r] = make_double2(wr, wi);
+    const double2 p = psi[r];
+    psi[r] = make_double2(p.x + ck.x * wr - ck.y * wi, p.y + ck.x * wi + ck.y * wr);
+  }
+}
+
 // y = H_w x for one row handled by a group of G lanes; NT = 1 specialises the
 // single-drive case (term bit selects the accumulator), NT = 0 is generic.
 template <int G, int NT>
@@ -510,6 +554,22 @@ hipError_t launch_exponential(const DevCSR& A, int nterms, const LaunchPlan& pla
 
 hipError_t launch_final_norm(const double* part, int np, DevStats* st_dev, hipStream_t st) {
   hipLaunchKernelGGL(k_final_norm, dim3(1), dim3(kBlock), 0, st, part, np, st_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_start(double2* psi, double2* v0, int64_t n, double2 c0, int K,
+                             DevStats* st_dev, hipStream_t st) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kMaxBlocks));
+  hipLaunchKernelGGL(k_cheb_start, dim3(nb), dim3(kBlock), 0, st, psi, v0, n, c0, K, st_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_update(const double2* y, const double2* v, double2* prev, double2* psi,
+                              int64_t n, double scale, double sigma, bool first, double2 ck,
+                              hipStream_t st) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kMaxBlocks));
+  hipLaunchKernelGGL(k_cheb_update, dim3(nb), dim3(kBlock), 0, st, y, v, prev, psi, n, scale,
+                     sigma, first ? 1 : 0, ck);
   return hipGetLastError();
 }
 

@@ -525,13 +525,13 @@ void launch_lz(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, const Te
                      tbits, tw, x, y, pout + nb, L, j);
 }
 
-template <int NT>
+template <int NT, bool RV>
 void launch_ap(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, const TermWeights& tw,
                const double2* x, double2* y, hipStream_t st) {
   const size_t lds = tile_lds_bytes(tbits);
-  hipLaunchKernelGGL((k_tile_pass1<NT, false, false>), dim3(nb), dim3(kPass1Threads), lds, st, S,
+  hipLaunchKernelGGL((k_tile_pass1<NT, false, RV>), dim3(nb), dim3(kPass1Threads), lds, st, S,
                      tbits, tw, x, y, nullptr, 0, nullptr, nullptr, 0);
-  hipLaunchKernelGGL((k_tile_pass2<NT, false, false>), dim3(nb), dim3(kPass2Threads), lds, st, H,
+  hipLaunchKernelGGL((k_tile_pass2<NT, false, RV>), dim3(nb), dim3(kPass2Threads), lds, st, H,
                      tbits, tw, x, y, nullptr, nullptr, 0);
 }
 
@@ -550,6 +550,8 @@ hipError_t tile_prepare() {
   if (e == hipSuccess) e = allow_pair<0, true, false>();
   if (e == hipSuccess) e = allow_pair<1, false, false>();
   if (e == hipSuccess) e = allow_pair<0, false, false>();
+  if (e == hipSuccess) e = allow_pair<1, false, true>();
+  if (e == hipSuccess) e = allow_pair<0, false, true>();
   return e;
 }
 
@@ -569,10 +571,12 @@ hipError_t launch_tile_lz_spmv(const DevSELL& S, const DevSELLHi& H, int tbits, 
 }
 
 hipError_t launch_tile_apply(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, int nterms,
-                             const TermWeights& tw, const double2* x, double2* y,
+                             bool real_vals, const TermWeights& tw, const double2* x, double2* y,
                              hipStream_t st) {
-  if (nterms == 1) launch_ap<1>(S, H, tbits, nb, tw, x, y, st);
-  else launch_ap<0>(S, H, tbits, nb, tw, x, y, st);
+  if (nterms == 1 && real_vals) launch_ap<1, true>(S, H, tbits, nb, tw, x, y, st);
+  else if (nterms == 1) launch_ap<1, false>(S, H, tbits, nb, tw, x, y, st);
+  else if (real_vals) launch_ap<0, true>(S, H, tbits, nb, tw, x, y, st);
+  else launch_ap<0, false>(S, H, tbits, nb, tw, x, y, st);
   return hipGetLastError();
 }
 

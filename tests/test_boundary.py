@@ -83,6 +83,7 @@ def test_host_side_argument_errors():
     assert lib.cfet_tridiag_expm(None, None, 65, 0.1, None, None, None) == 1
     assert lib.cfet_propagate(None, None, 0.0, 0.1, 1, 1, 4, None) == 1
     assert lib.cfet_propagate_static(None, None, 0.0, 0.1, 1, 1, 4, None) == 1
+    assert lib.cfet_propagate_chebyshev(None, None, 0.0, 0.1, 1, 1, 1e-12, None) == 1
     assert lib.cfet_select_dt(None, None, 0.0, 1.0, 10, 1, 2.5, 1, 8, 5.0, 1e-8, 1, 0, None,
                               None) == 1
     assert lib.cfet_stats(None, None) == 1
