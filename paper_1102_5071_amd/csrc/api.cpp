@@ -1724,16 +1724,26 @@ int run_cheb(cfet_ctx* c, double t0, double dt, int64_t nsteps, const SchemeTabl
       double2* y = V[2];
       for (int k = 1; k <= K; ++k) {
         const bool ev = timed && c->events.used < c->events.cap;
+        const double scale = (k == 1 ? 1.0 : 2.0) / h;
         if (ev) (void)hipEventRecord(c->events.begin[c->events.used], st);
-        e = apply_stored(c, tw, cur, y, st);
-        if (e != hipSuccess) return hip_fail(c, e, "Chebyshev apply");
+        if (c->use_sell && c->hi.nuni) {
+          // split layout: the term is applied in the second pass's epilogue
+          const cfet::ChebTerm ct{prev, psi, scale, sigma, coef(k), k == 1 ? 1 : 0};
+          e = cfet::launch_tile_cheb(c->sell, c->hi, c->tbits, c->nb_tile, c->nterms,
+                                     c->tile_real, tw, cur, y, ct, st);
+          if (e != hipSuccess) return hip_fail(c, e, "Chebyshev apply");
+        } else {
+          e = apply_stored(c, tw, cur, y, st);
+          if (e != hipSuccess) return hip_fail(c, e, "Chebyshev apply");
+        }
         if (ev) {
           (void)hipEventRecord(c->events.end[c->events.used], st);
           c->events.used += 1;
         }
-        e = cfet::launch_cheb_update(y, cur, prev, psi, c->n, (k == 1 ? 1.0 : 2.0) / h, sigma,
-                                     k == 1, coef(k), st);
-        if (e != hipSuccess) return hip_fail(c, e, "Chebyshev update");
+        if (!(c->use_sell && c->hi.nuni)) {
+          e = cfet::launch_cheb_update(y, cur, prev, psi, c->n, scale, sigma, k == 1, coef(k), st);
+          if (e != hipSuccess) return hip_fail(c, e, "Chebyshev update");
+        }
         std::swap(cur, prev);
       }
     }

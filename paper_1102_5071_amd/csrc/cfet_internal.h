@@ -143,6 +143,22 @@ constexpr int kTileBitsMax = 12;
 int tile_grid(int64_t n, int tbits, int num_cus);
 // Allows the tile kernels their LDS (once per process and device).
 hipError_t tile_prepare();
+// One term of the Chebyshev series fused into the second pass's epilogue:
+// w = scale (y - sigma x) - prev (prev omitted when first), prev <- w,
+// psi += ck w, with y = H x complete for the row (y itself is not written).
+struct ChebTerm {
+  double2* prev;
+  double2* psi;
+  double scale;
+  double sigma;
+  double2 ck;
+  int first;
+};
+// y = H x, then the Chebyshev term on the split layout (the first pass writes
+// y, the second applies the term instead of storing y).
+hipError_t launch_tile_cheb(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, int nterms,
+                            bool real_vals, const TermWeights& tw, const double2* x, double2* y,
+                            const ChebTerm& ct, hipStream_t st);
 // y = H x (real_vals: every stored value is real; real products only).
 hipError_t launch_tile_apply(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, int nterms,
                              bool real_vals, const TermWeights& tw, const double2* x, double2* y,

@@ -394,10 +394,13 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
 
 // Second pass over tiles of the permuted order (every offset inside the tile):
 // y[row] += H_hi x.  LZ: Lanczos form (state of the first pass, partials).
+// Without LZ and with ct.psi set, the row's complete y feeds one term of the
+// Chebyshev series (ChebTerm) instead of being stored.
 template <int NT, bool LZ, bool RV, int THREADS = kPass2Threads>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tile_pass2(
     DevSELLHi H, int tbits, TermWeights tw, const double2* __restrict__ x,
-    double2* __restrict__ y, double* __restrict__ part_out, const LzScalars* L, int j) {
+    double2* __restrict__ y, double* __restrict__ part_out, const LzScalars* L, int j,
+    ChebTerm ct) {
   extern __shared__ double2 xt[];
   const int T = 1 << tbits;
   double* red = reinterpret_cast<double*>(xt + T);
@@ -484,6 +487,19 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
                                       reinterpret_cast<dvec2*>(y) + row);
         const double2 xr = xt[qloc];
         apart += (xr.x * ar + xr.y * ai) * inv;
+      } else if (ct.psi) {
+        const double2 xr = xt[qloc];
+        double wr = ct.scale * ((y1.x + ar) - ct.sigma * xr.x);
+        double wi = ct.scale * ((y1.y + ai) - ct.sigma * xr.y);
+        if (!ct.first) {
+          const double2 pp = ct.prev[row];
+          wr -= pp.x;
+          wi -= pp.y;
+        }
+        ct.prev[row] = make_double2(wr, wi);
+        const double2 p = ct.psi[row];
+        ct.psi[row] = make_double2(p.x + ct.ck.x * wr - ct.ck.y * wi,
+                                   p.y + ct.ck.x * wi + ct.ck.y * wr);
       } else {
         y[row] = make_double2(y1.x + ar, y1.y + ai);
       }
@@ -522,17 +538,17 @@ void launch_lz(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, const Te
   hipLaunchKernelGGL((k_tile_pass1<NT, true, RV>), dim3(nb), dim3(kPass1Threads), lds, st, S,
                      tbits, tw, x, y, pin, npin, pout, L, j);
   hipLaunchKernelGGL((k_tile_pass2<NT, true, RV>), dim3(nb), dim3(kPass2Threads), lds, st, H,
-                     tbits, tw, x, y, pout + nb, L, j);
+                     tbits, tw, x, y, pout + nb, L, j, ChebTerm{});
 }
 
 template <int NT, bool RV>
 void launch_ap(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, const TermWeights& tw,
-               const double2* x, double2* y, hipStream_t st) {
+               const double2* x, double2* y, const ChebTerm& ct, hipStream_t st) {
   const size_t lds = tile_lds_bytes(tbits);
   hipLaunchKernelGGL((k_tile_pass1<NT, false, RV>), dim3(nb), dim3(kPass1Threads), lds, st, S,
                      tbits, tw, x, y, nullptr, 0, nullptr, nullptr, 0);
   hipLaunchKernelGGL((k_tile_pass2<NT, false, RV>), dim3(nb), dim3(kPass2Threads), lds, st, H,
-                     tbits, tw, x, y, nullptr, nullptr, 0);
+                     tbits, tw, x, y, nullptr, nullptr, 0, ct);
 }
 
 }  // namespace
@@ -573,10 +589,21 @@ hipError_t launch_tile_lz_spmv(const DevSELL& S, const DevSELLHi& H, int tbits, 
 hipError_t launch_tile_apply(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, int nterms,
                              bool real_vals, const TermWeights& tw, const double2* x, double2* y,
                              hipStream_t st) {
-  if (nterms == 1 && real_vals) launch_ap<1, true>(S, H, tbits, nb, tw, x, y, st);
-  else if (nterms == 1) launch_ap<1, false>(S, H, tbits, nb, tw, x, y, st);
-  else if (real_vals) launch_ap<0, true>(S, H, tbits, nb, tw, x, y, st);
-  else launch_ap<0, false>(S, H, tbits, nb, tw, x, y, st);
+  const ChebTerm none{};
+  if (nterms == 1 && real_vals) launch_ap<1, true>(S, H, tbits, nb, tw, x, y, none, st);
+  else if (nterms == 1) launch_ap<1, false>(S, H, tbits, nb, tw, x, y, none, st);
+  else if (real_vals) launch_ap<0, true>(S, H, tbits, nb, tw, x, y, none, st);
+  else launch_ap<0, false>(S, H, tbits, nb, tw, x, y, none, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_cheb(const DevSELL& S, const DevSELLHi& H, int tbits, int nb, int nterms,
+                            bool real_vals, const TermWeights& tw, const double2* x, double2* y,
+                            const ChebTerm& ct, hipStream_t st) {
+  if (nterms == 1 && real_vals) launch_ap<1, true>(S, H, tbits, nb, tw, x, y, ct, st);
+  else if (nterms == 1) launch_ap<1, false>(S, H, tbits, nb, tw, x, y, ct, st);
+  else if (real_vals) launch_ap<0, true>(S, H, tbits, nb, tw, x, y, ct, st);
+  else launch_ap<0, false>(S, H, tbits, nb, tw, x, y, ct, st);
   return hipGetLastError();
 }
 
