@@ -226,6 +226,12 @@ def run_batched(args):
     vec_bytes = float(np.sum(mv * (48.0 + 64.0) * dims)
                       + np.sum(expos * dims * 16.0 * (mv / expos + 2.0)))
     achieved = vec_bytes / elapsed / 1e9
+    # measured HBM traffic of one whole step (all kernels), when the committed
+    # counter summary matches these sources
+    traffic = measured_traffic("batched_step", f"batched_{nin}", 1)
+    if traffic is not None:
+        log(f"batched step: measured traffic {traffic / 1e9:.1f} GB per step "
+            f"({traffic / (vec_bytes / K):.2f} x the vector bytes)")
     psi_end = psi.clone()
     state_error = None
     if not args.no_error:
@@ -240,7 +246,7 @@ def run_batched(args):
     m_plain = int(st1["max_m_eff"])
     plain_per_L = {}
     Ks = min(K, args.plain_steps)
-    for t_i, inst in enumerate(Bt.instances):
+    for t_i, inst in enumerate(Bt.instances if Ks > 0 else []):
         L = inst["L"]
         if L in plain_per_L:
             continue
@@ -256,12 +262,14 @@ def run_batched(args):
         path = B.PATH_NAMES[Pp.stats()["path"]]
         plain_per_L[L] = (Ks / el, path)
         Pp.close()
-    per_step_plain = sum(1.0 / plain_per_L[i["L"]][0] for i in Bt.instances)
-    plain_rate = nin / per_step_plain
-    log("plain path (m=%d): " % m_plain + ", ".join(
-        f"L={L}: {r:.0f} steps/s ({p})" for L, (r, p) in sorted(plain_per_L.items()))
-        + f" -> {plain_rate:.1f} trajectory-steps/s for the batch one after another; "
-        f"batched/plain = {rate / plain_rate:.2f}")
+    plain_rate = None
+    if plain_per_L:
+        per_step_plain = sum(1.0 / plain_per_L[i["L"]][0] for i in Bt.instances)
+        plain_rate = nin / per_step_plain
+        log("plain path (m=%d): " % m_plain + ", ".join(
+            f"L={L}: {r:.0f} steps/s ({p})" for L, (r, p) in sorted(plain_per_L.items()))
+            + f" -> {plain_rate:.1f} trajectory-steps/s for the batch one after another; "
+            f"batched/plain = {rate / plain_rate:.2f}")
     cpu = None
     if args.cpu_steps != 0:
         from oracle import cfet as O
@@ -293,11 +301,15 @@ def run_batched(args):
         "config": {"workload": label, "trajectories": nin, "total_dim": P.total,
                    "state_error": state_error, "matvecs_per_exponential":
                        round(float(mv.sum()) / (nin * K * 2), 3),
-                   "plain_path_trajectory_steps_per_s": round(plain_rate, 3),
-                   "batched_over_plain": round(rate / plain_rate, 3)},
+                   "plain_path_trajectory_steps_per_s": (round(plain_rate, 3)
+                                                         if plain_rate else None),
+                   "batched_over_plain": round(rate / plain_rate, 3) if plain_rate else None},
         "roofline": {"bound": "hbm", "kernel": "batched step (all kernels, vector bytes only)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": vec_bytes / K, "launch": "one step",
+                     "traffic_GBps": (round(traffic * K / elapsed / 1e9, 1)
+                                      if traffic is not None else None)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -404,7 +416,8 @@ def main():
     ap.add_argument("--steps-override", type=int, default=0,
                     help="adjoint: steps of the control window (default T/dt)")
     ap.add_argument("--plain-steps", type=int, default=20,
-                    help="batched: steps timed on the plain path per chain length")
+                    help="batched: steps timed on the plain path per chain length "
+                         "(0: no plain comparison)")
     ap.add_argument("--L", type=int, default=0)
     ap.add_argument("--dt", type=float, default=0.0,
                     help="fix the time step (skips the step selection)")
