@@ -894,9 +894,10 @@ bool compact_shared_lists(int64_t nsl, int pad, std::vector<int32_t>* nuni,
 // all-rows groups, no row in the others).  groups[s] packs the four padded
 // counts in 16 bits each (group g at bits 16 g).  Returns false when a group
 // would not fit 16 bits or memory runs out.
-bool arrange_tiled_lists(int64_t nsl, std::vector<int32_t>* nuni, std::vector<int64_t>* uptr,
-                         std::vector<uint32_t>* ucol, std::vector<double>* uval,
-                         std::vector<uint64_t>* umask, std::vector<uint64_t>* groups) {
+bool arrange_tiled_lists(int64_t nsl, uint32_t tmask, std::vector<int32_t>* nuni,
+                         std::vector<int64_t>* uptr, std::vector<uint32_t>* ucol,
+                         std::vector<double>* uval, std::vector<uint64_t>* umask,
+                         std::vector<uint64_t>* groups) {
   std::vector<uint32_t> oc;
   std::vector<double> ov;
   std::vector<uint64_t> om;
@@ -917,24 +918,30 @@ bool arrange_tiled_lists(int64_t nsl, std::vector<int32_t>* nuni, std::vector<in
     uint64_t packed = 0;
     for (int g = 0; g < 4; ++g) {
       const bool driven = g < 2, full = (g % 2) == 0;
-      int64_t taken = 0;
-      for (int i = 0; i < cnt; ++i) {
-        const uint32_t ct = (*ucol)[b + i];
-        const uint64_t m = (*umask)[b + i];
-        if (((ct >> cfet::kTermShift) != 0) != driven || (m == ~0ull) != full) continue;
-        oc.push_back(ct);
-        ov.push_back((*uval)[2 * (b + i)]);
-        ov.push_back((*uval)[2 * (b + i) + 1]);
-        om.push_back(m);
-        ++taken;
-      }
       const uint32_t pad_term = driven ? (1u << cfet::kTermShift) : 0u;
-      while (taken % 4) {
-        oc.push_back(pad_term);
-        ov.push_back(0.0);
-        ov.push_back(0.0);
-        om.push_back(full ? ~0ull : 0ull);
-        ++taken;
+      int64_t taken = 0;
+      // entries outside the tile (offset above tmask) first, then the others,
+      // each part padded to whole batches of four (zero value, offset 0): a
+      // batch is either all gathers or all tile reads
+      for (int outside = 1; outside >= 0; --outside) {
+        for (int i = 0; i < cnt; ++i) {
+          const uint32_t ct = (*ucol)[b + i];
+          const uint64_t m = (*umask)[b + i];
+          if (((ct >> cfet::kTermShift) != 0) != driven || (m == ~0ull) != full) continue;
+          if (((ct & cfet::kColMask) > tmask) != (outside == 1)) continue;
+          oc.push_back(ct);
+          ov.push_back((*uval)[2 * (b + i)]);
+          ov.push_back((*uval)[2 * (b + i) + 1]);
+          om.push_back(m);
+          ++taken;
+        }
+        while (taken % 4) {
+          oc.push_back(pad_term);
+          ov.push_back(0.0);
+          ov.push_back(0.0);
+          om.push_back(full ? ~0ull : 0ull);
+          ++taken;
+        }
       }
       if (taken >= 65536) return false;
       packed |= uint64_t(taken) << (16 * g);
@@ -1341,9 +1348,10 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     // groups of four entries
     std::vector<uint64_t> groups1, groups2;
     if (staged && split)
-      staged = arrange_tiled_lists(nsl, &S.nuni, &S.uptr, &S.ucol, &S.uval, &S.umask, &groups1) &&
-               arrange_tiled_lists(n / 64, &HS.nuni, &HS.uptr, &HS.ucol, &HS.uval, &HS.umask,
-                                   &groups2);
+      staged = arrange_tiled_lists(nsl, (1u << sp.tbits) - 1u, &S.nuni, &S.uptr, &S.ucol,
+                                   &S.uval, &S.umask, &groups1) &&
+               arrange_tiled_lists(n / 64, 0xFFFFFFFFu, &HS.nuni, &HS.uptr, &HS.ucol, &HS.uval,
+                                   &HS.umask, &groups2);
     if (staged && uniform)
       staged = compact_shared_lists(nsl, 1, &S.nuni, &S.uptr, &S.ucol, &S.uval, &S.umask);
     if (staged && split)

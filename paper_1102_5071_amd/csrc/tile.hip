@@ -112,18 +112,32 @@ __device__ __forceinline__ void t_acc(uint32_t ct, dvec2 v, double2 xv, const Wt
   }
 }
 
-// x of the tile-local index (qb ^ ob) / 16: qb = 16 qloc, ob = 16 offset
-// (byte offsets; the mask keeps the read inside the tile)
-__device__ __forceinline__ double2 t_lds(const double2* xt, uint32_t qb, uint32_t ob,
-                                         uint32_t tmask16) {
-  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(xt) +
-                                           ((qb ^ ob) & tmask16));
+typedef __attribute__((address_space(3))) const dvec2* lds_cptr;
+
+// x of the tile-local index qloc ^ offset: qb = LDS byte address of the lane's
+// own element (tile base + 16 qloc), ob = 16 (offset & tile mask)
+// (wavefront-uniform, formed with scalar operations).  The tile base is
+// aligned to the tile's byte size (it is the start of the dynamic LDS), so
+// qb ^ ob stays in the tile: one vector XOR per entry, no add of the base.
+__device__ __forceinline__ double2 t_lds(const double2*, uint32_t qb, uint32_t ob) {
+  const dvec2 v = *(lds_cptr)(uintptr_t)(qb ^ ob);
+  return make_double2(v.x, v.y);
+}
+
+// LDS byte address of the lane's element, kept opaque to the compiler so that
+// it does not fold the per-entry XOR back into (qloc ^ offset) & mask,
+// shifted, plus the base (several vector operations per entry)
+__device__ __forceinline__ uint32_t t_lane_bytes(const double2* xt, int qloc) {
+  uint32_t qb = (uint32_t)(uintptr_t)((lds_cptr)xt) + ((uint32_t)qloc << 4);
+  asm volatile("" : "+v"(qb));
+  return qb;
 }
 
 // One group of a slice's shared entries (count cnt, a multiple of four) into
 // (ar, ai) without weights.  FULL: every row holds every entry (no lane test).
 // Offsets up to tmask read the tile in LDS; larger ones (GLOBAL: first pass,
-// identity order) gather x[row ^ offset].  The metadata of four entries is
+// identity order) gather x[row ^ offset]; the host stores them first in the
+// group, in whole batches of four.  The metadata of four entries is
 // read (scalar loads) before any of it is used: one latency per four.
 template <bool FULL, bool RV, bool GLOBAL>
 __device__ __forceinline__ void t_group(const CFET_CONST uint32_t* uc, const CFET_CONST dvec2* uv,
@@ -131,7 +145,6 @@ __device__ __forceinline__ void t_group(const CFET_CONST uint32_t* uc, const CFE
                                         uint64_t lanebit, uint32_t qb, int64_t row,
                                         uint32_t tmask, const double2* xt,
                                         const double2* __restrict__ x, double& ar, double& ai) {
-  const uint32_t tmask16 = (tmask << 4) | 15u;
   for (int k = k0; k < k0 + cnt; k += 4) {
     uint32_t off[4];
     uint64_t m[4];
@@ -144,12 +157,15 @@ __device__ __forceinline__ void t_group(const CFET_CONST uint32_t* uc, const CFE
       v[u].x = uv[k + u].x;
       v[u].y = RV ? 0.0 : uv[k + u].y;
     }
+    // a batch is all gathers or all tile reads (the host orders and pads the
+    // lists so): one decision per batch, no per-entry branch
+    if (GLOBAL && off[0] > tmask) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (GLOBAL && off[u] > tmask)
+      for (int u = 0; u < 4; ++u)
         xv[u] = x[(FULL || (m[u] & lanebit)) ? row ^ (int64_t)off[u] : row];
-      else
-        xv[u] = t_lds(xt, qb, off[u] << 4, tmask16);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = t_lds(xt, qb, (off[u] & tmask) << 4);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -195,14 +211,13 @@ __device__ __forceinline__ void t_shared_any(const CFET_CONST uint32_t* uc,
                                              uint32_t tmask, const double2* xt,
                                              const double2* __restrict__ x, const double* wl,
                                              double& ar, double& ai) {
-  const uint32_t tmask16 = (tmask << 4) | 15u;
   for (int k = 0; k < nu; ++k) {
     const uint32_t ct = uc[k];
     const uint32_t off = ct & kColMask;
     const uint64_t m = um[k];
     if (!(m & lanebit)) continue;
     const double2 xv = (GLOBAL && off > tmask) ? x[row ^ (int64_t)off]
-                                               : t_lds(xt, qb, off << 4, tmask16);
+                                               : t_lds(xt, qb, (off & tmask) << 4);
     const double w = wl[ct >> kTermShift];
     const double er = w * uv[k].x, ei = RV ? 0.0 : w * uv[k].y;
     ar = fma(er, xv.x, fma(-ei, xv.y, ar));
@@ -341,7 +356,7 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
         ct0 = __builtin_nontemporal_load(cp);
         v0 = __builtin_nontemporal_load(vp);
       }
-      const uint32_t qb = (uint32_t)qloc << 4;
+      const uint32_t qb = t_lane_bytes(xt, qloc);
       double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;  // unweighted, by term (NT = 1)
       double ar = 0.0, ai = 0.0;                          // weighted
       const int nu = as_const(S.nuni)[slice];
@@ -461,7 +476,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
         y1n = LZ ? __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(y) + r)
                  : dvec2{y[r].x, y[r].y};
       }
-      const uint32_t qb = (uint32_t)qloc << 4;
+      const uint32_t qb = t_lane_bytes(xt, qloc);
       double ar = 0.0, ai = 0.0;
       const int nu = as_const(H.nuni)[slice];
       if (nu > 0) {
