@@ -356,23 +356,48 @@ def run_adjoint(args):
     path = B.PATH_NAMES[P.stats()["path"]]
     log(f"plain forward ({path} path): {el_f * 1e3:.1f} ms -> {N / el_f:.1f} steps/s; "
         f"gradient / forward time = {elapsed / el_f:.2f}")
-    # central differences of a few components with the GPU forward map
-    h = 1e-4
-    fd_err = 0.0
+    # the roofline of the gradient's dominant kernel: the persistent launches
+    # (forward, segment recomputation, adjoint exponentials) timed with events
+    # over one more gradient call; each of the three sweeps runs N s
+    # exponentials of m vectors
+    s_exp = B.scheme_info(p.scheme)[1].shape[0]
+    P.profile(True, max_launches=1 << 14, segments=False)
+    st_a = P.stats()
+    P.gradient(psi0, target, 0.0, p.dt, N, p.scheme, p.m)
+    st_b = P.stats()
+    P.profile(False)
+    launches = st_b["timed_launches"] - st_a["timed_launches"]
+    timed_ms = st_b["timed_ms"] - st_a["timed_ms"]
+    nnz_total = p.H0.nnz + sum(h.nnz for h in p.Hk)
+    grad_bytes = 3 * N * s_exp * exponential_algorithmic_bytes(p.dim, nnz_total, 1 + len(p.Hk),
+                                                                min(p.m, p.dim))
+    grad_achieved = grad_bytes / (timed_ms * 1e-3) / 1e9 if timed_ms > 0 else None
+    log(f"k_propagate in the gradient: {launches} launches, {timed_ms:.1f} ms, "
+        f"{grad_bytes / 1e9:.1f} GB algorithmic -> {grad_achieved:.0f} GB/s")
+    # central differences of a few components with the GPU forward map: h = 1e-6
+    # (rounding-limited) and the fourth-order stencil at h = 1e-3
     scale = float(np.max(np.abs(g)))
+
+    def F_at(q, d):
+        u = p.drives[0]["u"].copy()
+        u[q] += d
+        Pq = B.Propagator(p.H0, p.Hk, [dict(p.drives[0], u=u)])
+        y = psi0.clone()
+        Pq.propagate(y, 0.0, p.dt, N, p.scheme, p.m)
+        val = abs(torch.vdot(target, y).item()) ** 2
+        Pq.close()
+        return val
+
+    fd_err = fd4_err = 0.0
     for q in (0, p.meta["K"] // 2, p.meta["K"] - 1):
-        vals = []
-        for sgn in (+1, -1):
-            u = p.drives[0]["u"].copy()
-            u[q] += sgn * h
-            Pq = B.Propagator(p.H0, p.Hk, [dict(p.drives[0], u=u)])
-            y = psi0.clone()
-            Pq.propagate(y, 0.0, p.dt, N, p.scheme, p.m)
-            vals.append(abs(torch.vdot(target, y).item()) ** 2)
-            Pq.close()
-        fd = (vals[0] - vals[1]) / (2 * h)
+        h = 1e-6
+        fd = (F_at(q, h) - F_at(q, -h)) / (2 * h)
         fd_err = max(fd_err, abs(fd - g[q]) / scale)
-    log(f"finite differences (h = 1e-4, 3 components): max error {fd_err:.2e} of max |dF/du|")
+        h = 1e-3
+        fd4 = (-F_at(q, 2 * h) + 8 * F_at(q, h) - 8 * F_at(q, -h) + F_at(q, -2 * h)) / (12 * h)
+        fd4_err = max(fd4_err, abs(fd4 - g[q]) / scale)
+    log(f"finite differences (3 components): central h = 1e-6 {fd_err:.2e}, fourth order "
+        f"h = 1e-3 {fd4_err:.2e} of max |dF/du|")
     cpu = None
     if args.cpu_steps != 0:
         from oracle import adjoint as OA
@@ -396,8 +421,14 @@ def run_adjoint(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
         "config": {"workload": label, "plain_forward_steps_per_s": round(N / el_f, 3),
                    "gradient_over_forward_time": round(elapsed / el_f, 3),
-                   "fd_max_rel_error": fd_err, "F": F},
-        "roofline": None,
+                   "fd_max_rel_error": fd_err, "fd4_max_rel_error": fd4_err, "F": F},
+        "roofline": ({"bound": "latency",
+                      "kernel": "k_propagate (forward, recomputation and adjoint exponentials)",
+                      "achieved": round(grad_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(grad_achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                      "bytes_per_launch": grad_bytes / max(1, launches), "launches": launches,
+                      "avg_launch_us": round(timed_ms * 1e3 / max(1, launches), 3)}
+                     if grad_achieved else None),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -339,8 +339,10 @@ CFET_API const char *cfet_last_error(const cfet_ctx *c);
 /* Kernel timing for measurement: with enable != 0, cfet_propagate records a
  * HIP event pair on the caller's stream around every launch of its dominant
  * kernel -- the Lanczos SpMV on the multi-kernel path (both launches of a
- * split layout between one event pair), the whole persistent kernel on the
- * single-workgroup and cooperative paths -- (up to max_launches
+ * split layout between one event pair; the apply of each term with
+ * cfet_propagate_chebyshev), the whole persistent kernel on the
+ * single-workgroup and cooperative paths, also its launches inside
+ * cfet_gradient -- (up to max_launches
  * pairs; later launches run untimed), and cfet_stats reports the count and
  * summed duration.  enable == 2 records the events only; any other nonzero
  * value also runs the persistent kernels' segment timers (cfet_stats

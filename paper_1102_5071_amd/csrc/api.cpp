@@ -478,8 +478,16 @@ hipError_t persistent_exponential(cfet_ctx* c, int path, double2* psi, double2* 
   pa.no_combine = no_combine ? 1 : 0;
   pa.export_Y = Y;
   if (bar) pa.bar = bar;  // cleared by the caller on the stream
-  return cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop, path == 2,
-                                 path == 3 ? c->coop_blocks : 1, st, bar == nullptr);
+  const bool timed = c->profiling && c->events.used < c->events.cap;
+  if (timed) (void)hipEventRecord(c->events.begin[c->events.used], st);
+  const hipError_t e = cfet::launch_persistent(pa, path == 2 ? c->preset_single : c->preset_coop,
+                                               path == 2, path == 3 ? c->coop_blocks : 1, st,
+                                               bar == nullptr);
+  if (timed && e == hipSuccess) {
+    (void)hipEventRecord(c->events.end[c->events.used], st);
+    c->events.used += 1;
+  }
+  return e;
 }
 
 }  // namespace
