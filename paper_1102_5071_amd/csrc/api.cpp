@@ -200,6 +200,10 @@ void free_ctx(cfet_ctx* c) {
   if (c->hi.uval) (void)hipFree(c->hi.uval);
   if (c->hi.umask) (void)hipFree(c->hi.umask);
   if (c->hi.tile_row) (void)hipFree(c->hi.tile_row);
+  if (c->sell.ccolt) (void)hipFree(c->sell.ccolt);
+  if (c->sell.cval) (void)hipFree(c->sell.cval);
+  if (c->hi.ccolt) (void)hipFree(c->hi.ccolt);
+  if (c->hi.cval) (void)hipFree(c->hi.cval);
   if (c->basis) (void)hipFree(c->basis);
   if (c->partA) (void)hipFree(c->partA);
   if (c->partB) (void)hipFree(c->partB);
@@ -965,6 +969,154 @@ bool arrange_tiled_lists(int64_t nsl, uint32_t tmask, std::vector<int32_t>* nuni
   return true;
 }
 
+// The entries that every slice's shared list holds with a full row mask and
+// the same offset, term and value (a driven sum of site operators with one
+// coefficient: every sigma_x flip), moved out of the per-slice lists into one
+// common list.  The tiled kernels then read them from one place, where the
+// scalar cache keeps them, instead of from every slice's own list.  The
+// common list is arranged as the kernels read it: driven terms, then H0;
+// each part with the entries outside the tile (offset above tmask) first,
+// each run padded to whole batches of four (zero value, offset 0).
+constexpr int kCommonMax = 64;
+
+struct CommonList {
+  std::vector<uint32_t> col;
+  std::vector<double> val;   // re, im
+  int nd = 0, nh = 0;
+};
+
+bool extract_common(int64_t nsl, uint32_t tmask, unsigned nth, std::vector<int32_t>* nuni,
+                    std::vector<int64_t>* uptr, std::vector<uint32_t>* ucol,
+                    std::vector<double>* uval, std::vector<uint64_t>* umask, CommonList* C) {
+  struct Key {
+    uint32_t ct;
+    uint64_t re, im;
+    bool operator<(const Key& o) const {
+      if (ct != o.ct) return ct < o.ct;
+      if (re != o.re) return re < o.re;
+      return im < o.im;
+    }
+    bool operator==(const Key& o) const { return ct == o.ct && re == o.re && im == o.im; }
+  };
+  auto key_of = [&](int64_t e) {
+    Key k;
+    k.ct = (*ucol)[e];
+    std::memcpy(&k.re, &(*uval)[2 * e], 8);
+    std::memcpy(&k.im, &(*uval)[2 * e + 1], 8);
+    return k;
+  };
+  *C = CommonList();
+  if (nsl <= 0) return true;
+  std::vector<Key> cand;
+  for (int64_t e = (*uptr)[0]; e < (*uptr)[1]; ++e)
+    if ((*umask)[e] == ~0ull) cand.push_back(key_of(e));
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  if (cand.empty()) return true;
+  const unsigned T = std::max(1u, nth);
+  std::vector<std::vector<int64_t>> cnt(T, std::vector<int64_t>(cand.size(), 0));
+  std::atomic<unsigned> next{0};
+  auto find = [&](const Key& k) -> int64_t {
+    auto it = std::lower_bound(cand.begin(), cand.end(), k);
+    return (it != cand.end() && *it == k) ? int64_t(it - cand.begin()) : -1;
+  };
+  run_threads(nsl, T, [&](int64_t s0, int64_t s1) {
+    std::vector<int64_t>& my = cnt[next.fetch_add(1)];
+    for (int64_t sl = s0; sl < s1; ++sl)
+      for (int64_t e = (*uptr)[sl]; e < (*uptr)[sl + 1]; ++e)
+        if ((*umask)[e] == ~0ull) {
+          const int64_t i = find(key_of(e));
+          if (i >= 0) ++my[size_t(i)];
+        }
+  });
+  std::vector<char> common(cand.size(), 0);
+  int ncommon = 0;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    int64_t tot = 0;
+    for (unsigned t = 0; t < T; ++t) tot += cnt[t][i];
+    if (tot == nsl && ncommon < kCommonMax) {
+      common[i] = 1;
+      ++ncommon;
+    }
+  }
+  if (ncommon == 0) return true;
+  // every slice must hold each common entry exactly once (the shared lists
+  // hold a key at most once per slice); otherwise leave the lists as they are
+  std::atomic<bool> once{true};
+  run_threads(nsl, T, [&](int64_t s0, int64_t s1) {
+    for (int64_t sl = s0; sl < s1 && once.load(std::memory_order_relaxed); ++sl) {
+      int found = 0;
+      for (int64_t e = (*uptr)[sl]; e < (*uptr)[sl + 1]; ++e)
+        if ((*umask)[e] == ~0ull) {
+          const int64_t i = find(key_of(e));
+          if (i >= 0 && common[size_t(i)]) ++found;
+        }
+      if (found != ncommon) once.store(false);
+    }
+  });
+  if (!once.load()) return true;
+  // the common list, in the kernels' order
+  for (int driven = 1; driven >= 0; --driven) {
+    int taken = 0;
+    for (int outside = 1; outside >= 0; --outside) {
+      for (size_t i = 0; i < cand.size(); ++i) {
+        if (!common[i]) continue;
+        if (((cand[i].ct >> cfet::kTermShift) != 0) != (driven == 1)) continue;
+        if (((cand[i].ct & cfet::kColMask) > tmask) != (outside == 1)) continue;
+        double re, im;
+        std::memcpy(&re, &cand[i].re, 8);
+        std::memcpy(&im, &cand[i].im, 8);
+        C->col.push_back(cand[i].ct);
+        C->val.push_back(re);
+        C->val.push_back(im);
+        ++taken;
+      }
+      while (taken % 4) {
+        C->col.push_back(driven ? (1u << cfet::kTermShift) : 0u);
+        C->val.push_back(0.0);
+        C->val.push_back(0.0);
+        ++taken;
+      }
+    }
+    (driven ? C->nd : C->nh) = taken;
+  }
+  // the per-slice lists without them (each slice holds each common entry once)
+  std::vector<int64_t> nptr(nsl + 1, 0);
+  for (int64_t sl = 0; sl < nsl; ++sl) nptr[sl + 1] = nptr[sl] + ((*nuni)[sl] - ncommon);
+  std::vector<uint32_t> oc;
+  std::vector<double> ov;
+  std::vector<uint64_t> om;
+  try {
+    oc.resize(size_t(nptr[nsl]));
+    ov.resize(2 * size_t(nptr[nsl]));
+    om.resize(size_t(nptr[nsl]));
+  } catch (const std::bad_alloc&) {
+    return false;
+  }
+  run_threads(nsl, T, [&](int64_t s0, int64_t s1) {
+    for (int64_t sl = s0; sl < s1; ++sl) {
+      int64_t w = nptr[sl];
+      for (int64_t e = (*uptr)[sl]; e < (*uptr)[sl + 1]; ++e) {
+        if ((*umask)[e] == ~0ull) {
+          const int64_t i = find(key_of(e));
+          if (i >= 0 && common[size_t(i)]) continue;
+        }
+        oc[size_t(w)] = (*ucol)[e];
+        ov[2 * size_t(w)] = (*uval)[2 * e];
+        ov[2 * size_t(w) + 1] = (*uval)[2 * e + 1];
+        om[size_t(w)] = (*umask)[e];
+        ++w;
+      }
+      (*nuni)[sl] = int32_t(nptr[sl + 1] - nptr[sl]);
+    }
+  });
+  ucol->swap(oc);
+  uval->swap(ov);
+  umask->swap(om);
+  uptr->swap(nptr);
+  return true;
+}
+
 // Split of the shared-part layout into two passes (see DevSELLHi).  Applies to
 // operators on 2^nbits rows (nbits >= 8): entries whose offset row ^ col has a
 // bit at or above split_bit = min(16, nbits - 2) leave the first pass, whose
@@ -1355,6 +1507,12 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
     // compact shared lists; the tiled kernels of the split layout read them in
     // groups of four entries
     std::vector<uint64_t> groups1, groups2;
+    CommonList common1, common2;
+    if (staged && split)
+      staged = extract_common(nsl, (1u << sp.tbits) - 1u, nth, &S.nuni, &S.uptr, &S.ucol,
+                              &S.uval, &S.umask, &common1) &&
+               extract_common(n / 64, 0xFFFFFFFFu, nth, &HS.nuni, &HS.uptr, &HS.ucol, &HS.uval,
+                              &HS.umask, &common2);
     if (staged && split)
       staged = arrange_tiled_lists(nsl, (1u << sp.tbits) - 1u, &S.nuni, &S.uptr, &S.ucol,
                                    &S.uval, &S.umask, &groups1) &&
@@ -1431,6 +1589,23 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
         e = hipMemcpy(c->hi.ugroups, groups2.data(), (n / 64) * sizeof(uint64_t),
                       hipMemcpyHostToDevice);
       c->sell_bytes += 8 * nsl + 8 * (n / 64);
+      // the common lists (read once per slice from the scalar cache; counted once)
+      const CommonList* cl[2] = {&common1, &common2};
+      for (int p = 0; p < 2 && e == hipSuccess; ++p) {
+        const size_t nc = cl[p]->col.size();
+        if (nc == 0) continue;
+        uint32_t** dc = p == 0 ? &c->sell.ccolt : &c->hi.ccolt;
+        double2** dv = p == 0 ? &c->sell.cval : &c->hi.cval;
+        e = hipMalloc(dc, nc * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(dv, nc * sizeof(double2));
+        if (e == hipSuccess)
+          e = hipMemcpy(*dc, cl[p]->col.data(), nc * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+          e = hipMemcpy(*dv, cl[p]->val.data(), nc * sizeof(double2), hipMemcpyHostToDevice);
+        (p == 0 ? c->sell.ncd : c->hi.ncd) = cl[p]->nd;
+        (p == 0 ? c->sell.nch : c->hi.nch) = cl[p]->nh;
+        c->sell_bytes += 20 * int64_t(nc);
+      }
     }
     if (split) {
       const int64_t hsl = n / 64;

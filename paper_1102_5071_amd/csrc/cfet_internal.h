@@ -105,6 +105,13 @@ struct DevSELL {
   // (driven terms held by all rows / by some rows, H0 all / some), 16 bits
   // each, group g at bits 16 g.
   uint64_t* ugroups = nullptr;
+  // Split layout only: the entries every row of every slice holds with the
+  // same offset, term and value (e.g. a driven sum of sigma_x with one
+  // coefficient), stored once: ncd of driven terms, then nch of H0, each part
+  // with the entries outside the tile first, padded to whole batches of four.
+  uint32_t* ccolt = nullptr;
+  double2* cval = nullptr;
+  int32_t ncd = 0, nch = 0;
 };
 
 // Second pass of the split shared-part layout (operators on 2^nbits rows whose
@@ -134,6 +141,9 @@ struct DevSELLHi {
   uint64_t* ugroups = nullptr;   // per slice the four group sizes, as in DevSELL
   int64_t* tile_row = nullptr;   // row of the first index of each tile of 2^tbits
                                  // permuted indices (the tile's row bits above tbits)
+  uint32_t* ccolt = nullptr;     // common entries of every slice, as in DevSELL
+  double2* cval = nullptr;
+  int32_t ncd = 0, nch = 0;
 };
 
 int sell_grid(int64_t n);

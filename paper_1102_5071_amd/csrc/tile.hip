@@ -184,6 +184,41 @@ __device__ __forceinline__ void t_group(const CFET_CONST uint32_t* uc, const CFE
 
 // Unweighted sums of a slice's shared entries, by term: (a0r, a0i) over H0's
 // entries, (a1r, a1i) over the driven term's (one driven term: NT = 1).
+// The common entries (held by every row of every slice), unweighted by term:
+// (a1r, a1i) driven, (a0r, a0i) H0.  Every wavefront reads the same few
+// entries, so their scalar loads hit the scalar cache.
+template <bool RV, bool GLOBAL>
+__device__ __forceinline__ void t_common_nt1(const uint32_t* cc, const double2* cv, int ncd,
+                                             int nch, uint64_t lanebit, uint32_t qb, int64_t row,
+                                             uint32_t tmask, const double2* xt,
+                                             const double2* __restrict__ x, double& a0r,
+                                             double& a0i, double& a1r, double& a1i) {
+  const CFET_CONST uint32_t* uc = as_const(cc);
+  const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(cv));
+  t_group<true, RV, GLOBAL>(uc, uv, nullptr, 0, ncd, lanebit, qb, row, tmask, xt, x, a1r, a1i);
+  t_group<true, RV, GLOBAL>(uc, uv, nullptr, ncd, nch, lanebit, qb, row, tmask, xt, x, a0r, a0i);
+}
+
+// The common entries, any number of driven terms: (ar, ai) += w v x.
+template <bool RV, bool GLOBAL>
+__device__ __forceinline__ void t_common_any(const uint32_t* cc, const double2* cv, int nc,
+                                             uint32_t qb, int64_t row, uint32_t tmask,
+                                             const double2* xt, const double2* __restrict__ x,
+                                             const double* wl, double& ar, double& ai) {
+  const CFET_CONST uint32_t* uc = as_const(cc);
+  const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(cv));
+  for (int k = 0; k < nc; ++k) {
+    const uint32_t ct = uc[k];
+    const uint32_t off = ct & kColMask;
+    const double2 xv = (GLOBAL && off > tmask) ? x[row ^ (int64_t)off]
+                                               : t_lds(xt, qb, (off & tmask) << 4);
+    const double w = wl[ct >> kTermShift];
+    const double er = w * uv[k].x, ei = RV ? 0.0 : w * uv[k].y;
+    ar = fma(er, xv.x, fma(-ei, xv.y, ar));
+    ai = fma(er, xv.y, fma(ei, xv.x, ai));
+  }
+}
+
 template <bool RV, bool GLOBAL>
 __device__ __forceinline__ void t_shared_nt1(const CFET_CONST uint32_t* uc,
                                              const CFET_CONST dvec2* uv,
@@ -359,6 +394,11 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
       const uint32_t qb = t_lane_bytes(xt, qloc);
       double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;  // unweighted, by term (NT = 1)
       double ar = 0.0, ai = 0.0;                          // weighted
+      if (NT == 1)
+        t_common_nt1<RV, true>(S.ccolt, S.cval, S.ncd, S.nch, lanebit, qb, row, tmask, xt, x,
+                               a0r, a0i, a1r, a1i);
+      else
+        t_common_any<RV, true>(S.ccolt, S.cval, S.ncd + S.nch, qb, row, tmask, xt, x, wl, ar, ai);
       const int nu = as_const(S.nuni)[slice];
       if (nu > 0) {
         const int64_t ub = as_const(S.uptr)[slice];
@@ -479,18 +519,28 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
       const uint32_t qb = t_lane_bytes(xt, qloc);
       double ar = 0.0, ai = 0.0;
       const int nu = as_const(H.nuni)[slice];
-      if (nu > 0) {
-        const int64_t ub = as_const(H.uptr)[slice];
-        const CFET_CONST uint32_t* uc = as_const(H.ucolt + ub);
-        const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(H.uval) + ub);
-        const CFET_CONST uint64_t* um = as_const(H.umask + ub);
-        if (NT == 1) {
-          double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+      if (NT == 1) {
+        double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+        t_common_nt1<RV, false>(H.ccolt, H.cval, H.ncd, H.nch, lanebit, qb, row, tmask, xt, x,
+                                a0r, a0i, a1r, a1i);
+        if (nu > 0) {
+          const int64_t ub = as_const(H.uptr)[slice];
+          const CFET_CONST uint32_t* uc = as_const(H.ucolt + ub);
+          const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(H.uval) + ub);
+          const CFET_CONST uint64_t* um = as_const(H.umask + ub);
           t_shared_nt1<RV, false>(uc, uv, um, as_const(H.ugroups)[slice], lanebit, qb, row,
                                   tmask, xt, x, a0r, a0i, a1r, a1i);
-          ar = W.w0 * a0r + W.w1 * a1r;
-          ai = W.w0 * a0i + W.w1 * a1i;
-        } else {
+        }
+        ar = W.w0 * a0r + W.w1 * a1r;
+        ai = W.w0 * a0i + W.w1 * a1i;
+      } else {
+        t_common_any<RV, false>(H.ccolt, H.cval, H.ncd + H.nch, qb, row, tmask, xt, x, wl, ar,
+                                ai);
+        if (nu > 0) {
+          const int64_t ub = as_const(H.uptr)[slice];
+          const CFET_CONST uint32_t* uc = as_const(H.ucolt + ub);
+          const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(H.uval) + ub);
+          const CFET_CONST uint64_t* um = as_const(H.umask + ub);
           t_shared_any<RV, false>(uc, uv, um, nu, lanebit, qb, row, tmask, xt, x, wl, ar, ai);
         }
       }
