@@ -200,6 +200,8 @@ void free_ctx(cfet_ctx* c) {
   if (c->hi.uval) (void)hipFree(c->hi.uval);
   if (c->hi.umask) (void)hipFree(c->hi.umask);
   if (c->hi.tile_row) (void)hipFree(c->hi.tile_row);
+  if (c->sell.uhdr) (void)hipFree(c->sell.uhdr);
+  if (c->hi.uhdr) (void)hipFree(c->hi.uhdr);
   if (c->sell.ccolt) (void)hipFree(c->sell.ccolt);
   if (c->sell.cval) (void)hipFree(c->sell.cval);
   if (c->hi.ccolt) (void)hipFree(c->hi.ccolt);
@@ -1588,6 +1590,22 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       if (e == hipSuccess)
         e = hipMemcpy(c->hi.ugroups, groups2.data(), (n / 64) * sizeof(uint64_t),
                       hipMemcpyHostToDevice);
+      // per slice {uptr, ugroups} side by side for the tiled kernels (the group
+      // sizes replace the 8-byte uptr and 4-byte nuni they read otherwise)
+      for (int p = 0; p < 2 && e == hipSuccess; ++p) {
+        const int64_t ns = p == 0 ? nsl : n / 64;
+        const std::vector<int64_t>& up = p == 0 ? S.uptr : HS.uptr;
+        const std::vector<uint64_t>& gr = p == 0 ? groups1 : groups2;
+        std::vector<uint64_t> hdr(2 * size_t(ns));
+        for (int64_t sl = 0; sl < ns; ++sl) {
+          hdr[2 * size_t(sl)] = uint64_t(up[size_t(sl)]);
+          hdr[2 * size_t(sl) + 1] = gr[size_t(sl)];
+        }
+        uint64_t** dh = p == 0 ? &c->sell.uhdr : &c->hi.uhdr;
+        e = hipMalloc(dh, hdr.size() * sizeof(uint64_t));
+        if (e == hipSuccess)
+          e = hipMemcpy(*dh, hdr.data(), hdr.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+      }
       c->sell_bytes += 8 * nsl + 8 * (n / 64);
       // the common lists (read once per slice from the scalar cache; counted once)
       const CommonList* cl[2] = {&common1, &common2};

@@ -112,6 +112,9 @@ struct DevSELL {
   uint32_t* ccolt = nullptr;
   double2* cval = nullptr;
   int32_t ncd = 0, nch = 0;
+  // Split layout only: per slice {uptr, ugroups} side by side (one scalar
+  // load for both).
+  uint64_t* uhdr = nullptr;
 };
 
 // Second pass of the split shared-part layout (operators on 2^nbits rows whose
@@ -144,6 +147,7 @@ struct DevSELLHi {
   uint32_t* ccolt = nullptr;     // common entries of every slice, as in DevSELL
   double2* cval = nullptr;
   int32_t ncd = 0, nch = 0;
+  uint64_t* uhdr = nullptr;      // per slice {uptr, ugroups}, as in DevSELL
 };
 
 int sell_grid(int64_t n);

@@ -184,6 +184,12 @@ __device__ __forceinline__ void t_group(const CFET_CONST uint32_t* uc, const CFE
 
 // Unweighted sums of a slice's shared entries, by term: (a0r, a0i) over H0's
 // entries, (a1r, a1i) over the driven term's (one driven term: NT = 1).
+// Entries of a slice's list: the sum of its four group sizes.
+__device__ __forceinline__ int group_total(uint64_t g) {
+  return (int)(g & 0xFFFF) + (int)((g >> 16) & 0xFFFF) + (int)((g >> 32) & 0xFFFF) +
+         (int)(g >> 48);
+}
+
 // The common entries (held by every row of every slice), unweighted by term:
 // (a1r, a1i) driven, (a0r, a0i) H0.  Every wavefront reads the same few
 // entries, so their scalar loads hit the scalar cache.
@@ -380,9 +386,10 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
         dn = __builtin_nontemporal_load(S.diag + row + WAVES * 64);
       // the first per-row slot is read before the shared entries, so its
       // latency overlaps them
-      const int width = as_const(S.slice_width)[slice];
+      // (operators whose entries are all shared or diagonal have no slots)
+      const int width = S.slots > 0 ? as_const(S.slice_width)[slice] : 0;
       const int len = width > 0 ? S.rowlen[row] : 0;
-      const int64_t base = as_const(S.slice_ptr)[slice];
+      const int64_t base = width > 0 ? as_const(S.slice_ptr)[slice] : 0;
       const uint32_t* __restrict__ cp = S.colt + base + lane;
       const dvec2* __restrict__ vp = reinterpret_cast<const dvec2*>(S.val) + base + lane;
       uint32_t ct0 = 0u;
@@ -399,17 +406,18 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
                                a0r, a0i, a1r, a1i);
       else
         t_common_any<RV, true>(S.ccolt, S.cval, S.ncd + S.nch, qb, row, tmask, xt, x, wl, ar, ai);
-      const int nu = as_const(S.nuni)[slice];
-      if (nu > 0) {
-        const int64_t ub = as_const(S.uptr)[slice];
+      const int64_t ub = (int64_t)as_const(S.uhdr)[2 * slice];
+      const uint64_t groups = as_const(S.uhdr)[2 * slice + 1];
+      if (groups != 0) {
         const CFET_CONST uint32_t* uc = as_const(S.ucolt + ub);
         const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(S.uval) + ub);
         const CFET_CONST uint64_t* um = as_const(S.umask + ub);
         if (NT == 1)
-          t_shared_nt1<RV, true>(uc, uv, um, as_const(S.ugroups)[slice], lanebit, qb, row, tmask,
-                                 xt, x, a0r, a0i, a1r, a1i);
+          t_shared_nt1<RV, true>(uc, uv, um, groups, lanebit, qb, row, tmask, xt, x, a0r, a0i,
+                                 a1r, a1i);
         else
-          t_shared_any<RV, true>(uc, uv, um, nu, lanebit, qb, row, tmask, xt, x, wl, ar, ai);
+          t_shared_any<RV, true>(uc, uv, um, group_total(groups), lanebit, qb, row, tmask, xt, x,
+                                 wl, ar, ai);
       }
       for (int k = 0; k < len; ++k) {
         uint32_t ct = ct0;
@@ -518,31 +526,26 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
       }
       const uint32_t qb = t_lane_bytes(xt, qloc);
       double ar = 0.0, ai = 0.0;
-      const int nu = as_const(H.nuni)[slice];
+      const int64_t ub = (int64_t)as_const(H.uhdr)[2 * slice];
+      const uint64_t groups = as_const(H.uhdr)[2 * slice + 1];
+      const CFET_CONST uint32_t* uc = as_const(H.ucolt + ub);
+      const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(H.uval) + ub);
+      const CFET_CONST uint64_t* um = as_const(H.umask + ub);
       if (NT == 1) {
         double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
         t_common_nt1<RV, false>(H.ccolt, H.cval, H.ncd, H.nch, lanebit, qb, row, tmask, xt, x,
                                 a0r, a0i, a1r, a1i);
-        if (nu > 0) {
-          const int64_t ub = as_const(H.uptr)[slice];
-          const CFET_CONST uint32_t* uc = as_const(H.ucolt + ub);
-          const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(H.uval) + ub);
-          const CFET_CONST uint64_t* um = as_const(H.umask + ub);
-          t_shared_nt1<RV, false>(uc, uv, um, as_const(H.ugroups)[slice], lanebit, qb, row,
-                                  tmask, xt, x, a0r, a0i, a1r, a1i);
-        }
+        if (groups != 0)
+          t_shared_nt1<RV, false>(uc, uv, um, groups, lanebit, qb, row, tmask, xt, x, a0r, a0i,
+                                  a1r, a1i);
         ar = W.w0 * a0r + W.w1 * a1r;
         ai = W.w0 * a0i + W.w1 * a1i;
       } else {
         t_common_any<RV, false>(H.ccolt, H.cval, H.ncd + H.nch, qb, row, tmask, xt, x, wl, ar,
                                 ai);
-        if (nu > 0) {
-          const int64_t ub = as_const(H.uptr)[slice];
-          const CFET_CONST uint32_t* uc = as_const(H.ucolt + ub);
-          const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(H.uval) + ub);
-          const CFET_CONST uint64_t* um = as_const(H.umask + ub);
-          t_shared_any<RV, false>(uc, uv, um, nu, lanebit, qb, row, tmask, xt, x, wl, ar, ai);
-        }
+        if (groups != 0)
+          t_shared_any<RV, false>(uc, uv, um, group_total(groups), lanebit, qb, row, tmask, xt,
+                                  x, wl, ar, ai);
       }
       if (LZ) {
         ar *= inv;
