@@ -200,6 +200,10 @@ void free_ctx(cfet_ctx* c) {
   if (c->hi.uval) (void)hipFree(c->hi.uval);
   if (c->hi.umask) (void)hipFree(c->hi.umask);
   if (c->hi.tile_row) (void)hipFree(c->hi.tile_row);
+  if (c->sell.urec) (void)hipFree(c->sell.urec);
+  if (c->hi.urec) (void)hipFree(c->hi.urec);
+  if (c->sell.crec) (void)hipFree(c->sell.crec);
+  if (c->hi.crec) (void)hipFree(c->hi.crec);
   if (c->sell.uhdr) (void)hipFree(c->sell.uhdr);
   if (c->hi.uhdr) (void)hipFree(c->hi.uhdr);
   if (c->sell.ccolt) (void)hipFree(c->sell.ccolt);
@@ -1663,7 +1667,35 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
       for (size_t q = 1; q < S.sval.size() && real; q += 2) real = (S.sval[q] == 0.0);
       for (size_t q = 1; q < S.uval.size() && real; q += 2) real = (S.uval[q] == 0.0);
       for (size_t q = 1; q < HS.uval.size() && real; q += 2) real = (HS.uval[q] == 0.0);
+      for (size_t q = 1; q < common1.val.size() && real; q += 2) real = (common1.val[q] == 0.0);
+      for (size_t q = 1; q < common2.val.size() && real; q += 2) real = (common2.val[q] == 0.0);
       c->tile_real = real;
+      // real values: the lists also as 64-byte records of four entries
+      auto records = [&](const std::vector<uint32_t>& col, const std::vector<double>& val,
+                         cfet::Rec4** out) -> hipError_t {
+        const size_t nrec = (col.size() + 3) / 4;
+        if (nrec == 0) return hipSuccess;
+        std::vector<cfet::Rec4> rec(nrec);
+        for (size_t i = 0; i < nrec; ++i) {
+          std::memset(&rec[i], 0, sizeof(cfet::Rec4));
+          for (int u = 0; u < 4; ++u) {
+            const size_t e = 4 * i + size_t(u);
+            if (e >= col.size()) break;
+            rec[i].col[u] = col[e];
+            rec[i].val[u] = val[2 * e];
+          }
+        }
+        hipError_t er = hipMalloc(out, nrec * sizeof(cfet::Rec4));
+        if (er == hipSuccess)
+          er = hipMemcpy(*out, rec.data(), nrec * sizeof(cfet::Rec4), hipMemcpyHostToDevice);
+        return er;
+      };
+      if (real) {
+        if (e == hipSuccess) e = records(S.ucol, S.uval, &c->sell.urec);
+        if (e == hipSuccess) e = records(HS.ucol, HS.uval, &c->hi.urec);
+        if (e == hipSuccess) e = records(common1.col, common1.val, &c->sell.crec);
+        if (e == hipSuccess) e = records(common2.col, common2.val, &c->hi.crec);
+      }
       if (e == hipSuccess) e = cfet::tile_prepare();
     }
     c->use_sell = true;

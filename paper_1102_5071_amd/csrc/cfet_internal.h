@@ -78,6 +78,15 @@ struct DevCSR {
 
 // Device copy of the operator in sliced-ELL form (sell.hip): slices of 64
 // consecutive rows stored column-major and padded to the slice's longest row.
+// Four entries of a shared list in one 64-byte record (the tiled kernels'
+// real-valued form reads a batch of four with one scalar load): offsets |
+// term, real values.
+struct alignas(64) Rec4 {
+  uint32_t col[4];
+  double val[4];
+  uint32_t pad[4];
+};
+
 struct DevSELL {
   int64_t n = 0;
   int64_t* slice_ptr = nullptr;  // first slot of each slice
@@ -115,6 +124,10 @@ struct DevSELL {
   // Split layout only: per slice {uptr, ugroups} side by side (one scalar
   // load for both).
   uint64_t* uhdr = nullptr;
+  // Split layout with real values only: the shared lists (record i holds
+  // entries 4 i .. 4 i + 3) and the common list as records.
+  Rec4* urec = nullptr;
+  Rec4* crec = nullptr;
 };
 
 // Second pass of the split shared-part layout (operators on 2^nbits rows whose
@@ -148,6 +161,8 @@ struct DevSELLHi {
   double2* cval = nullptr;
   int32_t ncd = 0, nch = 0;
   uint64_t* uhdr = nullptr;      // per slice {uptr, ugroups}, as in DevSELL
+  Rec4* urec = nullptr;          // records, as in DevSELL
+  Rec4* crec = nullptr;
 };
 
 int sell_grid(int64_t n);

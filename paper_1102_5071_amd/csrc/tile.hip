@@ -184,6 +184,47 @@ __device__ __forceinline__ void t_group(const CFET_CONST uint32_t* uc, const CFE
 
 // Unweighted sums of a slice's shared entries, by term: (a0r, a0i) over H0's
 // entries, (a1r, a1i) over the driven term's (one driven term: NT = 1).
+// t_group for real values from 64-byte records (one scalar load per batch
+// of four; record k / 4 holds entries k .. k + 3, k a multiple of four).
+template <bool FULL, bool GLOBAL>
+__device__ __forceinline__ void t_group_rec(const CFET_CONST Rec4* rec,
+                                            const CFET_CONST uint64_t* um, int k0, int cnt,
+                                            uint64_t lanebit, uint32_t qb, int64_t row,
+                                            uint32_t tmask, const double2* xt,
+                                            const double2* __restrict__ x, double& ar,
+                                            double& ai) {
+  typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+  for (int k = k0; k < k0 + cnt; k += 4) {
+    // the whole record in one load
+    const u32x16 w = *reinterpret_cast<const CFET_CONST u32x16*>(rec + (k >> 2));
+    uint32_t off[4];
+    uint64_t m[4];
+    double v[4];
+    double2 xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      off[u] = w[u] & kColMask;
+      m[u] = FULL ? ~0ull : um[k + u];
+      v[u] = __builtin_bit_cast(double, (uint64_t)w[4 + 2 * u] | ((uint64_t)w[5 + 2 * u] << 32));
+    }
+    if (GLOBAL && off[0] > tmask) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        xv[u] = x[(FULL || (m[u] & lanebit)) ? row ^ (int64_t)off[u] : row];
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = t_lds(xt, qb, (off[u] & tmask) << 4);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (FULL || (m[u] & lanebit)) {
+        ar = fma(v[u], xv[u].x, ar);
+        ai = fma(v[u], xv[u].y, ai);
+      }
+    }
+  }
+}
+
 // Entries of a slice's list: the sum of its four group sizes.
 __device__ __forceinline__ int group_total(uint64_t g) {
   return (int)(g & 0xFFFF) + (int)((g >> 16) & 0xFFFF) + (int)((g >> 32) & 0xFFFF) +
@@ -194,11 +235,18 @@ __device__ __forceinline__ int group_total(uint64_t g) {
 // (a1r, a1i) driven, (a0r, a0i) H0.  Every wavefront reads the same few
 // entries, so their scalar loads hit the scalar cache.
 template <bool RV, bool GLOBAL>
-__device__ __forceinline__ void t_common_nt1(const uint32_t* cc, const double2* cv, int ncd,
-                                             int nch, uint64_t lanebit, uint32_t qb, int64_t row,
+__device__ __forceinline__ void t_common_nt1(const uint32_t* cc, const double2* cv,
+                                             const Rec4* crec, int ncd, int nch,
+                                             uint64_t lanebit, uint32_t qb, int64_t row,
                                              uint32_t tmask, const double2* xt,
                                              const double2* __restrict__ x, double& a0r,
                                              double& a0i, double& a1r, double& a1i) {
+  if (RV) {
+    const CFET_CONST Rec4* rc = as_const(crec);
+    t_group_rec<true, GLOBAL>(rc, nullptr, 0, ncd, lanebit, qb, row, tmask, xt, x, a1r, a1i);
+    t_group_rec<true, GLOBAL>(rc, nullptr, ncd, nch, lanebit, qb, row, tmask, xt, x, a0r, a0i);
+    return;
+  }
   const CFET_CONST uint32_t* uc = as_const(cc);
   const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(cv));
   t_group<true, RV, GLOBAL>(uc, uv, nullptr, 0, ncd, lanebit, qb, row, tmask, xt, x, a1r, a1i);
@@ -228,13 +276,22 @@ __device__ __forceinline__ void t_common_any(const uint32_t* cc, const double2* 
 template <bool RV, bool GLOBAL>
 __device__ __forceinline__ void t_shared_nt1(const CFET_CONST uint32_t* uc,
                                              const CFET_CONST dvec2* uv,
-                                             const CFET_CONST uint64_t* um, uint64_t groups,
+                                             const CFET_CONST uint64_t* um,
+                                             const CFET_CONST Rec4* rec, uint64_t groups,
                                              uint64_t lanebit, uint32_t qb, int64_t row,
                                              uint32_t tmask, const double2* xt,
                                              const double2* __restrict__ x, double& a0r,
                                              double& a0i, double& a1r, double& a1i) {
   const int c0 = (int)(groups & 0xFFFF), c1 = (int)((groups >> 16) & 0xFFFF);
   const int c2 = (int)((groups >> 32) & 0xFFFF), c3 = (int)(groups >> 48);
+  if (RV) {
+    t_group_rec<true, GLOBAL>(rec, um, 0, c0, lanebit, qb, row, tmask, xt, x, a1r, a1i);
+    t_group_rec<false, GLOBAL>(rec, um, c0, c1, lanebit, qb, row, tmask, xt, x, a1r, a1i);
+    t_group_rec<true, GLOBAL>(rec, um, c0 + c1, c2, lanebit, qb, row, tmask, xt, x, a0r, a0i);
+    t_group_rec<false, GLOBAL>(rec, um, c0 + c1 + c2, c3, lanebit, qb, row, tmask, xt, x, a0r,
+                               a0i);
+    return;
+  }
   t_group<true, RV, GLOBAL>(uc, uv, um, 0, c0, lanebit, qb, row, tmask, xt, x, a1r, a1i);
   t_group<false, RV, GLOBAL>(uc, uv, um, c0, c1, lanebit, qb, row, tmask, xt, x, a1r, a1i);
   t_group<true, RV, GLOBAL>(uc, uv, um, c0 + c1, c2, lanebit, qb, row, tmask, xt, x, a0r, a0i);
@@ -402,8 +459,8 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
       double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;  // unweighted, by term (NT = 1)
       double ar = 0.0, ai = 0.0;                          // weighted
       if (NT == 1)
-        t_common_nt1<RV, true>(S.ccolt, S.cval, S.ncd, S.nch, lanebit, qb, row, tmask, xt, x,
-                               a0r, a0i, a1r, a1i);
+        t_common_nt1<RV, true>(S.ccolt, S.cval, S.crec, S.ncd, S.nch, lanebit, qb, row, tmask,
+                               xt, x, a0r, a0i, a1r, a1i);
       else
         t_common_any<RV, true>(S.ccolt, S.cval, S.ncd + S.nch, qb, row, tmask, xt, x, wl, ar, ai);
       const int64_t ub = (int64_t)as_const(S.uhdr)[2 * slice];
@@ -413,8 +470,8 @@ __global__ __launch_bounds__(THREADS) void k_tile_pass1(
         const CFET_CONST dvec2* uv = as_const(reinterpret_cast<const dvec2*>(S.uval) + ub);
         const CFET_CONST uint64_t* um = as_const(S.umask + ub);
         if (NT == 1)
-          t_shared_nt1<RV, true>(uc, uv, um, groups, lanebit, qb, row, tmask, xt, x, a0r, a0i,
-                                 a1r, a1i);
+          t_shared_nt1<RV, true>(uc, uv, um, as_const(S.urec + (ub >> 2)), groups, lanebit, qb,
+                                 row, tmask, xt, x, a0r, a0i, a1r, a1i);
         else
           t_shared_any<RV, true>(uc, uv, um, group_total(groups), lanebit, qb, row, tmask, xt, x,
                                  wl, ar, ai);
@@ -533,11 +590,11 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(8, 8)))
       const CFET_CONST uint64_t* um = as_const(H.umask + ub);
       if (NT == 1) {
         double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
-        t_common_nt1<RV, false>(H.ccolt, H.cval, H.ncd, H.nch, lanebit, qb, row, tmask, xt, x,
-                                a0r, a0i, a1r, a1i);
+        t_common_nt1<RV, false>(H.ccolt, H.cval, H.crec, H.ncd, H.nch, lanebit, qb, row, tmask,
+                                xt, x, a0r, a0i, a1r, a1i);
         if (groups != 0)
-          t_shared_nt1<RV, false>(uc, uv, um, groups, lanebit, qb, row, tmask, xt, x, a0r, a0i,
-                                  a1r, a1i);
+          t_shared_nt1<RV, false>(uc, uv, um, as_const(H.urec + (ub >> 2)), groups, lanebit, qb,
+                                  row, tmask, xt, x, a0r, a0i, a1r, a1i);
         ar = W.w0 * a0r + W.w1 * a1r;
         ai = W.w0 * a0i + W.w1 * a1i;
       } else {
