@@ -319,7 +319,7 @@ struct PersistArgs {
   double2* psi;
   double2* basis;           // basis vector j >= 1 at basis + (j-1)*n
   double2* zbuf;            // 2 * n: H u_k of the last two Lanczos steps
-  double* part;             // 2 parities x 2 sums x gridDim partial sums
+  double* part;             // 2 parities x gridDim records of two partial sums
   unsigned long long* bar;  // barrier counters (persistent_barrier_words(), reset per launch)
   int* fault;               // set when a barrier wait times out
   DevStats* stats;

@@ -123,18 +123,6 @@ __device__ __forceinline__ void vst(double2* base, int64_t i, int64_t n, double2
   __builtin_amdgcn_raw_buffer_store_b128(v, vec_rsrc(base, n), (int)(i * 16), 0, kCpolDevice);
 }
 
-__device__ __forceinline__ double dload(const double* p) {
-  const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)v);
-}
-
-__device__ __forceinline__ void dstore(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
-                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Barrier state: words kBarGroupStride*(1+g) = arrival counter of group g
 // (blocks b with b % groups == g), one 128-byte line each, so arrivals of
 // different groups do not serialise on one address; word 0 is unused.
@@ -198,6 +186,8 @@ struct Shared {
   // the single workgroup's per-iteration sums: two alternating sets of
   // per-wavefront values (first sum at [w], second at [kRedB + w])
   double red2[2][2 * kRedB];
+  // per-wavefront values of the cross-block re-sum (first sum at [w], second at [kRedB + w])
+  double pr[2 * kRedB];
   double alpha[kMaxM];
   double beta[kMaxM];
   double inv[kMaxM];
@@ -272,28 +262,45 @@ __device__ __forceinline__ void p_block_sum2_1b(double& a, double& b, double (*r
   parity ^= 1;
 }
 
-// Global sums of (a, b) over all threads of all blocks.  Returns false on a fault.
-template <bool SINGLE>
-__device__ __forceinline__ bool all_reduce2(double& a, double& b, const PersistArgs& A, Shared& sh,
-                                            unsigned long long& epoch, int& pc) {
-  p_block_sum2(a, b, sh.red);
-  if (SINGLE) return true;
-  double* P = A.part + (size_t)(pc & 1) * 2 * gridDim.x;
-  if (threadIdx.x == 0) {
-    dstore(P + 2 * blockIdx.x, a);
-    dstore(P + 2 * blockIdx.x + 1, b);
+// Cross-block sums.  Each block publishes its two partial sums as one
+// 16-byte record (set `ph & 1` of A.part, record blockIdx.x); after the grid
+// barrier every block re-sums all records in the same fixed order: thread t
+// loads record t (the launch has at most as many blocks as a block has
+// threads), the wavefronts reduce with the DPP sum, and every thread adds the
+// per-wavefront values in wavefront order, so all blocks hold bit-identical
+// totals.  The record load is issued before the gathers of the next phase,
+// which are issued unconditionally, so waiting for the record does not wait
+// for them.
+__device__ __forceinline__ void publish_partial(const PersistArgs& A, int ph, double a, double b) {
+  double2* P = reinterpret_cast<double2*>(A.part) + (size_t)(ph & 1) * gridDim.x;
+  vst<false>(P, blockIdx.x, gridDim.x, make_double2(a, b));
+}
+
+__device__ __forceinline__ void resum_issue(const PersistArgs& A, int ph, double2& pv) {
+  const double2* P = reinterpret_cast<const double2*>(A.part) + (size_t)(ph & 1) * gridDim.x;
+  // threads past the last record read 0 (outside the buffer's records)
+  pv = vld<false>(P, threadIdx.x, gridDim.x);
+}
+
+// BLOCK: the block size (a compile-time constant: reading blockDim is a
+// memory load, and waiting for it would wait for the gathers in flight)
+template <int BLOCK>
+__device__ __forceinline__ void resum_finish(double2 pv, Shared& sh, double& a, double& b) {
+  double sa = pv.x, sb = pv.y;
+  sa = p_wave_sum(sa);
+  sb = p_wave_sum(sb);
+  if ((threadIdx.x & 63) == 0) {
+    sh.pr[threadIdx.x >> 6] = sa;
+    sh.pr[kRedB + (threadIdx.x >> 6)] = sb;
   }
-  if (!grid_barrier(A.bar, A.fault, epoch, A.spin_limit, &sh.ok)) return false;
-  pc += 1;
-  double sa = 0.0, sb = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
-    sa += dload(P + 2 * i);
-    sb += dload(P + 2 * i + 1);
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+  for (int w = 0; w < BLOCK / 64; ++w) {
+    ta += sh.pr[w];
+    tb += sh.pr[kRedB + w];
   }
-  a = sa;
-  b = sb;
-  p_block_sum2(a, b, sh.red);
-  return true;
+  a = ta;
+  b = tb;
 }
 
 // Segment timer (block 0, thread 0, only when A.timing is set).
@@ -425,8 +432,12 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
   // u_{k-1} and u_{k-2} of such a column are the running copies g1, g2 that
   // this lane formed itself in the two phases before, with the same fused
   // multiply-adds as the column's owner, so they equal the owner's values bit
-  // for bit (by induction from u_0).
-  auto gather = [&](int k) {
+  // for bit (by induction from u_0).  Every entry issues its load (no branch,
+  // so the compiler can count the loads in flight): an entry that needs none
+  // reads index n, outside the buffer's records, which returns 0 without a
+  // memory access; its register is never read.  live = false: no entry needs
+  // a value (the phase after the last product).
+  auto gather = [&](int k, bool live) {
     if (SINGLE) return;
     const double2* __restrict__ a0 = psi;
     const double2* __restrict__ az = Zb(k - 1);
@@ -434,11 +445,10 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
     for (int p = 0; p < PMAX; ++p) {
 #pragma unroll
       for (int q = 0; q < QMAX; ++q) {
-        if (rowp[p] >= 0 && q < cnt[p] && !((lmask[p] >> q) & 1u)) {
-          const int64_t c = ccol[p][q] & kColMask;
-          if (k == 0) g1[p][q] = vld<SINGLE>(a0, c, n);
-          else gz[p][q] = vld<SINGLE>(az, c, n);
-        }
+        const bool need = live && rowp[p] >= 0 && q < cnt[p] && !((lmask[p] >> q) & 1u);
+        const int64_t c = need ? (int64_t)(ccol[p][q] & kColMask) : n;
+        if (k == 0) g1[p][q] = vld<SINGLE>(a0, c, n);
+        else gz[p][q] = vld<SINGLE>(az, c, n);
       }
     }
   };
@@ -474,35 +484,17 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
           if (A.save) A.save[eidx * n + rowp[p]] = u1[p];  // the state before this exponential
         }
       __syncthreads();
-      gather(0);
+      gather(0, true);
       for (int k = 0; k <= m; ++k) {
         if (k >= 1) {
           tm.lap(A.stats, 1);
           // ---- reduction of phase k-1; the gathers of phase k fly meanwhile
           if (!SINGLE) {
-            // wave 0 re-sums the block partials in a fixed order (the same in
-            // every block); the loads are issued before the gathers so that
-            // waiting for them does not wait for the gathers
-            double sa = 0.0, sb = 0.0;
-            if (threadIdx.x < 64) {
-              const double* P = A.part + (size_t)((pc - 1) & 1) * 2 * gridDim.x;
-              for (int t = threadIdx.x; t < (int)gridDim.x; t += 64) {
-                sa += dload(P + 2 * t);
-                sb += dload(P + 2 * t + 1);
-              }
-            }
-            if (k < m) gather(k);
-            if (threadIdx.x < 64) {
-              sa = p_wave_sum(sa);
-              sb = p_wave_sum(sb);
-              if (threadIdx.x == 0) {
-                sh.red[kRedA] = sa;
-                sh.red[kRedA + 1] = sb;
-              }
-            }
-            __syncthreads();
-            S1 = sh.red[kRedA];
-            S2 = sh.red[kRedA + 1];
+            // every block re-sums the block partials in the same fixed order
+            double2 pv;
+            resum_issue(A, pc - 1, pv);
+            gather(k, k < m);
+            resum_finish<BLOCK>(pv, sh, S1, S2);
           }
           const double nu = sqrt(S2);
           if (k == 1) {
@@ -667,15 +659,13 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
             sh.red[kRedB + (threadIdx.x >> 6)] = s_uu;
           }
           __syncthreads();
-          double* P = A.part + (size_t)(pc & 1) * 2 * gridDim.x;
           if (threadIdx.x == 0) {
             double ta = 0.0, tb = 0.0;
             for (int wv = 0; wv < BLOCK / 64; ++wv) {
               ta += sh.red[wv];
               tb += sh.red[kRedB + wv];
             }
-            dstore(P + 2 * blockIdx.x, ta);
-            dstore(P + 2 * blockIdx.x + 1, tb);
+            publish_partial(A, pc, ta, tb);
           }
           if (!grid_barrier(A.bar, A.fault, epoch, A.spin_limit, &sh.ok)) {
             ok = false;
@@ -785,13 +775,11 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
       if (lane == 0 && rowp[p] >= 0) s1 += u1[p].x * u1[p].x + u1[p].y * u1[p].y;
     p_block_sum2(s0, s1, sh.red);
     if (!SINGLE) {
-      double* P = A.part + (size_t)(pc & 1) * 2 * gridDim.x;
-      if (threadIdx.x == 0) dstore(P + 2 * blockIdx.x + 1, s1);
+      if (threadIdx.x == 0) publish_partial(A, pc, s0, s1);
       if (grid_barrier(A.bar, A.fault, epoch, A.spin_limit, &sh.ok)) {
-        double sb = 0.0;
-        for (int t = threadIdx.x; t < (int)gridDim.x; t += blockDim.x) sb += dload(P + 2 * t + 1);
-        p_block_sum2(s0, sb, sh.red);
-        s1 = sb;
+        double2 pv;
+        resum_issue(A, pc, pv);
+        resum_finish<BLOCK>(pv, sh, s0, s1);
       } else {
         ok = false;
       }
@@ -917,6 +905,8 @@ hipError_t launch_persistent(const PersistArgs& args, int preset, bool single, i
   PersistArgs a = args;
   void* kargs[] = {&a};
   const int block = persistent_block_threads(preset, single);
+  // the cross-block re-sum loads one partial record per thread
+  if (!single && nblocks > block) return hipErrorInvalidValue;
   if (single) {
     e = hipLaunchKernel(fn, dim3(1), dim3(block), kargs, 0, st);
   } else {
