@@ -24,6 +24,7 @@
 #include <cmath>
 
 #include "cfet_internal.h"
+#include "partials.hpp"
 #include "tridiag.hpp"
 
 namespace cfet {
@@ -56,10 +57,10 @@ __device__ double block_sum(double v, double* red) {
   return red[16];
 }
 
+// THREADS: the kernel's block size
+template <int THREADS>
 __device__ double sum_partials(const double* __restrict__ part, int np, double* red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
-  return block_sum(s, red);
+  return block_sum(thread_partials<THREADS>(part, np), red);
 }
 
 __device__ __forceinline__ bool block0_thread0() { return blockIdx.x == 0 && threadIdx.x == 0; }
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_spmv(
     if (block0_thread0()) S->brk[j] = 1;
     return;
   }
-  const double nrm2 = sum_partials(part_in, np_in, red);
+  const double nrm2 = sum_partials<kBlock>(part_in, np_in, red);
   double inv;
   if (j == 0) {
     const double b0 = sqrt(nrm2);
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_axpy(int64_t n, const double2* __
                                                     int j) {
   __shared__ double red[17];
   if (S->brk[j]) return;
-  const double alpha = sum_partials(part_in, np_in, red);
+  const double alpha = sum_partials<kBlock>(part_in, np_in, red);
   if (block0_thread0()) S->alpha[j] = alpha;
   const double ca = alpha * S->inv_nrm[j];
   const double cb = (j > 0) ? S->beta[j - 1] * S->inv_nrm[j - 1] : 0.0;
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(64) void k_lz_small(const double* __restrict__ part
   int meff;
   double alast = 0.0;
   if (!done) {
-    alast = sum_partials(part_in, np_in, red);
+    alast = sum_partials<64>(part_in, np_in, red);
     meff = m;
   } else {
     meff = S->m_eff;
@@ -413,7 +414,7 @@ __global__ void k_stats_init(DevStats* st) {
 __global__ __launch_bounds__(kBlock) void k_final_norm(const double* __restrict__ part, int np,
                                                        DevStats* st) {
   __shared__ double red[17];
-  const double s = sum_partials(part, np, red);
+  const double s = sum_partials<kBlock>(part, np, red);
   if (threadIdx.x == 0) st->last_norm2 = s;
 }
 

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cfet_internal.h"
+#include "partials.hpp"
 
 namespace cfet {
 
@@ -54,9 +55,7 @@ __device__ double s_block_sum(double v, double* red) {
 }
 
 __device__ double s_sum_partials(const double* __restrict__ part, int np, double* red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
-  return s_block_sum(s, red);
+  return s_block_sum(thread_partials<kSellBlock>(part, np), red);
 }
 
 template <int NT>

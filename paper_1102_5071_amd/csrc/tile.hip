@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "cfet_internal.h"
+#include "partials.hpp"
 
 namespace cfet {
 
@@ -74,9 +75,7 @@ __device__ double t_block_sum(double v, double* red) {
 
 template <int WAVES>
 __device__ double t_sum_partials(const double* __restrict__ part, int np, double* red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
-  return t_block_sum<WAVES>(s, red);
+  return t_block_sum<WAVES>(thread_partials<64 * WAVES>(part, np), red);
 }
 
 // The layout arrays are not written while the kernels run: reading them
