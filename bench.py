@@ -219,7 +219,8 @@ def run_batched(args):
     log(f"timed: {elapsed * 1e3:.1f} ms for {K} steps x {nin} trajectories -> "
         f"{rate:.1f} trajectory-steps/s; Krylov dimension {st1['min_m_eff']}..{st1['max_m_eff']}, "
         f"{mv.sum() / (nin * K * 2):.2f} H applications per exponential, unroll {st1['unroll']}, "
-        f"graph {st1['graph']}, create-time layout timing {st1['tune_us']}")
+        f"block {st1['block_threads']} threads, graph {st1['graph']}, "
+        f"create-time layout timing {st1['tune_us']}")
     # algorithmic bytes, vectors only (shared operators excluded: a lower bound)
     dims = np.array(P.dims, dtype=np.float64)
     expos = 2 * K
@@ -303,7 +304,9 @@ def run_batched(args):
                        round(float(mv.sum()) / (nin * K * 2), 3),
                    "plain_path_trajectory_steps_per_s": (round(plain_rate, 3)
                                                          if plain_rate else None),
-                   "batched_over_plain": round(rate / plain_rate, 3) if plain_rate else None},
+                   "batched_over_plain": round(rate / plain_rate, 3) if plain_rate else None,
+                   "launch_layout": {"block_threads": st1["block_threads"],
+                                     "rows_per_lane": st1["unroll"]}},
         "roofline": {"bound": "hbm", "kernel": "batched step (all kernels, vector bytes only)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -79,7 +79,7 @@ class _BatchStats(ctypes.Structure):
                 ("matvecs", c_int64), ("exponentials", c_int64), ("breakdowns", c_int64),
                 ("early_stops", c_int64), ("min_m_eff", c_int32), ("max_m_eff", c_int32),
                 ("status", c_int32), ("unroll", c_int32), ("graph", c_int32),
-                ("reserved", c_int32), ("tune_us", c_double * 4)]
+                ("block_threads", c_int32), ("tune_us", c_double * 12)]
 
 
 BATCH_NO_GRAPH = 0x1000

@@ -78,6 +78,7 @@ __device__ __forceinline__ RowMap row_map(const BGroup& gr, int g, int lb) {
 // Sum v over the lanes of this block that serve instance j (fixed order) and
 // write it to the partial of (slot, block within the group): the partials of
 // one instance are contiguous, so its reduction reads them coalesced.
+template <int W>
 __device__ void block_partial(double v, const BGroup& gr, double* red, const BLaunch& L,
                               int lb) {
 #pragma unroll
@@ -88,7 +89,7 @@ __device__ void block_partial(double v, const BGroup& gr, double* red, const BLa
   __syncthreads();
   if (threadIdx.x < gr.B) {
     double t = 0.0;
-    for (int i = 0; i < kBatchBlock / 64; ++i) t += red[i * 64 + threadIdx.x];
+    for (int i = 0; i < W; ++i) t += red[i * 64 + threadIdx.x];
     L.part[(int64_t)(gr.slot0 + threadIdx.x) * L.pstride + (lb - gr.block0)] = t;
   }
 }
@@ -101,8 +102,9 @@ __device__ __forceinline__ bool group_idle(const BGroup& gr, const int* done) {
 }
 
 // ---- START / COMBINE partial sums: ||V_0||^2 of every instance
-__global__ __launch_bounds__(kBatchBlock) void k_b_norm(BLaunch L) {
-  __shared__ double red[4 * 64];
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_b_norm(BLaunch L) {
+  __shared__ double red[W * 64];
   const int lb = logical_block(L.total_blocks);
   if (lb >= L.total_blocks) return;
   const int g = find_group(L.groups, L.ngroups, lb);
@@ -111,17 +113,18 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_norm(BLaunch L) {
   double s = 0.0;
   if (M.lane_ok) {
     const double2* __restrict__ x = L.V + gr.voff;
-    for (int64_t r = M.r0 + M.sub; r < M.r1; r += 4 * M.rpw) {
+    for (int64_t r = M.r0 + M.sub; r < M.r1; r += W * M.rpw) {
       const double2 v = x[r * gr.B + M.j];
       s += v.x * v.x + v.y * v.y;
     }
   }
-  block_partial(s, gr, red, L, lb);
+  block_partial<W>(s, gr, red, L, lb);
 }
 
 // ---- y = H_w v_k (v_k = V_k * inv_k) and partials of Re<v_k, y>
-__global__ __launch_bounds__(kBatchBlock) void k_b_spmm(BLaunch L, int k) {
-  __shared__ double red[4 * 64];
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_b_spmm(BLaunch L, int k) {
+  __shared__ double red[W * 64];
   __shared__ double wl[kBatchMaxGroup][kBatchMaxK1];
   const int lb = logical_block(L.total_blocks);
   if (lb >= L.total_blocks) return;
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_spmm(BLaunch L, int k) {
   const BState* st = L.st;
   const int K1 = st->K1;
   const long long cur = st->cursor;
-  for (int t = threadIdx.x; t < gr.B * K1; t += blockDim.x) {
+  for (int t = threadIdx.x; t < gr.B * K1; t += 64 * W) {
     const int jj = t / K1, tt = t % K1;
     wl[jj][tt] = st->wts[((int64_t)cur * st->nslots + gr.slot0 + jj) * K1 + tt];
   }
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_spmm(BLaunch L, int k) {
     const int B = gr.B;
     const int j = M.j;
     const double* __restrict__ wt = wl[j];
-    for (int64_t r = M.r0 + M.sub; r < M.r1; r += 4 * M.rpw) {
+    for (int64_t r = M.r0 + M.sub; r < M.r1; r += W * M.rpw) {
       double ar = 0.0, ai = 0.0;
       int64_t e = gr.rowptr[r];
       const int64_t e1 = gr.rowptr[r + 1];
@@ -199,12 +202,13 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_spmm(BLaunch L, int k) {
       s += (xo.x * yv.x + xo.y * yv.y) * invk;
     }
   }
-  block_partial(s, gr, red, L, lb);
+  block_partial<W>(s, gr, red, L, lb);
 }
 
 // ---- w = y - alpha_k v_k - beta_{k-1} v_{k-1}, stored as V_{k+1}; partials of ||w||^2
-__global__ __launch_bounds__(kBatchBlock) void k_b_axpy(BLaunch L, int k) {
-  __shared__ double red[4 * 64];
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_b_axpy(BLaunch L, int k) {
+  __shared__ double red[W * 64];
   const int lb = logical_block(L.total_blocks);
   if (lb >= L.total_blocks) return;
   const int g = find_group(L.groups, L.ngroups, lb);
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_axpy(BLaunch L, int k) {
     const double2* __restrict__ y = L.Y + gr.voff;
     double2* __restrict__ w = L.V + (int64_t)(k + 1) * L.ntot + gr.voff;
     const int B = gr.B;
-    for (int64_t r = M.r0 + M.sub; r < M.r1; r += 4 * M.rpw) {
+    for (int64_t r = M.r0 + M.sub; r < M.r1; r += W * M.rpw) {
       const int64_t i = r * B + M.j;
       const double2 a = vk[i];
       const double2 yv = y[i];
@@ -237,12 +241,13 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_axpy(BLaunch L, int k) {
       s += wr * wr + wi * wi;
     }
   }
-  block_partial(s, gr, red, L, lb);
+  block_partial<W>(s, gr, red, L, lb);
 }
 
 // ---- psi = sum_l coef_l V_l; partials of ||psi||^2
-__global__ __launch_bounds__(kBatchBlock) void k_b_combine(BLaunch L) {
-  __shared__ double red[4 * 64];
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_b_combine(BLaunch L) {
+  __shared__ double red[W * 64];
   const int lb = logical_block(L.total_blocks);
   if (lb >= L.total_blocks) return;
   const int g = find_group(L.groups, L.ngroups, lb);
@@ -255,7 +260,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_combine(BLaunch L) {
     const double2* __restrict__ cf = L.S.coef + (int64_t)slot * kMaxM;
     double2* __restrict__ psi = L.V + gr.voff;
     const int B = gr.B;
-    for (int64_t r = M.r0 + M.sub; r < M.r1; r += 4 * M.rpw) {
+    for (int64_t r = M.r0 + M.sub; r < M.r1; r += W * M.rpw) {
       const int64_t i = r * B + M.j;
       double ar = 0.0, ai = 0.0;
       for (int l = 0; l < meff; ++l) {
@@ -268,7 +273,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_combine(BLaunch L) {
       s += ar * ar + ai * ai;
     }
   }
-  block_partial(s, gr, red, L, lb);
+  block_partial<W>(s, gr, red, L, lb);
 }
 
 // Fixed-order sum of instance j's block partials by one wavefront.
@@ -391,7 +396,8 @@ __global__ void k_b_set_cursor(BState* st, long long v) {
   if (threadIdx.x == 0) st->cursor = v;
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_b_pack(BLaunch L, const double2* __restrict__ user,
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_b_pack(BLaunch L, const double2* __restrict__ user,
                                                         const int64_t* __restrict__ uoff, int dir) {
   const int lb = logical_block(L.total_blocks);
   if (lb >= L.total_blocks) return;
@@ -402,7 +408,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_b_pack(BLaunch L, const double2
   const int64_t uo = uoff[gr.slot0 + M.j];
   double2* __restrict__ x = L.V + gr.voff;
   double2* __restrict__ u = const_cast<double2*>(user) + uo;
-  for (int64_t r = M.r0 + M.sub; r < M.r1; r += 4 * M.rpw) {
+  for (int64_t r = M.r0 + M.sub; r < M.r1; r += W * M.rpw) {
     if (dir == 0) x[r * gr.B + M.j] = u[r];
     else u[r] = x[r * gr.B + M.j];
   }
@@ -424,8 +430,18 @@ __global__ void k_b_stats_reset(BSlots S, int nslots) {
 
 static inline int row_grid(const BLaunch& L) { return L.total_blocks; }
 
+// launch a row kernel with the batch's block layout (L.waves wavefronts)
+#define CFET_ROW_LAUNCH(KERNEL, ...)                                                        \
+  do {                                                                                     \
+    switch (L.waves) {                                                                     \
+      case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(row_grid(L)), dim3(128), 0, s, __VA_ARGS__); break; \
+      case 8: hipLaunchKernelGGL(KERNEL<8>, dim3(row_grid(L)), dim3(512), 0, s, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(KERNEL<4>, dim3(row_grid(L)), dim3(256), 0, s, __VA_ARGS__); break; \
+    }                                                                                      \
+  } while (0)
+
 hipError_t batch_norm(const BLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_norm, dim3(row_grid(L)), dim3(kBatchBlock), 0, s, L);
+  CFET_ROW_LAUNCH(k_b_norm, L);
   return hipGetLastError();
 }
 
@@ -435,17 +451,17 @@ hipError_t batch_scalars(const BLaunch& L, int mode, int k, hipStream_t s) {
 }
 
 hipError_t batch_spmm(const BLaunch& L, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_spmm, dim3(row_grid(L)), dim3(kBatchBlock), 0, s, L, k);
+  CFET_ROW_LAUNCH(k_b_spmm, L, k);
   return hipGetLastError();
 }
 
 hipError_t batch_axpy(const BLaunch& L, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_axpy, dim3(row_grid(L)), dim3(kBatchBlock), 0, s, L, k);
+  CFET_ROW_LAUNCH(k_b_axpy, L, k);
   return hipGetLastError();
 }
 
 hipError_t batch_combine(const BLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_combine, dim3(row_grid(L)), dim3(kBatchBlock), 0, s, L);
+  CFET_ROW_LAUNCH(k_b_combine, L);
   return hipGetLastError();
 }
 
@@ -460,12 +476,12 @@ hipError_t batch_set_cursor(const BLaunch& L, long long v, hipStream_t s) {
 }
 
 hipError_t batch_pack(const BLaunch& L, const double2* user, const int64_t* uoff, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_pack, dim3(row_grid(L)), dim3(kBatchBlock), 0, s, L, user, uoff, 0);
+  CFET_ROW_LAUNCH(k_b_pack, L, user, uoff, 0);
   return hipGetLastError();
 }
 
 hipError_t batch_unpack(const BLaunch& L, double2* user, const int64_t* uoff, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_pack, dim3(row_grid(L)), dim3(kBatchBlock), 0, s, L, user, uoff, 1);
+  CFET_ROW_LAUNCH(k_b_pack, L, user, uoff, 1);
   return hipGetLastError();
 }
 

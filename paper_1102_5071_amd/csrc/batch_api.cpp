@@ -43,7 +43,8 @@ struct cfet_batch {
   int total_blocks = 0;
   int64_t pstride = 0;             // partial sums per instance (most blocks of a group)
   int unroll = 1;                  // rows per lane and pass (autotuned)
-  std::vector<double> tune_us;     // timing of each candidate (autotune)
+  int waves = cfet::kBatchDefaultWaves;  // wavefronts per block of the row kernels (autotuned)
+  std::vector<double> tune_us;     // timing of each candidate (autotune), [waves][unroll]
   // workspace
   int m_alloc = 0;
   double2* V = nullptr;
@@ -115,11 +116,13 @@ void free_batch(cfet_batch* b) {
 }
 
 // Block layout of the row kernels for a given unroll: fills rows_per_block,
+static_assert(sizeof(cfet_batch_stats_t) == 168 && offsetof(cfet_batch_stats_t, tune_us) == 72,
+              "cfet_batch_stats_t layout is part of the ABI");
 // nblocks, block0 and returns the total number of blocks.
-int layout_blocks(std::vector<BGroup>& G, int unroll) {
+int layout_blocks(std::vector<BGroup>& G, int unroll, int waves) {
   int total = 0;
   for (auto& g : G) {
-    g.rows_per_block = (cfet::kBatchBlock / 64) * (64 / g.lpr) * unroll;
+    g.rows_per_block = waves * (64 / g.lpr) * unroll;
     g.nblocks = int((g.n + g.rows_per_block - 1) / g.rows_per_block);
     g.block0 = total;
     total += g.nblocks;
@@ -138,6 +141,7 @@ BLaunch launch_of(const cfet_batch* b) {
   L.Y = b->Y;
   L.part = b->part;
   L.pstride = b->pstride;
+  L.waves = b->waves;
   L.S = b->S;
   L.st = b->st;
   return L;
@@ -181,7 +185,8 @@ hipError_t enqueue_step(const BLaunch& L, int m, int s_count, hipStream_t s) {
 
 // Time one Lanczos product (SpMM and the reduction of its partial sums) per
 // layout candidate on the real operators and keep the fastest; the candidates
-// change how many rows a block covers, and with it the number of partials.
+// (wavefronts per block x rows per lane) change how many rows a block covers,
+// and with it the number of partials.
 int autotune(cfet_batch* b) {
   hipError_t e = hipSuccess;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -208,16 +213,18 @@ int autotune(cfet_batch* b) {
   }
   if (e == hipSuccess) e = hipMemset(b->V, 0, sizeof(double2) * b->ntot);
   double best = 1e300;
-  int best_u = 1;
+  int best_u = 1, best_w = cfet::kBatchDefaultWaves;
   b->tune_us.clear();
+  for (int wv : cfet::kBatchWaveChoices)
   for (int u : kTuneCandidates) {
     if (e != hipSuccess) break;
     std::vector<BGroup> G = b->groups;
-    const int tb = layout_blocks(G, u);
+    const int tb = layout_blocks(G, u, wv);
     e = hipMemcpy(b->d_groups, G.data(), G.size() * sizeof(BGroup), hipMemcpyHostToDevice);
     if (e != hipSuccess) break;
     BLaunch L = launch_of(b);
     L.total_blocks = tb;
+    L.waves = wv;
     e = cfet::batch_spmm(L, 0, nullptr);  // warm-up
     if (e == hipSuccess) e = cfet::batch_scalars(L, cfet::kBAlpha, 0, nullptr);
     if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
@@ -234,12 +241,14 @@ int autotune(cfet_batch* b) {
     if (e == hipSuccess && us < best) {
       best = us;
       best_u = u;
+      best_w = wv;
     }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (e != hipSuccess) return bhip(b, e, "cfet_batch_create: autotune");
   b->unroll = best_u;
+  b->waves = best_w;
   return CFET_OK;
 }
 
@@ -515,7 +524,9 @@ CFET_API int cfet_batch_create(int32_t nops, const cfet_csr* ops, int32_t ninst,
     return rc;
   }
   b->ntot = voff;
-  layout_blocks(b->groups, kTuneCandidates[0]);
+  // partial-sum rows sized for the layout with the most blocks (the smallest
+  // block and rows per lane among the candidates)
+  layout_blocks(b->groups, kTuneCandidates[0], cfet::kBatchWaveChoices[0]);
   for (const auto& g : b->groups) b->pstride = std::max<int64_t>(b->pstride, g.nblocks);
   // per-slot state and workspace
   const size_t ns = size_t(ninst), nm = ns * cfet::kMaxM;
@@ -557,6 +568,7 @@ CFET_API int cfet_batch_create(int32_t nops, const cfet_csr* ops, int32_t ninst,
   }
   if (flags & CFET_BATCH_NO_AUTOTUNE) {
     b->unroll = 8;
+    b->waves = cfet::kBatchDefaultWaves;
   } else {
     rc = autotune(b);
     if (rc != CFET_OK) {
@@ -565,7 +577,7 @@ CFET_API int cfet_batch_create(int32_t nops, const cfet_csr* ops, int32_t ninst,
       return rc;
     }
   }
-  b->total_blocks = layout_blocks(b->groups, b->unroll);
+  b->total_blocks = layout_blocks(b->groups, b->unroll, b->waves);
   e = hipMemcpy(b->d_groups, b->groups.data(), b->groups.size() * sizeof(BGroup),
                 hipMemcpyHostToDevice);
   if (e == hipSuccess) e = cfet::batch_stats_reset(launch_of(b), nullptr);
@@ -722,7 +734,8 @@ CFET_API int cfet_batch_stats(cfet_batch* b, cfet_batch_stats_t* out) {
   }
   out->unroll = b->unroll;
   out->graph = b->graph_used ? 1 : 0;
-  for (size_t i = 0; i < b->tune_us.size() && i < 4; ++i) out->tune_us[i] = b->tune_us[i];
+  out->block_threads = 64 * b->waves;
+  for (size_t i = 0; i < b->tune_us.size() && i < 12; ++i) out->tune_us[i] = b->tune_us[i];
   return hs.status;
 }
 

@@ -19,7 +19,11 @@
 namespace cfet {
 
 constexpr int kBatchMaxGroup = 64;  // instances per group (one wavefront lane each)
-constexpr int kBatchBlock = 256;    // threads of the row kernels (4 wavefronts)
+// wavefronts per block of the row kernels: chosen at create among these
+// (with the rows each lane covers); every row kernel of a batch uses the
+// same block layout, since the block partials follow it
+constexpr int kBatchWaveChoices[] = {2, 4, 8};
+constexpr int kBatchDefaultWaves = 4;
 constexpr int kBatchMaxK1 = 8;      // 1 + driven terms
 
 struct BGroup {
@@ -83,6 +87,7 @@ struct BLaunch {
   double2* Y;            // H v_k
   double* part;          // [slot][pstride] partial sums: instance slot, block of its group
   int64_t pstride;
+  int waves;             // wavefronts per block of the row kernels (2, 4 or 8)
   BSlots S;
   BState* st;
 };

@@ -69,6 +69,14 @@ def test_dt_choice_struct_layout():
     assert B._DtChoice.order.offset == 72 and B._DtChoice.rounds.offset == 92
 
 
+def test_batch_stats_struct_layout():
+    # the binding's mirror of cfet_batch_stats_t: the launch layout fields,
+    # then 12 create-time timings (3 block sizes x 4 rows per lane)
+    assert ctypes.sizeof(B._BatchStats) == 168
+    assert B._BatchStats.block_threads.offset == 68 and B._BatchStats.tune_us.offset == 72
+    assert B._BatchStats.tune_us.size == 96
+
+
 def test_host_side_argument_errors():
     lib = _lib()
     assert lib.cfet_scheme_info(99, None, None, None, None) == 1
