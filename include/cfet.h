@@ -442,6 +442,13 @@ CFET_API int cfet_batch_propagate(cfet_batch *b, void *psi_dev, double t0, doubl
                                   int64_t nsteps, int32_t scheme, int32_t krylov_m, double tol,
                                   void *hip_stream);
 
+/* Fix the launch layout of the batch's row kernels instead of the one chosen
+ * at create (tests, reproducible layouts): block_threads 128, 256 or 512,
+ * rows_per_lane 2, 4, 8 or 16.  Results differ between layouts only in the
+ * order of the block-partial sums.  Synchronises with the batch's last call;
+ * the next call re-records its step graph.  CFET_EINVAL for other values. */
+CFET_API int cfet_batch_set_layout(cfet_batch *b, int32_t block_threads, int32_t rows_per_lane);
+
 /* Synchronise and report statistics; returns the latched device status. */
 CFET_API int cfet_batch_stats(cfet_batch *b, cfet_batch_stats_t *s);
 

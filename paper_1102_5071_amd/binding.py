@@ -129,6 +129,7 @@ def load():
     lib.cfet_batch_propagate.argtypes = [c_void_p, c_void_p, c_double, c_double, c_int64,
                                          c_int32, c_int32, c_double, c_void_p]
     lib.cfet_batch_stats.argtypes = [c_void_p, POINTER(_BatchStats)]
+    lib.cfet_batch_set_layout.argtypes = [c_void_p, c_int32, c_int32]
     lib.cfet_batch_instance_matvecs.argtypes = [c_void_p, c_void_p]
     lib.cfet_batch_destroy.argtypes = [c_void_p]
     lib.cfet_batch_last_error.restype = ctypes.c_char_p
@@ -136,7 +137,7 @@ def load():
     for name in ("cfet_create", "cfet_propagate", "cfet_propagate_static", "cfet_gradient", "cfet_apply", "cfet_stats",
                  "cfet_destroy", "cfet_scheme_info", "cfet_step_weights", "cfet_tridiag_expm",
                  "cfet_profile", "cfet_batch_create", "cfet_batch_propagate", "cfet_batch_stats",
-                 "cfet_batch_instance_matvecs", "cfet_batch_destroy"):
+                 "cfet_batch_set_layout", "cfet_batch_instance_matvecs", "cfet_batch_destroy"):
         getattr(lib, name).restype = c_int32
     _LIB = lib
     return lib
@@ -426,6 +427,10 @@ class BatchPropagator:
         out = {f[0]: getattr(st, f[0]) for f in _BatchStats._fields_}
         out["tune_us"] = list(out["tune_us"])
         return out
+
+    def set_layout(self, block_threads: int, rows_per_lane: int):
+        """Fix the row kernels' launch layout (cfet_batch_set_layout)."""
+        self._check(load().cfet_batch_set_layout(self._b, int(block_threads), int(rows_per_lane)))
 
     def instance_matvecs(self):
         out = np.zeros(len(self.dims), dtype=np.int64)

@@ -560,6 +560,17 @@ CFET_API int cfet_batch_create(int32_t nops, const cfet_csr* ops, int32_t ninst,
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->h_mcap), ns * sizeof(int));
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    // the device parameters, with the latched status cleared: the per-call
+    // upload never rewrites the status, so it must start at CFET_OK whether
+    // or not the layouts are timed below
+    BState hs{};
+    hs.wts = b->d_wts;
+    hs.nslots = b->ninst;
+    hs.K1 = b->K1;
+    hs.status = CFET_OK;
+    e = hipMemcpy(b->st, &hs, sizeof(BState), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     rc = bhip(b, e, "cfet_batch_create: device setup");
     g_berr = b->err;
@@ -691,6 +702,33 @@ CFET_API int cfet_batch_propagate(cfet_batch* b, void* psi_dev, double t0, doubl
   e = cfet::batch_unpack(L, static_cast<double2*>(psi_dev), b->d_uoff, s);
   if (e != hipSuccess) return bhip(b, e, "cfet_batch_propagate: launch");
   b->have_work = true;
+  return CFET_OK;
+}
+
+CFET_API int cfet_batch_set_layout(cfet_batch* b, int32_t block_threads, int32_t rows_per_lane) {
+  if (!b) return bfail(nullptr, CFET_EINVAL, "cfet_batch_set_layout: null batch");
+  int waves = 0;
+  for (int wv : cfet::kBatchWaveChoices)
+    if (64 * wv == block_threads) waves = wv;
+  bool rows_ok = false;
+  for (int u : kTuneCandidates) rows_ok = rows_ok || u == rows_per_lane;
+  if (waves == 0 || !rows_ok)
+    return bfail(b, CFET_EINVAL,
+                 "cfet_batch_set_layout: block_threads must be 128, 256 or 512 and "
+                 "rows_per_lane 2, 4, 8 or 16");
+  hipError_t e = b->have_work ? hipStreamSynchronize(b->last_stream) : hipSuccess;
+  if (e != hipSuccess) return bhip(b, e, "cfet_batch_set_layout: synchronise");
+  b->waves = waves;
+  b->unroll = rows_per_lane;
+  // the partial rows (pstride) were sized at create for the layout with the most blocks
+  b->total_blocks = layout_blocks(b->groups, b->unroll, b->waves);
+  e = hipMemcpy(b->d_groups, b->groups.data(), b->groups.size() * sizeof(BGroup),
+                hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bhip(b, e, "cfet_batch_set_layout: upload");
+  if (b->exec) {  // recorded with the old grid: re-record on the next call
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
   return CFET_OK;
 }
 

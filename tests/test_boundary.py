@@ -140,6 +140,7 @@ def test_batch_host_side_argument_errors():
     assert out.value is None
     assert lib.cfet_batch_propagate(None, None, 0.0, 0.1, 1, 1, 4, 0.0, None) == 1
     assert lib.cfet_batch_stats(None, None) == 1
+    assert lib.cfet_batch_set_layout(None, 256, 8) == 1
     assert lib.cfet_batch_instance_matvecs(None, None) == 1
     assert lib.cfet_batch_destroy(None) == 0
 

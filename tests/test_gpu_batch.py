@@ -197,3 +197,74 @@ def test_batch_argument_errors():
             assert ei.value.code == 1
         P.propagate(psi, 0.0, 0.1, 0, "CF4:2", 8)  # nsteps = 0 is a no-op
         assert not psi.any()
+
+
+def layout_batch():
+    """The mixed batch plus two longer chains, so that in every launch layout
+    some group spans several blocks (block partials summed across blocks)."""
+    ops, insts = mixed_batch(4)
+    rng = np.random.default_rng(44)
+    for L in (11, 12):
+        ops.append(I.sigma_x_sum(L))
+        sx = len(ops) - 1
+        ops.append(I.ising_chain(L, 1.0, rng.uniform(-1, 1, L)))
+        insts.append({"h0": len(ops) - 1, "hk": [sx],
+                      "drives": [{"kind": "cos", "A": 0.8, "omega": 1.7, "phi": 0.1}],
+                      "psi0": I.random_state(1 << L, rng)})
+    return ops, insts
+
+
+@pytest.fixture(scope="module")
+def layout_case():
+    ops, insts = layout_batch()
+    ref, ref_mv = oracle_run(ops, insts, 0.1, 0.04, 4, "CF4:2", 12, 1e-10)
+    return ops, insts, ref, ref_mv
+
+
+@pytest.mark.parametrize("threads", [128, 256, 512])
+def test_every_launch_layout_matches_oracle(layout_case, threads):
+    # the create-time tuner may keep any of the twelve layouts: each one,
+    # fixed with cfet_batch_set_layout, against the oracle (graph replays,
+    # re-recorded after each change of layout)
+    ops, insts, ref, ref_mv = layout_case
+    psi0 = np.concatenate([i["psi0"] for i in insts])
+    with B.BatchPropagator(ops, insts, autotune=False) as P:
+        before = P.instance_matvecs()
+        for rows in (2, 4, 8, 16):
+            P.set_layout(threads, rows)
+            psi = torch.from_numpy(psi0).to("cuda")
+            P.propagate(psi, 0.1, 0.04, 4, "CF4:2", 12, 1e-10)
+            st = P.stats()
+            assert st["status"] == 0 and st["graph"] == 1, st
+            assert (st["block_threads"], st["unroll"]) == (threads, rows)
+            mv = P.instance_matvecs()
+            assert list(mv - before) == list(ref_mv), (threads, rows)
+            before = mv
+            for t, (a, b) in enumerate(zip(P.split(psi), ref)):
+                r = rel(a.cpu().numpy(), b)
+                assert r <= TOL, (threads, rows, t, r)
+
+
+def test_set_layout_rejects_other_values():
+    ops, insts = mixed_batch(5)
+    with B.BatchPropagator(ops, insts, autotune=False) as P:
+        for bad in ((64, 8), (1024, 8), (256, 3), (256, 32), (256, 0)):
+            with pytest.raises(B.CfetError):
+                P.set_layout(*bad)
+        P.set_layout(512, 2)
+        assert (P.stats()["block_threads"], P.stats()["unroll"]) == (512, 2)
+
+
+def test_status_starts_clear_without_autotune():
+    # the latched device status must read CFET_OK on a batch created without
+    # the layout timing, also when its device memory was used before
+    # (regression: it was left as allocated)
+    ops, insts = layout_batch()
+    psi0 = np.concatenate([i["psi0"] for i in insts])
+    for _ in range(3):
+        with B.BatchPropagator(ops, insts, autotune=False) as P:
+            psi = torch.from_numpy(psi0).to("cuda")
+            P.propagate(psi, 0.0, 0.04, 2, "CF4:2", 12, 1e-10)
+            assert P.stats()["status"] == 0
+    with B.BatchPropagator(ops, insts, autotune=False) as P:
+        assert P.stats()["status"] == 0
