@@ -552,13 +552,25 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
           const double2 ucur = ucurs[p];
           double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
           if (rowp[p] >= 0) {
+            // the single workgroup reads the ring values of all its
+            // register-held entries first, with nothing between the reads,
+            // so that they are in flight together (past the row's length an
+            // entry holds value 0 and column 0, a valid index of the ring,
+            // and adds a zero product)
+            double2 xs[SINGLE ? QMAX : 1];
+            if constexpr (SINGLE) {
+#pragma unroll
+              for (int q = 0; q < QMAX; ++q) xs[q] = lu[k % 3][(int)(ccol[p][q] & kColMask)];
+            }
 #pragma unroll
             for (int q = 0; q < QMAX; ++q) {
-              if (q < cnt[p]) {
+              if (SINGLE || q < cnt[p]) {
                 const uint32_t ct = ccol[p][q];
                 const auto v = cval[p][q];
                 double2 xv;
-                if ((lmask[p] >> q) & 1u) {
+                if constexpr (SINGLE) {
+                  xv = xs[q];
+                } else if ((lmask[p] >> q) & 1u) {
                   xv = lu[k % 3][(int)((int64_t)(ct & kColMask) - r0)];  // u_k, own block
                 } else {
                   const double2 xg2 = (k >= 2) ? g2[p][q] : make_double2(0.0, 0.0);
