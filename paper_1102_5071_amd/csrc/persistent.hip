@@ -552,15 +552,20 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
           const double2 ucur = ucurs[p];
           double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
           if (rowp[p] >= 0) {
-            // the single workgroup reads the ring values of all its
-            // register-held entries first, with nothing between the reads,
-            // so that they are in flight together (past the row's length an
-            // entry holds value 0 and column 0, a valid index of the ring,
-            // and adds a zero product)
-            double2 xs[SINGLE ? QMAX : 1];
-            if constexpr (SINGLE) {
+            // the ring values of all register-held entries are read first,
+            // with nothing between the reads, so that they are in flight
+            // together (an entry whose column is another block's row reads
+            // index 0 and does not use it; in the single workgroup an entry
+            // past the row's length holds value 0 and column 0, a valid index
+            // of the ring, and adds a zero product)
+            double2 xs[QMAX];
 #pragma unroll
-              for (int q = 0; q < QMAX; ++q) xs[q] = lu[k % 3][(int)(ccol[p][q] & kColMask)];
+            for (int q = 0; q < QMAX; ++q) {
+              const int li =
+                  SINGLE ? (int)(ccol[p][q] & kColMask)
+                         : (((lmask[p] >> q) & 1u) ? (int)((int64_t)(ccol[p][q] & kColMask) - r0)
+                                                   : 0);
+              xs[q] = lu[k % 3][li];
             }
 #pragma unroll
             for (int q = 0; q < QMAX; ++q) {
@@ -568,10 +573,8 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
                 const uint32_t ct = ccol[p][q];
                 const auto v = cval[p][q];
                 double2 xv;
-                if constexpr (SINGLE) {
-                  xv = xs[q];
-                } else if ((lmask[p] >> q) & 1u) {
-                  xv = lu[k % 3][(int)((int64_t)(ct & kColMask) - r0)];  // u_k, own block
+                if (SINGLE || ((lmask[p] >> q) & 1u)) {
+                  xv = xs[q];  // u_k of a row of this block
                 } else {
                   const double2 xg2 = (k >= 2) ? g2[p][q] : make_double2(0.0, 0.0);
                   xv = (k >= 1) ? form_u(gz[p][q], g1[p][q], xg2, c1, c2, c3) : g1[p][q];
