@@ -38,10 +38,12 @@ DEFAULT_CHUNK = {"hydrogen": 10, "ising": 50, "heisenberg": 1, "batched": 0, "ad
 # workloads time the selected number of steps instead (unless --dt fixes dt)
 DEFAULT_STEPS = {"hydrogen": (200, 20), "ising": (1000, 100), "heisenberg": (20, 2),
                  "batched": (200, 20), "adjoint": (200, 20)}
-# what limits the dominant kernel of each plain workload: the Heisenberg chain's
-# SpMV streams its operator and vectors from HBM (13 GB per SpMV in CSR terms);
-# the hydrogen and Ising operators and Krylov bases stay in the caches and their
-# persistent kernels wait on grid-wide round trips
+# the roofline each plain workload's dominant kernel is measured against: the
+# Heisenberg chain's SpMV streams its vectors and layout from HBM (1.7 GB of
+# counted traffic per SpMV on the split layout, 13 GB in complex-CSR terms;
+# its first pass runs below that ceiling, held by per-slice latency chains);
+# the hydrogen and Ising operators and Krylov bases stay in the caches and
+# their persistent kernels wait on grid-wide round trips
 BOUND = {"heisenberg": "hbm", "hydrogen": "latency", "ising": "latency"}
 # step selection per plain workload: (probe window start, probe window length,
 # probe steps n1, time span T the accuracy goal refers to).  The probe steps
