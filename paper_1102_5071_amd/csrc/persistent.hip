@@ -240,12 +240,14 @@ __device__ void p_block_sum2(double& a, double& b, double* red) {
 // 0 uses above (so the results are the same bit for bit).  Two calls in a row
 // use different sets; a set is rewritten only two calls later, after a block
 // barrier that every thread passes once it has read the set.
+// NW: wavefronts of the block, a compile-time constant, so that the reads of
+// the per-wavefront values are issued together (and no block size is loaded).
+template <int NW>
 __device__ __forceinline__ void p_block_sum2_1b(double& a, double& b, double (*red2)[2 * kRedB],
                                                 int& parity) {
   a = p_wave_sum(a);
   b = p_wave_sum(b);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
   double* R = red2[parity];
   if (l == 0) {
     R[w] = a;
@@ -253,7 +255,8 @@ __device__ __forceinline__ void p_block_sum2_1b(double& a, double& b, double (*r
   }
   __syncthreads();
   double ta = 0.0, tb = 0.0;
-  for (int i = 0; i < nw; ++i) {
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
     ta += R[i];
     tb += R[kRedB + i];
   }
@@ -661,7 +664,7 @@ __global__ __launch_bounds__(BLOCK) void k_propagate(PersistArgs A) {
         }
         tm.lap(A.stats, 0);
         if (SINGLE) {
-          p_block_sum2_1b(s_uz, s_uu, sh.red2, rpar);
+          p_block_sum2_1b<BLOCK / 64>(s_uz, s_uu, sh.red2, rpar);
           S1 = s_uz;
           S2 = s_uu;
         } else {
