@@ -157,6 +157,11 @@ typedef struct {
  * (results equal up to the order of summation).  cfet_stats_t.reordered tells.
  * This flag keeps the caller's order. */
 #define CFET_NO_REORDER 0x400u
+/* Keep the merged CSR operator on the device also where the dimension
+ * (n > 2^22) selects a SELL layout, so that cfet_gradient runs there (on the
+ * multi-kernel CSR path; cfet_propagate keeps the SELL layout).  Costs 20
+ * bytes per non-zero and 8 per row of device memory. */
+#define CFET_KEEP_CSR 0x4000u
 
 typedef struct cfet_ctx cfet_ctx;
 
@@ -269,7 +274,8 @@ CFET_API int cfet_propagate_chebyshev(cfet_ctx *c, void *psi_dev, double t0, dou
  * psi0_dev, target_dev: complex128[n] device buffers (read only).  Writes
  * *F_out and dFdu_out[0..K-1] (host) and synchronises hip_stream.  Device
  * workspace O((sqrt(nsteps) s + 2 m) n), allocated for the call.  Needs the
- * CSR layout (n <= 2^22; CFET_EUNSUPPORTED otherwise). */
+ * CSR operator: kept for n <= 2^22, above that only with CFET_KEEP_CSR at
+ * create (CFET_EUNSUPPORTED otherwise). */
 CFET_API int cfet_gradient(cfet_ctx *c, const void *psi0_dev, const void *target_dev, double t0,
                            double dt, int64_t nsteps, int32_t scheme, int32_t krylov_m,
                            const double *u, int32_t K, double *F_out, double *dFdu_out,

@@ -27,6 +27,7 @@ PATH_FLAGS = {None: 0, "auto": 0, "multi": 0x10, "single": 0x20, "coop": 0x40,
               "sell": 0x10 | 0x100, "sell_uniform": 0x10 | 0x200, "sell_split": 0x10 | 0x800}
 LAYOUT_FLAGS = {None: 0, "auto": 0, "sell": 0x100, "sell_uniform": 0x200, "sell_split": 0x800}
 NO_REORDER = 0x400
+KEEP_CSR = 0x4000
 PATH_NAMES = {0: "none", 1: "multi", 2: "single", 3: "coop"}
 LAYOUT_NAMES = {0: "csr", 1: "sell", 2: "sell_uniform", 3: "sell_split"}
 # the kernel(s) of one Lanczos SpMV on the multi-kernel path, per layout
@@ -214,7 +215,7 @@ class Propagator:
     """Owns a cfet context for H(t) = H0 + sum_k f_k(t) Hk[k]."""
 
     def __init__(self, H0, Hk, drives, validate_hermitian: bool = False, path=None,
-                 layout=None, reorder: bool = True):
+                 layout=None, reorder: bool = True, keep_csr: bool = False):
         lib = load()
         keep = []
         self.nterms = len(Hk)
@@ -225,7 +226,8 @@ class Propagator:
         dv = (_Drive * self.nterms)(*[_drive_struct(d, keep) for d in drives])
         ctx = c_void_p()
         flags = ((VALIDATE_HERMITIAN if validate_hermitian else 0) | PATH_FLAGS[path]
-                 | LAYOUT_FLAGS[layout] | (0 if reorder else NO_REORDER))
+                 | LAYOUT_FLAGS[layout] | (0 if reorder else NO_REORDER)
+                 | (KEEP_CSR if keep_csr else 0))
         code = lib.cfet_create(ctypes.byref(h0), self.nterms, hk, dv, flags, ctypes.byref(ctx))
         if code != 0:
             raise CfetError(code, lib.cfet_last_error(None).decode(errors="replace"))

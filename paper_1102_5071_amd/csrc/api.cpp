@@ -1365,7 +1365,7 @@ int cfet_create(const cfet_csr* H0, int32_t nterms, const cfet_csr* Hk, const cf
   const bool use_sell =
       (flags & (CFET_LAYOUT_SELL | CFET_LAYOUT_SELL_UNIFORM | CFET_LAYOUT_SELL_SPLIT)) ||
       n > kAutoCoopMaxN;
-  const bool need_csr = !use_sell || n <= kAutoCoopMaxN;
+  const bool need_csr = !use_sell || n <= kAutoCoopMaxN || (flags & CFET_KEEP_CSR);
   c->A.n = n;
   c->A.nnz = nnz;
   const unsigned nth_all = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -2201,7 +2201,8 @@ int cfet_gradient(cfet_ctx* c, const void* psi0_dev, const void* target_dev, dou
   if (!is_device_ptr(psi0_dev) || !is_device_ptr(target_dev))
     return fail(c, CFET_EINVAL, "psi0 and target must be device memory");
   if (!c->A.rowptr)
-    return fail(c, CFET_EUNSUPPORTED, "cfet_gradient needs the CSR layout (dimension <= 2^22)");
+    return fail(c, CFET_EUNSUPPORTED,
+                "cfet_gradient needs the CSR operator (dimension <= 2^22, or CFET_KEEP_CSR)");
   int kstar = -1;
   for (int k = 0; k < c->nterms && kstar < 0; ++k)
     if (c->drives[k].kind == CFET_DRIVE_PWC) kstar = k;

@@ -139,3 +139,40 @@ def test_control_problem_full_size_gradient_properties():
         fd4 = (-shifted(q, 2 * h) + 8 * shifted(q, h) - 8 * shifted(q, -h)
                + shifted(q, -2 * h)) / (12 * h)
         assert abs(fd4 - g[q]) <= 2e-9 * scale, (q, fd4, g[q])
+
+
+def test_gradient_above_the_csr_size_with_keep_csr():
+    # 2^23 rows: the context stores the SELL layouts only, and the gradient
+    # needs the CSR operator.  Without CFET_KEEP_CSR it refuses; with it the
+    # gradient runs (multi-kernel CSR sweep) while propagation keeps the SELL
+    # layout.  F equals |<target|psi_N>|^2 of the plain propagation, and
+    # central differences of F (h = 1e-6, from the same call with the pieces
+    # overridden) agree with dF/du on every piece.
+    p = I.config_adjoint(L=23, K=4, T=0.2, dt=0.05)
+    m, N = 10, p.nsteps
+    target = p.meta["target"]
+    u = np.asarray(p.drives[0]["u"], dtype=np.float64)
+    with B.Propagator(p.H0, p.Hk, p.drives) as P:
+        with pytest.raises(B.CfetError):
+            P.gradient(dev(p.psi0), dev(target), 0.0, p.dt, N, p.scheme, m)
+    with B.Propagator(p.H0, p.Hk, p.drives, keep_csr=True) as P:
+        F, g = P.gradient(dev(p.psi0), dev(target), 0.0, p.dt, N, p.scheme, m)
+        assert P.stats()["status"] == 0
+        psi = dev(p.psi0)
+        P.propagate(psi, 0.0, p.dt, N, p.scheme, m)
+        st = P.stats()
+        assert st["status"] == 0 and st["path"] == 1 and st["layout"] != 0
+        F_plain = abs(np.vdot(target, psi.cpu().numpy())) ** 2
+        assert abs(F - F_plain) <= 1e-9 * F_plain, (F, F_plain)
+        g = np.asarray(g)
+        scale = np.max(np.abs(g))
+        assert scale > 0.0
+        h = 1e-6
+        for q in range(len(u)):
+            up, um = u.copy(), u.copy()
+            up[q] += h
+            um[q] -= h
+            Fp = P.gradient(dev(p.psi0), dev(target), 0.0, p.dt, N, p.scheme, m, u=up)[0]
+            Fm = P.gradient(dev(p.psi0), dev(target), 0.0, p.dt, N, p.scheme, m, u=um)[0]
+            fd = (Fp - Fm) / (2 * h)
+            assert abs(fd - g[q]) <= 1e-6 * scale, (q, fd, g[q])
