@@ -290,16 +290,19 @@ __global__ __launch_bounds__(kBlock) void k_lz_axpy(int64_t n, const double2* __
   const double cb = (j > 0) ? S->beta[j - 1] * S->inv_nrm[j - 1] : 0.0;
   double s = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // the three vectors stream through once (each larger than the caches at
+  // the sizes where this path runs): non-temporal loads and store
+  typedef double dv2 __attribute__((ext_vector_type(2)));
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
-    const double2 y = wnext[r];
-    const double2 a = wj[r];
+    const dv2 y = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(wnext) + r);
+    const dv2 a = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(wj) + r);
     double wr = y.x - ca * a.x, wi = y.y - ca * a.y;
     if (j > 0) {
-      const double2 b = wjm1[r];
+      const dv2 b = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(wjm1) + r);
       wr -= cb * b.x;
       wi -= cb * b.y;
     }
-    wnext[r] = make_double2(wr, wi);
+    __builtin_nontemporal_store(dv2{wr, wi}, reinterpret_cast<dv2*>(wnext) + r);
     s += wr * wr + wi * wi;
   }
   s = block_sum(s, red);
@@ -368,13 +371,17 @@ __global__ __launch_bounds__(kBlock) void k_lz_combine(double2* __restrict__ psi
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
     double accr = 0.0, acci = 0.0;
+    // the basis vectors and psi stream through once: non-temporal accesses
+    typedef double dv2 __attribute__((ext_vector_type(2)));
     for (int jj = 0; jj < meff; ++jj) {
-      const double2 v = (jj == 0) ? psi[r] : basis[(int64_t)(jj - 1) * n + r];
+      const dv2* src = (jj == 0) ? reinterpret_cast<const dv2*>(psi) + r
+                                 : reinterpret_cast<const dv2*>(basis) + (int64_t)(jj - 1) * n + r;
+      const dv2 v = __builtin_nontemporal_load(src);
       const double2 k = cf[jj];
       accr += k.x * v.x - k.y * v.y;
       acci += k.x * v.y + k.y * v.x;
     }
-    psi[r] = make_double2(accr, acci);
+    __builtin_nontemporal_store(dv2{accr, acci}, reinterpret_cast<dv2*>(psi) + r);
     s += accr * accr + acci * acci;
   }
   s = block_sum(s, red);
