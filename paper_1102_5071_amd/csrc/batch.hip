@@ -227,17 +227,18 @@ __global__ __launch_bounds__(64 * W) void k_b_axpy(BLaunch L, int k) {
     const double2* __restrict__ y = L.Y + gr.voff;
     double2* __restrict__ w = L.V + (int64_t)(k + 1) * L.ntot + gr.voff;
     const int B = gr.B;
+    typedef double dv2 __attribute__((ext_vector_type(2)));
     for (int64_t r = M.r0 + M.sub; r < M.r1; r += W * M.rpw) {
       const int64_t i = r * B + M.j;
-      const double2 a = vk[i];
-      const double2 yv = y[i];
+      const dv2 a = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(vk) + i);
+      const dv2 yv = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(y) + i);
       double wr = yv.x - ca * a.x, wi = yv.y - ca * a.y;
       if (k > 0) {
-        const double2 b = vm[i];
+        const dv2 b = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(vm) + i);
         wr -= cb * b.x;
         wi -= cb * b.y;
       }
-      w[i] = make_double2(wr, wi);
+      __builtin_nontemporal_store(dv2{wr, wi}, reinterpret_cast<dv2*>(w) + i);
       s += wr * wr + wi * wi;
     }
   }
@@ -263,13 +264,14 @@ __global__ __launch_bounds__(64 * W) void k_b_combine(BLaunch L) {
     for (int64_t r = M.r0 + M.sub; r < M.r1; r += W * M.rpw) {
       const int64_t i = r * B + M.j;
       double ar = 0.0, ai = 0.0;
+      typedef double dv2 __attribute__((ext_vector_type(2)));
       for (int l = 0; l < meff; ++l) {
-        const double2 v = L.V[(int64_t)l * L.ntot + gr.voff + i];
+        const dv2 v = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(L.V) + (int64_t)l * L.ntot + gr.voff + i);
         const double2 c = cf[l];
         ar += c.x * v.x - c.y * v.y;
         ai += c.x * v.y + c.y * v.x;
       }
-      psi[i] = make_double2(ar, ai);
+      __builtin_nontemporal_store(dv2{ar, ai}, reinterpret_cast<dv2*>(psi) + i);
       s += ar * ar + ai * ai;
     }
   }
