@@ -198,7 +198,8 @@ __global__ __launch_bounds__(64 * W) void k_b_spmm(BLaunch L, int k) {
         ai += wt[0] * hi;
       }
       const double2 yv = make_double2(ar * invk, ai * invk);
-      y[r * B + j] = yv;
+      typedef double dv2 __attribute__((ext_vector_type(2)));
+      __builtin_nontemporal_store(dv2{yv.x, yv.y}, reinterpret_cast<dv2*>(y) + r * B + j);
       s += (xo.x * yv.x + xo.y * yv.y) * invk;
     }
   }
