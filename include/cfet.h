@@ -425,9 +425,12 @@ typedef struct {
   int32_t unroll;         /* launch layout chosen at create: rows per lane and pass */
   int32_t graph;          /* 1 if the last call replayed the step graph */
   int32_t block_threads;  /* launch layout chosen at create: threads per block (128, 256, 512) */
-  double tune_us[12];     /* create-time timing (us) of one product and its reduction,
-                             [i * 4 + j] for 128, 256, 512 threads per block (i) and
-                             2, 4, 8, 16 rows per lane and pass (j); 0 if not timed */
+  double tune_us[12];     /* create-time timing (us) of one product, its reduction and
+                             the three-term update, [i * 4 + j] for 128, 256, 512
+                             threads per block (i) and 2, 4, 8, 16 rows per lane and
+                             pass (j); 0 if not timed.  The layout kept is, among those
+                             within 3 % of the fastest, the one with the most rows per
+                             block */
 } cfet_batch_stats_t;
 
 /* Build a batch.  ops: nops CSR matrices (host or device arrays, copied and

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "batch_internal.h"
+#include "partials.hpp"
 #include "tridiag.hpp"
 
 namespace cfet {
@@ -281,10 +282,9 @@ __global__ __launch_bounds__(64 * W) void k_b_combine(BLaunch L) {
 
 // Fixed-order sum of instance j's block partials by one wavefront.
 __device__ double slot_sum(const BLaunch& L, const BGroup& gr, int j) {
-  double s = 0.0;
   const int lane = threadIdx.x & 63;
   const double* __restrict__ p = L.part + (int64_t)(gr.slot0 + j) * L.pstride;
-  for (int b = lane; b < gr.nblocks; b += 64) s += p[b];
+  double s = thread_partials_chunked<64, 16>(p, gr.nblocks, lane);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   return lane_read(s, 0);

@@ -29,4 +29,26 @@ __device__ __forceinline__ double thread_partials(const double* __restrict__ par
   return s;
 }
 
+// The same sum for lane `lane` of `THREADS` lanes when the count has no useful
+// bound: chunks of PER values per lane, each chunk's loads issued together
+// (one memory round trip per chunk instead of per value), in the same order.
+template <int THREADS, int PER>
+__device__ __forceinline__ double thread_partials_chunked(const double* __restrict__ part, int np,
+                                                          int lane) {
+  double s = 0.0;
+  if (np <= 0) return s;
+  for (int c = 0; c < np; c += PER * THREADS) {
+    double v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = c + lane + j * THREADS;
+      v[j] = part[i < np ? i : np - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      if (c + lane + j * THREADS < np) s += v[j];
+  }
+  return s;
+}
+
 }  // namespace cfet
