@@ -430,7 +430,7 @@ typedef struct {
                              threads per block (i) and 2, 4, 8, 16 rows per lane and
                              pass (j); 0 if not timed.  The layout kept is, among those
                              within 3 % of the fastest, the one with the most rows per
-                             block */
+                             block, then the fewest threads per block */
 } cfet_batch_stats_t;
 
 /* Build a batch.  ops: nops CSR matrices (host or device arrays, copied and

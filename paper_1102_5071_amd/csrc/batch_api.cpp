@@ -188,9 +188,11 @@ hipError_t enqueue_step(const BLaunch& L, int m, int s_count, hipStream_t s) {
 // Time the first Lanczos iteration's product, its reduction and the
 // three-term update per layout candidate (wavefronts per block x rows per
 // lane) on the real operators.  Among the candidates within kTuneSlack of the
-// fastest, keep the one whose blocks cover the most rows: the other kernels of
-// a step (the second reduction, the recombination) pay per block and per
-// partial, which this timing leaves out.
+// fastest, keep the one whose blocks cover the most rows, and of those the one
+// with the fewest wavefronts per block: the other kernels of a step (the
+// second reduction, the recombination) pay per block and per partial, and a
+// smaller block waits at its barrier for fewer wavefronts, none of which this
+// timing shows.
 int autotune(cfet_batch* b) {
   hipError_t e = hipSuccess;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -249,16 +251,14 @@ int autotune(cfet_batch* b) {
   double fastest = 1e300;
   for (double us : b->tune_us) fastest = std::min(fastest, us);
   int best_u = 1, best_w = cfet::kBatchDefaultWaves, best_rows = 0;
-  double best_us = 1e300;
   size_t i = 0;
   for (int wv : cfet::kBatchWaveChoices)
     for (int u : kTuneCandidates) {
       const double us = b->tune_us[i++];
       if (us > fastest * (1.0 + kTuneSlack)) continue;
       const int rows = wv * u;  // rows per block, per lane of a row
-      if (rows > best_rows || (rows == best_rows && us < best_us)) {
+      if (rows > best_rows || (rows == best_rows && wv < best_w)) {
         best_rows = rows;
-        best_us = us;
         best_u = u;
         best_w = wv;
       }
