@@ -245,6 +245,29 @@ def test_every_launch_layout_matches_oracle(layout_case, threads):
                 assert r <= TOL, (threads, rows, t, r)
 
 
+def test_autotune_keeps_the_documented_layout(layout_case):
+    # of the twelve timed layouts, the kept one is within 3 % of the fastest,
+    # covers the most rows per block among those, and of equals has the
+    # fewest threads per block; the batch then matches the oracle
+    ops, insts, ref, ref_mv = layout_case
+    with B.BatchPropagator(ops, insts) as P:
+        st = P.stats()
+        t = st["tune_us"]
+        assert len(t) == 12 and all(x > 0 for x in t), t
+        fastest = min(t)
+        cands = [(threads, rows) for threads in (128, 256, 512) for rows in (2, 4, 8, 16)]
+        ok = [c for c, x in zip(cands, t) if x <= fastest * 1.03]
+        most = max(th * r for th, r in ok)
+        want = min((c for c in ok if c[0] * c[1] == most), key=lambda c: c[0])
+        assert (st["block_threads"], st["unroll"]) == want, (st, t)
+        psi = torch.from_numpy(np.concatenate([i["psi0"] for i in insts])).to("cuda")
+        P.propagate(psi, 0.1, 0.04, 4, "CF4:2", 12, 1e-10)
+        assert P.stats()["status"] == 0
+        for k, (a, b) in enumerate(zip(P.split(psi), ref)):
+            r = rel(a.cpu().numpy(), b)
+            assert r <= TOL, (want, k, r)
+
+
 def test_set_layout_rejects_other_values():
     ops, insts = mixed_batch(5)
     with B.BatchPropagator(ops, insts, autotune=False) as P:
