@@ -184,7 +184,8 @@ __global__ __launch_bounds__(64 * W) void k_b_spmm(BLaunch L, int k) {
       }
       const double2 xo = x[r * B + j];
       if (!gr.shared_h0) {
-        const double2 d = gr.diag[r * B + j];
+        typedef double dv2 __attribute__((ext_vector_type(2)));
+        const dv2 d = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(gr.diag) + r * B + j);
         double hr = d.x * xo.x - d.y * xo.y, hi = d.x * xo.y + d.y * xo.x;
         if (gr.orp) {
           const int64_t* rp = gr.orp + (int64_t)j * (gr.n + 1);
