@@ -6,6 +6,7 @@ HIP library.  Usage (from the repository root):
 
     python tests/golden/make_goldens.py heisenberg --L 18 --steps 200
     python tests/golden/make_goldens.py heisenberg --L 24 --steps 2
+    python tests/golden/make_goldens.py heisenberg --L 24 --steps 1 --dt-window 4 --dt-steps 19
     python tests/golden/make_goldens.py hydrogen
 
 Heisenberg chain (disordered, J = 1, h_i ~ U[-1, 1] from seed 0, H1 = sum sx,
@@ -14,7 +15,9 @@ spin-chain workload of Sec. 11.1 at the dimensions of the at-scale
 configuration): up to L = 18 the whole final state is stored; above, the
 entries at seeded sample rows (with the slice and half-space edges), the norm
 and the projections onto seeded complex Gaussian vectors (which involve every
-entry), so the file stays small.
+entry), so the file stays small.  With --dt-window T --dt-steps N the step
+is T / N instead of 0.02 (the benchmark runs the step selected for a state
+error of 1e-8 over T = 4: 4 / 19) and the file name carries the step.
 
 Hydrogen (radial grid Nr = 2000, dr = 0.1, l <= 63, CF8:11, m = 30, 1s start):
 the 30 steps of dt = 0.002 from t0 = 40 that the hydrogen benchmark runs
@@ -70,8 +73,10 @@ def golden_path(name: str) -> str:
     return os.path.join(HERE, name)
 
 
-def heisenberg(L: int, steps: int) -> str:
+def heisenberg(L: int, steps: int, dt: float | None = None) -> str:
     p = I.config_heisenberg(L=L, nsteps=steps)
+    if dt is not None:
+        p.dt = dt
     n = p.dim
     H0 = p.H0.to_scipy()
     H1 = p.Hk[0].to_scipy()
@@ -91,7 +96,8 @@ def heisenberg(L: int, steps: int) -> str:
         out["rows"] = rows
         out["psi_rows"] = psi[rows]
         out["proj"] = np.array([np.vdot(r, psi) for r in projection_vectors(n)])
-    path = golden_path(f"heisenberg_L{L}_{steps}steps.npz")
+    tag = "" if dt is None else f"_dt{dt:.6f}"
+    path = golden_path(f"heisenberg_L{L}_{steps}steps{tag}.npz")
     np.savez(path, **out)
     print(f"heisenberg L={L}: {steps} steps in {el:.0f} s, |psi| = {out['norm']:.15f}, "
           f"matvecs {stats['n_matvec']} -> {path}", flush=True)
@@ -117,9 +123,12 @@ def main():
     ap.add_argument("which", choices=["heisenberg", "hydrogen"])
     ap.add_argument("--L", type=int, default=18)
     ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--dt-window", type=float, default=0.0)
+    ap.add_argument("--dt-steps", type=int, default=0)
     a = ap.parse_args()
     if a.which == "heisenberg":
-        heisenberg(a.L, a.steps)
+        dt = a.dt_window / a.dt_steps if a.dt_steps > 0 else None
+        heisenberg(a.L, a.steps, dt)
     else:
         hydrogen()
 

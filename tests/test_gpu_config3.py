@@ -11,6 +11,10 @@ oracle results and closed forms.
     norm, and projections onto seeded complex Gaussian vectors (each involves
     every entry: for an error vector d, <r|d> has standard deviation
     sqrt(2) ||d||, so |<r|d>| <= 1e-9 says ||d|| is of order 1e-10 or less);
+  - L = 24, one step of the step the benchmark times (dt = 4/19, selected for
+    a state error of 1e-8 over t = 4; the small exponentials then see
+    theta = dt ||T|| about ten times larger), on the default layout, against
+    the oracle's result stored the same way;
   - L = 18, the whole 200-step run, on the default path (multi-kernel, CSR)
     and on the multi-kernel path with both shared layouts: whole final state.
 * Hydrogen on the radial grid: the benchmark's window (t0 = 40, dt = 0.002,
@@ -102,6 +106,30 @@ def test_heisenberg_L24_two_steps_vs_oracle(layout, code):
         psi = dev(p.psi0)
         print(f"[L=24 {layout or 'default'}] propagating 2 steps", flush=True)
         P.propagate(psi, 0.0, p.dt, 2, p.scheme, p.m)
+        st = P.stats()
+        out = psi.cpu().numpy()
+    del psi
+    assert st["status"] == 0 and B.PATH_NAMES[st["path"]] == "multi"
+    assert st["matvecs"] == int(g["n_matvec"])
+    rows, projs = sample_rows(n)
+    assert np.array_equal(rows, g["rows"])
+    assert rel(out[rows], g["psi_rows"]) <= PROP_TOL
+    assert abs(np.linalg.norm(out) - float(g["norm"])) <= 1e-12
+    for r, ref in zip(projs, g["proj"]):
+        assert abs(np.vdot(r, out) - ref) <= 1e-9
+
+
+def test_heisenberg_L24_bench_step_vs_oracle():
+    g = golden("heisenberg_L24_1steps_dt0.210526.npz")
+    p = heisenberg(24)
+    n = p.dim
+    dt, steps = float(g["dt"]), int(g["steps"])
+    assert dt == 4.0 / 19 and steps == 1 and int(g["m"]) == p.m
+    with B.Propagator(p.H0, p.Hk, p.drives) as P:
+        assert P.stats()["layout"] == 3
+        psi = dev(p.psi0)
+        print(f"[L=24 dt={dt}] propagating {steps} step", flush=True)
+        P.propagate(psi, 0.0, dt, steps, p.scheme, p.m)
         st = P.stats()
         out = psi.cpu().numpy()
     del psi
